@@ -1,0 +1,17 @@
+"""FP64 CPU oracle of the bilateral filter and of its N-term expanded form.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the GPU library.  See fit.py (kernel
+expansions) and bfref.c (the filters T1, T2, T3).
+"""
+from .fit import (spatial_fit, spatial_rectangles, range_fit, range_kernel_approx,
+                  haar_family, haar_coefficient, gaussian_integral, truncation_radius,
+                  first_m_containing, cosine_coefficients, select_largest, PHI)
+from .filters import (Plan, make_plan, true_bf, expanded_brute, expanded_box,
+                      correlate_rects, to_unit)
+
+__all__ = ["spatial_fit", "spatial_rectangles", "range_fit", "range_kernel_approx",
+           "haar_family", "haar_coefficient", "gaussian_integral", "truncation_radius",
+           "first_m_containing", "cosine_coefficients", "select_largest", "PHI",
+           "Plan", "make_plan", "true_bf", "expanded_brute", "expanded_box",
+           "correlate_rects", "to_unit"]

@@ -1,0 +1,275 @@
+"""FP64 reference fit of the two kernel expansions (TEST INFRASTRUCTURE ONLY).
+
+This package is the oracle that the GPU library is checked against.  Only the
+tests, the smoke check and the benchmark's CPU-baseline leg may import it; the
+library never does, and the two share no code.
+
+It computes, in double precision and straight from the paper's definitions:
+
+* the Haar expansion of the truncated spatial kernel (Sec. III-C, Eqs.
+  Haar_scaling / Haar_mother / Haar_set, Haar_decomposition and the 2-D
+  coefficients of Eq. Haar_2D_coefficients), its best N-term selection
+  (Sec. III-A, Eq. N_term; Sec. IV-B, Eq. Haar_N_terms) and the box form of
+  each selected 2-D Haar function (App. A, Table VI);
+* the truncated-cosine expansion of the range kernel (Sec. III-B, Eq.
+  1D_truncated_cos; Sec. IV-C, Eq. trigonometric_N_terms) with its best N-term
+  selection out of the first 20N coefficients (App. B, Table VII).
+
+Readings where the paper is silent or ambiguous (each is listed in the design doc):
+
+* truncation: T_s = r + 1/2 for a window radius r, so that no integer offset
+  falls on +-T_s; T = max(T_r, span) for the range series, so the range box of
+  Eq. 1D_N_terms is identically one on every intensity difference;
+* N_s counts Haar *level groups* (lx, ly): all functions phi or psi_{j,.} of
+  one level in x times all of one level in y; groups are ranked by L2 energy;
+* range coefficients are ranked by raw |a_k| (this reproduces Table VII),
+  a_0 included in the candidate pool;
+* Haar functions are point-sampled at integer offsets on half-open intervals
+  [lo, hi); coefficients are the continuous integrals;
+* ties: energies rounded to 12 significant digits, then smaller lx+ly, then
+  smaller lx (phi counts as -1); |a_k| rounded to 1e-13 * max|a|, then smaller k.
+"""
+import math
+
+import numpy as np
+
+PHI = -1  # level index used for the scaling function phi
+
+
+# ----------------------------------------------------------------------------
+# Gaussian kernels (Sec. I: G_sigma(x) = exp(-x^2 / 2 sigma^2))
+# ----------------------------------------------------------------------------
+def gaussian(x, sigma):
+    x = np.asarray(x, dtype=np.float64)
+    return np.exp(-x * x / (2.0 * sigma * sigma))
+
+
+def gaussian_integral(a, b, sigma):
+    """Integral of exp(-t^2 / 2 sigma^2) over [a, b] (closed form with erf)."""
+    s = sigma * math.sqrt(2.0)
+    return sigma * math.sqrt(math.pi / 2.0) * (math.erf(b / s) - math.erf(a / s))
+
+
+def truncation_radius(sigma, eps=0.01):
+    """T = K^{-1}(eps) for a Gaussian K (Sec. IV-A): sigma * sqrt(2 ln(1/eps))."""
+    return sigma * math.sqrt(2.0 * math.log(1.0 / eps))
+
+
+# ----------------------------------------------------------------------------
+# 1-D Haar functions on [-T, T) (Sec. III-C, Eqs. Haar_scaling, Haar_mother,
+# Haar_set; support intervals as in App. A)
+# ----------------------------------------------------------------------------
+class Haar1D:
+    """One 1-D Haar function: +1 on [lo, mid), -1 on [mid, hi); phi is +1 on [lo, hi)."""
+
+    __slots__ = ("level", "k", "lo", "mid", "hi")
+
+    def __init__(self, level, k, lo, mid, hi):
+        self.level, self.k, self.lo, self.mid, self.hi = level, k, lo, mid, hi
+
+    def intervals(self):
+        """[(lo, hi, sign)] pieces on which the function is constant and nonzero."""
+        if self.level == PHI:
+            return [(self.lo, self.hi, 1.0)]
+        return [(self.lo, self.mid, 1.0), (self.mid, self.hi, -1.0)]
+
+    def sample(self, d):
+        """Point samples at (integer) offsets d, half-open intervals."""
+        d = np.asarray(d, dtype=np.float64)
+        out = np.zeros(d.shape)
+        for lo, hi, s in self.intervals():
+            out += s * ((d >= lo) & (d < hi))
+        return out
+
+    def norm2(self):
+        """Squared L2 norm: support width (phi: 2T; psi_{j,k}: 2T / 2^j)."""
+        return self.hi - self.lo
+
+    def __repr__(self):
+        name = "phi" if self.level == PHI else "psi_%d,%d" % (self.level, self.k)
+        return "%s[%g,%s,%g)" % (name, self.lo, "" if self.mid is None else "%g" % self.mid, self.hi)
+
+
+def haar_family(T, J):
+    """phi, psi_{0,0} and psi_{j,k}, j = 1..J, k in {+-1, ..., +-2^{j-1}}.
+
+    psi_{j,k}(x) = psi_{0,0}(2^j x - Z_k) with Z_k = sign(k)(2|k|-1) T, so psi_{j,k}
+    is +1 on [2^-j (Z_k - T), 2^-j Z_k) and -1 on [2^-j Z_k, 2^-j (Z_k + T))."""
+    fam = [Haar1D(PHI, 0, -T, None, T), Haar1D(0, 0, -T, 0.0, T)]
+    for j in range(1, J + 1):
+        ks = list(range(-2 ** (j - 1), 0)) + list(range(1, 2 ** (j - 1) + 1))
+        for k in ks:
+            Z = math.copysign(2 * abs(k) - 1, k) * T
+            s = 2.0 ** (-j)
+            fam.append(Haar1D(j, k, s * (Z - T), s * Z, s * (Z + T)))
+    return fam
+
+
+def haar_coefficient(f, sigma, T):
+    """Coefficient of Eq. Haar_decomposition for the Gaussian g = G_sigma:
+    c_0 = (1/2T) int g phi, c_{jk} = (2^j / 2T) int g psi_{j,k}."""
+    if f.level == PHI:
+        return gaussian_integral(f.lo, f.hi, sigma) / (2.0 * T)
+    return (2.0 ** f.level) * (gaussian_integral(f.lo, f.mid, sigma)
+                               - gaussian_integral(f.mid, f.hi, sigma)) / (2.0 * T)
+
+
+def max_level(T):
+    """Finest level J such that a half-cell T / 2^J is at least one pixel wide."""
+    return int(math.floor(math.log2(T)))
+
+
+# ----------------------------------------------------------------------------
+# Spatial fit: best N-term over 2-D Haar level groups (Eq. Haar_N_terms)
+# ----------------------------------------------------------------------------
+class SpatialFit:
+    pass
+
+
+def _round_sig(x, digits=12):
+    if x == 0.0:
+        return 0.0
+    return float("%.*e" % (digits - 1, x))
+
+
+def spatial_fit(sigma_s, radius, n_spatial):
+    """Best N_s-group Haar approximation of the Gaussian K_s(||x||) = g(x) g(y) on
+    [-T_s, T_s)^2, T_s = radius + 1/2.  The 2-D coefficients are products of 1-D
+    ones (Eq. Haar_2D_coefficients for a separable kernel)."""
+    T = radius + 0.5
+    J = max_level(T)
+    fam = haar_family(T, J)
+    coef = [haar_coefficient(f, sigma_s, T) for f in fam]
+    levels = [PHI] + list(range(0, J + 1))
+    # per-level 1-D energy sum c_b^2 ||b||^2; a group's energy is the product
+    e1 = {l: 0.0 for l in levels}
+    for f, c in zip(fam, coef):
+        e1[f.level] += c * c * f.norm2()
+    groups = []
+    for lx in levels:
+        for ly in levels:
+            groups.append((_round_sig(e1[lx] * e1[ly]), lx, ly))
+    n_groups = len(groups)
+    if not (1 <= n_spatial <= n_groups):
+        raise ValueError("n_spatial must be in [1, %d]" % n_groups)
+    groups.sort(key=lambda g: (-g[0], g[1] + g[2], g[1]))
+    sel = [(lx, ly) for _, lx, ly in groups[:n_spatial]]
+
+    d = np.arange(-radius, radius + 1)
+    u = {}
+    for l in levels:
+        u[l] = sum(c * f.sample(d) for f, c in zip(fam, coef) if f.level == l)
+    K = np.zeros((2 * radius + 1, 2 * radius + 1))  # K[dy + r, dx + r]
+    for lx, ly in sel:
+        K += np.outer(u[ly], u[lx])
+
+    out = SpatialFit()
+    out.sigma, out.radius, out.T, out.J = sigma_s, radius, T, J
+    out.family, out.coef = fam, coef
+    out.level_energy = e1
+    out.groups_ranked = groups
+    out.selected = sel
+    out.u = u
+    out.K = K
+    return out
+
+
+def spatial_rectangles(fit):
+    """The selected expansion written as weighted rectangles in offset space
+    (App. A: phi*psi = B1 - B2, psi*psi = B1 - B2 + B3 - B4; Eq. 2D_box_N_terms).
+
+    Returns an array of rows (ey_lo, ey_hi, ex_lo, ex_hi, w): K~_s(e) is the sum of
+    w over rectangles with ey_lo <= e_y <= ey_hi and ex_lo <= e_x <= ex_hi
+    (integer offsets, inclusive; the half-open real interval [lo, hi) holds the
+    integers ceil(lo) .. ceil(hi) - 1)."""
+    rows = []
+    by_level = {}
+    for f, c in zip(fit.family, fit.coef):
+        by_level.setdefault(f.level, []).append((f, c))
+    for lx, ly in fit.selected:
+        for fx, cx in by_level[lx]:
+            for fy, cy in by_level[ly]:
+                w = cx * cy
+                if w == 0.0:
+                    continue
+                for xlo, xhi, sx in fx.intervals():
+                    for ylo, yhi, sy in fy.intervals():
+                        rows.append((math.ceil(ylo), math.ceil(yhi) - 1,
+                                     math.ceil(xlo), math.ceil(xhi) - 1, w * sx * sy))
+    return np.array(rows, dtype=np.float64).reshape(-1, 5)
+
+
+# ----------------------------------------------------------------------------
+# Range fit: truncated cosine series (Eq. 1D_truncated_cos, Eq.
+# trigonometric_N_terms) with the candidate pool of App. B
+# ----------------------------------------------------------------------------
+class RangeFit:
+    pass
+
+
+def _gauss_legendre_panels(a, b, panels, nodes=16):
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    edges = np.linspace(a, b, panels + 1)
+    lo, hi = edges[:-1, None], edges[1:, None]
+    t = (0.5 * (hi - lo) * x[None, :] + 0.5 * (hi + lo)).ravel()
+    wt = (0.5 * (hi - lo) * w[None, :]).ravel()
+    return t, wt
+
+
+def cosine_coefficients(kernel, T, M):
+    """a_0 = (1/2T) int_{-T}^{T} f, a_j = (1/T) int_{-T}^{T} f(x) cos(pi j x / T) dx,
+    j < M, by composite 16-point Gauss-Legendre quadrature (4 panels per period
+    of the highest frequency, at least 256)."""
+    panels = max(256, 4 * M)
+    t, wt = _gauss_legendre_panels(-T, T, panels)
+    fw = kernel(t) * wt
+    a = np.empty(M)
+    for j0 in range(0, M, 64):
+        js = np.arange(j0, min(M, j0 + 64))
+        a[js] = np.cos(np.pi * js[:, None] * t[None, :] / T) @ fw / T
+    a[0] *= 0.5
+    return a
+
+
+def select_largest(a, n):
+    """Indices of the n largest |a_k| (ties broken toward smaller k after rounding
+    |a_k| to an absolute grid of 1e-13 * max|a|), returned in increasing k."""
+    mag = np.abs(a)
+    q = np.rint(mag / (1e-13 * mag.max())) if mag.max() > 0 else mag
+    order = sorted(range(len(a)), key=lambda k: (-q[k], k))
+    return sorted(order[:n])
+
+
+def range_fit(sigma_r, n_range, eps=0.01, span=1.0, kernel=None):
+    """Best N_r-term cosine approximation of K_r on [-T, T], T = max(T_r, span).
+
+    The approximated function on [-T, T] is K_r itself (untruncated there); with
+    span = 0 this is the paper's own regime T = T_r.  Returns the selected
+    (k, a_k, omega_k = pi k / T)."""
+    if not (1 <= n_range <= 64):
+        raise ValueError("n_range must be in [1, 64]")
+    if kernel is None:
+        kernel = lambda t: gaussian(t, sigma_r)
+    T_r = truncation_radius(sigma_r, eps)
+    T = max(T_r, span)
+    M = max(20 * n_range, 2)
+    a = cosine_coefficients(kernel, T, M)
+    ks = select_largest(a, n_range)
+    out = RangeFit()
+    out.sigma, out.T_r, out.T, out.M = sigma_r, T_r, T, M
+    out.a_all = a
+    out.k = np.array(ks, dtype=np.int64)
+    out.a = a[ks]
+    out.omega = np.pi * out.k / T
+    return out
+
+
+def range_kernel_approx(fit, t):
+    t = np.asarray(t, dtype=np.float64)
+    return sum(a * np.cos(w * t) for a, w in zip(fit.a, fit.omega))
+
+
+def first_m_containing(a, n):
+    """Table VII's M(N): the smallest M such that the first M coefficients hold the
+    N largest ones (raw-magnitude ranking)."""
+    return max(select_largest(a, n)) + 1

@@ -1,0 +1,410 @@
+"""Pins of the FP64 oracle to facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's formulas: each compares it with a printed
+value of the paper (Table VII, the Sec. V-A worked example), with an identity
+the paper states (App. A box representation, Parseval for a best N-term
+approximation, the cosine shift identity), with an independent numerical
+route (adaptive quadrature, scipy's complex error function, scipy's 2-D
+correlation, a pure-Python double loop) or with an invariant of Eq. BF
+(constant images, sigma_r -> infinity, convergence as N grows).  The last
+section plants mistakes in the oracle and checks that some pin fails.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, signal, special
+
+import oracle
+import synth
+from oracle import fit as F
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append([float(v) for v in line.split()])
+    return rows
+
+
+# ---------------------------------------------------------------------------
+# Range expansion (Sec. III-B, Eq. 1D_truncated_cos; App. B)
+# ---------------------------------------------------------------------------
+def test_table7_range_row():
+    """App. B, Table VII: G_40 on [-T_r, T_r] (eps = 0.01) gives M(N) = 2,2,3,...,8
+    under raw-magnitude ranking with a_0 in the pool."""
+    rows = _golden("table7_range_row.txt")
+    fit = F.range_fit(40.0, 8, eps=0.01, span=0.0)
+    assert abs(fit.T - 40.0 * math.sqrt(2 * math.log(100.0))) < 1e-12
+    for n, m in rows:
+        assert F.first_m_containing(fit.a_all, int(n)) == int(m)
+
+
+def _cos_coef_closed_form(sigma, T, k):
+    """a_k of a Gaussian on [-T, T] through the complex error function:
+    int_{-T}^{T} e^{-t^2/2s^2} cos(w t) dt = Re{ e^{-w^2 s^2/2} s sqrt(pi/2)
+    [erf((T - i w s^2)/(s sqrt2)) - erf((-T - i w s^2)/(s sqrt2))] }."""
+    w = math.pi * k / T
+    z1 = (T - 1j * w * sigma * sigma) / (sigma * math.sqrt(2))
+    z0 = (-T - 1j * w * sigma * sigma) / (sigma * math.sqrt(2))
+    with np.errstate(all="ignore"):  # exp underflow times erf overflow at large k
+        val = (math.exp(-0.5 * (w * sigma) ** 2) * sigma * math.sqrt(math.pi / 2)
+               * (special.erf(z1) - special.erf(z0))).real
+    return val / (2 * T) if k == 0 else val / T
+
+
+@pytest.mark.parametrize("sigma,T", [(0.3, 1.0), (0.2, 1.0), (1.0, 3.0), (40.0, 121.39417)])
+def test_cosine_coefficients_closed_form(sigma, T):
+    a = F.cosine_coefficients(lambda t: F.gaussian(t, sigma), T, 40)
+    checked = 0
+    for k in range(0, 40):
+        ref = _cos_coef_closed_form(sigma, T, k)
+        if not np.isfinite(ref):
+            continue
+        checked += 1
+        assert abs(a[k] - ref) < 1e-13, (k, a[k], ref)
+    assert checked >= 10
+
+
+@pytest.mark.parametrize("sigma", [0.05, 0.1])
+def test_cosine_coefficients_wide_interval(sigma):
+    """For T >> sigma the interval barely truncates the Gaussian, so
+    a_k -> sigma sqrt(2 pi) / T exp(-(pi k sigma / T)^2 / 2) (its Fourier transform)."""
+    T = 1.0
+    a = F.cosine_coefficients(lambda t: F.gaussian(t, sigma), T, 200)
+    k = np.arange(200)
+    ref = sigma * math.sqrt(2 * math.pi) / T * np.exp(-0.5 * (math.pi * k * sigma / T) ** 2)
+    ref[0] *= 0.5
+    assert np.abs(a - ref).max() < 1e-13
+
+
+def test_cosine_parseval_and_convergence():
+    """||f||^2 = 2T a_0^2 + T sum a_k^2 on [-T, T]; the best-N error is ||f||^2 minus
+    the kept energy (Sec. III-A), so it never grows with N."""
+    sigma, T = 0.1, 1.0
+    a = F.cosine_coefficients(lambda t: F.gaussian(t, sigma), T, 400)
+    norm2 = integrate.quad(lambda t: math.exp(-t * t / sigma ** 2), -T, T, epsabs=1e-14)[0]
+    energy = 2 * T * a[0] ** 2 + T * np.sum(a[1:] ** 2)
+    assert abs(energy - norm2) < 1e-12
+    t = np.linspace(-T, T, 4001)
+    errs = []
+    for n in (2, 4, 8, 16, 24):
+        fit = F.range_fit(sigma, n)
+        errs.append(np.sqrt(np.mean((F.range_kernel_approx(fit, t) - F.gaussian(t, sigma)) ** 2)))
+    assert all(e1 >= e2 for e1, e2 in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-6
+
+
+def test_range_selection_candidates_and_ties():
+    """a_0 is a candidate (Table VII needs it); at sigma_r = 0.1, T = 1 the kept
+    terms are k = 0..N-1; coefficients beyond the double-precision noise floor tie
+    and the tie goes to smaller k."""
+    for n in (8, 16, 32):
+        fit = F.range_fit(0.1, n)
+        assert fit.k.tolist() == list(range(n))
+    assert F.select_largest(np.array([1.0, 0.5, 0.5, 1e-20, 0.0]), 3) == [0, 1, 2]
+    assert F.select_largest(np.array([0.2, 1.0, 0.3]), 1) == [1]
+
+
+# ---------------------------------------------------------------------------
+# Spatial expansion (Sec. III-C, Eqs. Haar_scaling .. Haar_2D_coefficients)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sigma,T", [(1.0, 3.0), (3.0, 9.5), (16.0, 48.5)])
+def test_haar_coefficients_by_quadrature(sigma, T):
+    """c_0 = (1/2T) int g phi and c_jk = (2^j/2T) int g psi_jk against adaptive
+    quadrature of the sampled function definitions."""
+    fam = F.haar_family(T, F.max_level(T))
+    for f in fam:
+        c = F.haar_coefficient(f, sigma, T)
+        val = 0.0
+        for lo, hi, s in f.intervals():
+            val += s * integrate.quad(lambda x: math.exp(-x * x / (2 * sigma * sigma)), lo, hi,
+                                      epsabs=1e-15, epsrel=1e-13)[0]
+        scale = 1.0 if f.level == F.PHI else 2.0 ** f.level
+        assert abs(c - scale * val / (2 * T)) < 1e-13, f
+
+
+def test_haar_family_shapes():
+    """psi_{j,k}(x) = psi_00(2^j x - Z_k), Z_k = sign(k)(2|k|-1)T: check the supports
+    against the paper's worked list for T = 2 (Fig. Haar_1D) and the orthogonality
+    of the family on a fine grid."""
+    T = 2.0
+    fam = {(f.level, f.k): f for f in F.haar_family(T, 2)}
+    x = np.linspace(-T, T, 64001)[:-1] + T / 64000
+    psi00 = lambda u: np.where((u >= -T) & (u < 0), 1.0, 0.0) - np.where((u >= 0) & (u < T), 1.0, 0.0)
+    shifts = {(1, -1): (2, -T), (1, 1): (2, T), (2, -1): (4, -T), (2, 1): (4, T),
+              (2, -2): (4, -3 * T), (2, 2): (4, 3 * T)}
+    for (j, k), (mul, z) in shifts.items():
+        assert np.array_equal(fam[(j, k)].sample(x), psi00(mul * x - z)), (j, k)
+    B = np.array([f.sample(x) for f in fam.values()])
+    G = B @ B.T * (2 * T / len(x))
+    assert np.allclose(G - np.diag(np.diag(G)), 0.0, atol=1e-9)
+    assert np.allclose(np.diag(G), [f.norm2() for f in fam.values()], atol=1e-9)
+
+
+@pytest.mark.parametrize("sigma,T", [(1.0, 3.0), (5.0, 15.5)])
+def test_haar_expansion_reproduces_cell_averages(sigma, T):
+    """The Haar expansion through level J is the orthogonal projection onto
+    functions constant on the 2^{J+1} cells of width T/2^J: its value on a cell
+    is the cell average of g (independent quadrature)."""
+    J = 3
+    fam = F.haar_family(T, J)
+    coef = [F.haar_coefficient(f, sigma, T) for f in fam]
+    ncell = 2 ** (J + 1)
+    w = 2 * T / ncell
+    for i in range(ncell):
+        lo = -T + i * w
+        mid = lo + 0.5 * w
+        approx = sum(c * f.sample(np.array([mid]))[0] for f, c in zip(fam, coef))
+        avg = integrate.quad(lambda x: math.exp(-x * x / (2 * sigma * sigma)), lo, lo + w,
+                             epsabs=1e-15)[0] / w
+        assert abs(approx - avg) < 1e-12, (i, approx, avg)
+
+
+def test_haar_parseval_levels():
+    """Sum of level energies -> ||g||^2 on [-T, T] as J grows (Parseval), and the
+    survey-independent value of ||exp(-x^2/2)||^2 on [-3, 3] = sqrt(pi) erf(3)."""
+    sigma, T = 1.0, 3.0
+    norm2 = math.sqrt(math.pi) * math.erf(3.0)
+    for J, tol in ((3, 0.02), (10, 1e-6)):
+        fam = F.haar_family(T, J)
+        e = sum(F.haar_coefficient(f, sigma, T) ** 2 * f.norm2() for f in fam)
+        assert e <= norm2 + 1e-12
+        assert norm2 - e < tol
+
+
+def test_box_representation_app_a():
+    """App. A: phi psi_{j,k} = B1 - B2 and psi psi = B1 - B2 + B3 - B4 with
+    A1 = [2^-j (Z_k - T), 2^-j Z_k), A2 = [2^-j Z_k, 2^-j (Z_k + T)), pointwise on
+    the integer grid; and the rectangle list reproduces the sampled kernel."""
+    r = 12
+    T = r + 0.5
+    d = np.arange(-r, r + 1)
+    for f in F.haar_family(T, F.max_level(T)):
+        if f.level == F.PHI:
+            continue
+        Z = math.copysign(2 * abs(f.k) - 1, f.k) * T if f.level > 0 else 0.0
+        s = 2.0 ** (-f.level)
+        a1 = (d >= s * (Z - T)) & (d < s * Z)
+        a2 = (d >= s * Z) & (d < s * (Z + T))
+        assert np.array_equal(f.sample(d), a1.astype(float) - a2.astype(float))
+    for ss, rr, ns in ((3.0, 9, 4), (8.0, 24, 6), (4.0, 12, 9)):
+        fit = F.spatial_fit(ss, rr, ns)
+        K = np.zeros_like(fit.K)
+        for ey0, ey1, ex0, ex1, w in F.spatial_rectangles(fit):
+            K[int(ey0) + rr:int(ey1) + rr + 1, int(ex0) + rr:int(ex1) + rr + 1] += w
+        assert np.abs(K - fit.K).max() < 1e-15
+
+
+def test_worked_example_three_boxes():
+    """Sec. V-A: f1 + f2 + f3 (groups phi phi, phi psi_1, psi_1 phi: five Haar
+    functions) equals three centred boxes 2T x 2T, 2T x T, T x 2T."""
+    (n_haar, n_box, *dims), = _golden("worked_example_boxes.txt")
+    r = 10
+    T = r + 0.5
+    fit = F.spatial_fit(3.0, r, 3)
+    assert fit.selected == [(F.PHI, F.PHI), (F.PHI, 1), (1, F.PHI)]
+    nfun = sum(1 for f in fit.family if f.level in (F.PHI, 1))
+    assert nfun * 2 - 1 == n_haar  # phi shared by the three groups: 1 + 2 + 2
+    d = np.arange(-r, r + 1)
+    boxes = []
+    for i in range(int(n_box)):
+        h, w = dims[2 * i] * T, dims[2 * i + 1] * T
+        by = (d >= -h / 2) & (d < h / 2)
+        bx = (d >= -w / 2) & (d < w / 2)
+        boxes.append(np.outer(by, bx).astype(float).ravel())
+    A = np.array(boxes).T
+    coef, *_ = np.linalg.lstsq(A, fit.K.ravel(), rcond=None)
+    assert np.abs(A @ coef - fit.K.ravel()).max() < 1e-14
+
+
+def test_spatial_groups_symmetric_and_energy_ordered():
+    """Selected groups of the five workloads: symmetric kernels (Eq. BF asks for
+    symmetric K_s), kernel L2 error non-increasing in N_s."""
+    for ss, r in ((3.0, 9), (8.0, 24), (16.0, 48)):
+        d = np.arange(-r, r + 1)
+        G = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2 * ss * ss))
+        prev = np.inf
+        for ns in range(1, 10):
+            K = F.spatial_fit(ss, r, ns).K
+            if ns in (4, 6, 8):
+                assert np.allclose(K, K.T, atol=1e-15) and np.allclose(K, K[::-1], atol=1e-15)
+            err = np.sqrt(np.sum((K - G) ** 2))
+            assert err <= prev + 1e-9
+            prev = err
+
+
+# ---------------------------------------------------------------------------
+# The filters T1, T2, T3
+# ---------------------------------------------------------------------------
+def _py_true_bf(I, ss, r, sr):
+    H, W = I.shape
+    out = np.zeros_like(I)
+    for py in range(H):
+        for px in range(W):
+            num = den = 0.0
+            for qy in range(max(0, py - r), min(H, py + r + 1)):
+                for qx in range(max(0, px - r), min(W, px + r + 1)):
+                    w = math.exp(-((py - qy) ** 2 + (px - qx) ** 2) / (2 * ss * ss)) * \
+                        math.exp(-(I[py, px] - I[qy, qx]) ** 2 / (2 * sr * sr))
+                    num += w * I[qy, qx]
+                    den += w
+            out[py, px] = num / den
+    return out
+
+
+def _py_expanded(I, plan):
+    """Eq. BF with both expansions, written as a plain quadruple loop; the spatial
+    weight of q for output p is K~_s(p - q)."""
+    H, W = I.shape
+    r = plan.radius
+    out = np.zeros_like(I)
+    for py in range(H):
+        for px in range(W):
+            num = den = 0.0
+            for qy in range(max(0, py - r), min(H, py + r + 1)):
+                for qx in range(max(0, px - r), min(W, px + r + 1)):
+                    ws = plan.Ks[py - qy + r, px - qx + r]
+                    kr = sum(a * math.cos(w * (I[py, px] - I[qy, qx]))
+                             for a, w in zip(plan.a, plan.omega))
+                    num += ws * kr * I[qy, qx]
+                    den += ws * kr
+            out[py, px] = num / den
+    return out
+
+
+def test_true_bf_brute_force_tiny():
+    I = synth.gen_image(7, 9, 2, 0.05, 11).astype(np.float64)
+    ref = _py_true_bf(I, 1.5, 2, 0.2)
+    assert np.abs(oracle.true_bf(I, 1.5, 2, 0.2) - ref).max() < 1e-14
+
+
+def test_expanded_brute_force_tiny():
+    I = synth.gen_image(8, 7, 2, 0.05, 12).astype(np.float64)
+    plan = oracle.make_plan(1.5, 3, 4, 0.2, 8)
+    ref = _py_expanded(I, plan)
+    assert np.abs(oracle.expanded_brute(I, plan) - ref).max() < 1e-13
+    assert np.abs(oracle.expanded_box(I, plan) - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("H,W,ss,r,ns,sr,nr", [
+    (40, 56, 2.0, 6, 4, 0.1, 16), (64, 64, 3.0, 9, 4, 0.1, 8), (33, 47, 4.0, 12, 6, 0.2, 8),
+    (5, 60, 3.0, 9, 8, 0.05, 32), (60, 3, 2.0, 6, 5, 0.3, 8), (1, 1, 3.0, 9, 4, 0.1, 8),
+    (9, 11, 8.0, 24, 6, 0.1, 16)])
+def test_shift_identity_T2_equals_T3(H, W, ss, r, ns, sr, nr):
+    """Eq. 1D_N_terms: the cosine shift identity plus box sums reach the expanded
+    form exactly (up to rounding): T2 == T3 within 1e-12, incl. images smaller
+    than the window and the 1 x 1 image."""
+    I = synth.gen_image(H, W, 3, 0.03, H * 131 + W)
+    plan = oracle.make_plan(ss, r, ns, sr, nr)
+    o2, n2, d2 = oracle.expanded_brute(I, plan, return_parts=True)
+    o3, n3, d3 = oracle.expanded_box(I, plan, return_parts=True)
+    assert np.abs(o2 - o3).max() < 1e-12
+    assert np.abs(n2 - n3).max() < 1e-10 * max(1.0, np.abs(n2).max())
+    if H == W == 1:
+        assert abs(o3[0, 0] - float(I[0, 0])) < 1e-12
+
+
+def test_constant_image_is_unchanged():
+    """Eq. BF is a weighted average: a constant image maps to itself (T1, T2, T3)."""
+    Z = np.full((23, 31), 0.37)
+    plan = oracle.make_plan(3.0, 9, 4, 0.1, 8)
+    for out in (oracle.true_bf(Z, 3.0, 9, 0.1), oracle.expanded_brute(Z, plan),
+                oracle.expanded_box(Z, plan)):
+        assert np.abs(out - 0.37).max() < 1e-14
+
+
+def test_sigma_r_infinity_is_spatial_filter():
+    """sigma_r -> infinity: the range expansion is constant on every intensity
+    difference in [-1, 1] and the filter is the normalised spatial filter
+    (K~_s * I) / (K~_s * 1) (scipy)."""
+    I = synth.gen_image(48, 40, 4, 0.02, 5).astype(np.float64)
+    plan = oracle.make_plan(3.0, 9, 4, 1e6, 4)
+    kr = F.range_kernel_approx(plan.range, np.linspace(-1.0, 1.0, 101))
+    assert np.ptp(kr) < 1e-9 * abs(kr[50]) and abs(kr[50] - 1.0) < 1e-3
+    K = plan.Ks[::-1, ::-1]  # correlate2d(x, K') = sum_q K'(q - p) x(q); K~_s(p - q) needs the flip
+    num = signal.correlate2d(I, K, mode="same", boundary="fill")
+    den = signal.correlate2d(np.ones_like(I), K, mode="same", boundary="fill")
+    assert np.abs(oracle.expanded_box(I, plan) - num / den).max() < 1e-12
+
+
+def test_correlation_orientation_asymmetric_kernel():
+    """corr(p) = sum_q K(p - q) g(q) with an asymmetric rectangle kernel against
+    scipy's 2-D convolution (which is exactly that sum)."""
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((21, 17))
+    rects = np.array([[-3, 1, 0, 4, 0.7], [2, 3, -2, -1, -1.3], [0, 0, 0, 0, 0.25]])
+    K = np.zeros((7, 9))  # offsets ey in [-3, 3], ex in [-4, 4]
+    for ey0, ey1, ex0, ex1, w in rects:
+        K[int(ey0) + 3:int(ey1) + 4, int(ex0) + 4:int(ex1) + 5] += w
+    ref = signal.convolve2d(g, K, mode="same", boundary="fill")
+    assert np.abs(oracle.correlate_rects(g, rects) - ref).max() < 1e-12
+
+
+def test_expansion_converges_to_true_bf():
+    """Error of the expanded filter against the true bilateral filter falls as the
+    number of range terms grows (reported by the benchmark, asserted loosely)."""
+    I = synth.gen_image(64, 64, 5, 0.02, 21)
+    ref = oracle.true_bf(I, 3.0, 9, 0.1)
+    errs = []
+    for nr in (4, 8, 12, 16):
+        plan = oracle.make_plan(3.0, 9, 6, 0.1, nr)
+        errs.append(np.abs(oracle.expanded_box(I, plan) - ref).mean())
+    assert errs[0] > errs[1] > errs[-1]
+
+
+def test_uint8_input_is_scaled():
+    Iu = synth.gen_image_u8(20, 24, 3, 0.02, 4)
+    plan = oracle.make_plan(2.0, 6, 4, 0.1, 8)
+    a = oracle.expanded_box(Iu, plan)
+    b = oracle.expanded_box(Iu.astype(np.float64) / 255.0, plan)
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# Planted mistakes: each must make at least one pin above fail
+# ---------------------------------------------------------------------------
+def test_planted_mistakes_are_caught(monkeypatch):
+    # (1) a_0 without its 1/2 factor: Table VII changes
+    orig = F.cosine_coefficients
+
+    def no_half(kernel, T, M):
+        a = orig(kernel, T, M)
+        a[0] *= 2.0
+        return a
+    monkeypatch.setattr(F, "cosine_coefficients", no_half)
+    fit = F.range_fit(40.0, 8, eps=0.01, span=0.0)
+    assert [F.first_m_containing(fit.a_all, n) for n in range(1, 9)] != [2, 2, 3, 4, 5, 6, 7, 8]
+    monkeypatch.undo()
+
+    # (2) psi coefficient without 2^j: cell averages no longer reproduced
+    fam = F.haar_family(3.0, 3)
+    bad = [F.gaussian_integral(f.lo, f.hi, 1.0) / 6.0 if f.level == F.PHI else
+           (F.gaussian_integral(f.lo, f.mid, 1.0) - F.gaussian_integral(f.mid, f.hi, 1.0)) / 6.0
+           for f in fam]
+    mid = np.array([-3.0 + 0.75 * 0.5])
+    approx = sum(c * f.sample(mid)[0] for f, c in zip(fam, bad))
+    avg = integrate.quad(lambda x: math.exp(-x * x / 2), -3.0, -2.25)[0] / 0.75
+    assert abs(approx - avg) > 1e-3
+
+    # (3) a dropped sine term in the shift identity: T2 != T3
+    I = synth.gen_image(20, 20, 3, 0.03, 8)
+    plan = oracle.make_plan(2.0, 6, 4, 0.1, 8)
+    t2 = oracle.expanded_brute(I, plan)
+    cos_only = np.zeros_like(t2)
+    num = den = 0.0
+    Iu = I.astype(np.float64)
+    num = np.zeros_like(Iu)
+    den = np.zeros_like(Iu)
+    for a, w in zip(plan.a, plan.omega):
+        c = np.cos(w * Iu)
+        num += a * c * oracle.correlate_rects(c * Iu, plan.rects)
+        den += a * c * oracle.correlate_rects(c, plan.rects)
+    cos_only = num / den
+    assert np.abs(cos_only - t2).max() > 1e-3
