@@ -1,0 +1,183 @@
+/*
+ * bf.h - C ABI of the MI355X (gfx950) N-term bilateral filter library.
+ *
+ * The filter is Eq. (BF) of Dai, Yuan, Zhang, "Speeding up the Bilateral
+ * Filter: A Joint Acceleration Way" (IEEE TIP; arXiv 1803.00004):
+ *
+ *   out(p) = sum_q K_s(p - q) K_r(I(p) - I(q)) I(q) / sum_q K_s(p - q) K_r(I(p) - I(q))
+ *
+ * over the in-image pixels q of the (2r+1)^2 window, with K_s replaced by its
+ * best N_s-term Haar expansion (Sec. IV-B, Eq. Haar_N_terms, box form of
+ * App. A) and K_r by its best N_r-term truncated cosine expansion (Sec. IV-C,
+ * Eq. trigonometric_N_terms).  The cosine shift identity (Eq. 1D_N_terms)
+ * turns each range term into four linear filters of modulated images, each
+ * evaluated as a sum of 2-D box sums read from summed-area tables (Sec.
+ * III-D, Eqs. sum_sat_2D .. sum_sat_sum_region_2D).
+ *
+ * Conventions (all functions):
+ *  - Images are row-major and contiguous (pitch = W elements), H x W, with
+ *    1 <= H, W <= 32768.  Pointers named I/out/ws are DEVICE pointers.
+ *  - Intensities are float32 in [0, span] (default span 1) or uint8 (read as
+ *    byte / 255).  Values outside [0, span] or NaN give an unspecified (but
+ *    memory-safe) result.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *    Filtering calls only enqueue work and never synchronise the host; a
+ *    device fault shows up as BF_ERR_DEVICE from the launch check or at the
+ *    caller's next synchronisation.
+ *  - Every function returns a bf_status_t; on an error nothing is enqueued.
+ *  - Plans are immutable after creation and may be shared by threads, except
+ *    that bf_filter (no workspace argument) grows a workspace owned by the
+ *    plan and is therefore not safe to call concurrently on one plan;
+ *    concurrent callers use bf_filter_ws with their own workspaces.
+ */
+#ifndef BF_H
+#define BF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bf_plan_s *bf_plan_t;
+
+typedef enum {
+  BF_OK = 0,
+  BF_ERR_INVALID_ARG = 1,   /* bad pointer, size, parameter, or workspace too small */
+  BF_ERR_OUT_OF_MEMORY = 2, /* a device or host allocation failed */
+  BF_ERR_DEVICE = 3,        /* a HIP call or kernel launch failed */
+  BF_ERR_UNSUPPORTED = 4    /* valid request this build does not implement */
+} bf_status_t;
+
+/* Kernel shapes.  Eq. BF asks for symmetric kernels decreasing on R+; the
+ * Gaussian G_sigma(x) = exp(-x^2 / 2 sigma^2) (Sec. I) is the one implemented. */
+typedef enum { BF_KERNEL_GAUSSIAN = 0 } bf_kernel_t;
+
+/* Expansion sizes: n_range cosine terms (1..64) of K_r, n_spatial Haar level
+ * groups (1..(J+2)^2, J = floor(log2(radius + 1/2))) of K_s.  A level group is
+ * every 2-D Haar function phi/psi_{j,.}(x) times phi/psi_{j',.}(y) of one pair
+ * of levels; groups are kept in decreasing L2 energy (best N-term, Sec. III-A). */
+typedef struct {
+  int n_range;
+  int n_spatial;
+} bf_terms_t;
+
+typedef enum { BF_IN_F32 = 0, BF_IN_U8 = 1 } bf_dtype_t;
+
+/* PLAIN: int32 summed-area tables (exact), FP64 tap sums; max-abs error
+ * against the FP64 expanded form about 1e-6.  REDUCED: reserved for the
+ * reduced-precision path (BF_ERR_UNSUPPORTED when not built). */
+typedef enum { BF_PREC_PLAIN = 0, BF_PREC_REDUCED = 1 } bf_precision_t;
+
+#define BF_FLAG_HOST_ONLY 0x1u /* fit tables on the host only; no device work, no filtering */
+
+typedef struct {
+  bf_dtype_t in_dtype;      /* input element type, default BF_IN_F32 */
+  bf_precision_t precision; /* default BF_PREC_PLAIN */
+  double eps;               /* kernel truncation level (Sec. IV-A); 0 -> 0.01 */
+  double span;              /* intensity span D; range series on [-T, T], T = max(T_r, D); 0 -> 1 */
+  int tile;                 /* output tile edge of the summed-area tables; 0 -> automatic */
+  unsigned flags;           /* BF_FLAG_* */
+} bf_plan_opts_t;
+
+/* Create a plan: FP64 host fit of both expansions (Sec. IV, App. B), tap
+ * compilation, and upload of the tables to the current HIP device.
+ *   sigma_s, sigma_r > 0 and finite (sigma_r in intensity units of [0, span]);
+ *   radius >= 0 (0 -> ceil(K_s^{-1}(eps)) = ceil(sigma_s sqrt(2 ln(1/eps))));
+ *   opts may be NULL (all defaults).
+ * Errors: BF_ERR_INVALID_ARG for a NULL plan pointer or out-of-range
+ * parameter, BF_ERR_UNSUPPORTED for another kernel kind, BF_ERR_OUT_OF_MEMORY,
+ * BF_ERR_DEVICE.  The plan owns its device tables until bf_plan_destroy. */
+bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, double sigma_s,
+                           double sigma_r, int radius, bf_terms_t N, const bf_plan_opts_t *opts);
+
+/* Release a plan and everything it owns (waits for nothing; the caller must
+ * not destroy a plan while work that uses it is in flight).  NULL is a no-op. */
+bf_status_t bf_plan_destroy(bf_plan_t plan);
+
+/* Bytes of device workspace bf_filter_ws needs for an H x W image. */
+bf_status_t bf_workspace_size(bf_plan_t plan, int H, int W, size_t *bytes);
+
+/* Filter one image: out[H*W] (float32, same units as float input, [0, 1] for
+ * uint8 input) from I[H*W] (type fixed by the plan).  I and out are device
+ * pointers and must not overlap.  Uses a workspace owned by the plan, grown on
+ * demand (hipMalloc on first use at a larger size). */
+bf_status_t bf_filter(bf_plan_t plan, const void *I, float *out, int H, int W, void *stream);
+
+/* As bf_filter with a caller-owned device workspace of ws_bytes >=
+ * bf_workspace_size(plan, H, W).  Allocates nothing.  Calls that share a
+ * workspace must be ordered on one stream. */
+bf_status_t bf_filter_ws(bf_plan_t plan, const void *I, float *out, int H, int W, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/* As bf_filter_ws, also writing the numerator and denominator of Eq. BF
+ * (device float32 arrays of H*W; either may be NULL).  For validation. */
+bf_status_t bf_filter_parts(bf_plan_t plan, const void *I, float *out, float *num, float *den,
+                            int H, int W, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes for a batch (host arrays H[n], W[n]). */
+bf_status_t bf_batch_workspace_size(const bf_plan_t *plans, int n, const int *H, const int *W,
+                                    size_t *bytes);
+
+/* Filter n images of possibly different sizes and plans.  plans, I, out, H, W
+ * are HOST arrays of n entries (I[i], out[i] are device pointers); ws is a
+ * device workspace of >= bf_batch_workspace_size bytes.  If any entry is
+ * invalid the whole batch is rejected before anything is enqueued.  Output i
+ * is bitwise identical to bf_filter_ws(plans[i], I[i], out[i], H[i], W[i]). */
+bf_status_t bf_filter_batch(const bf_plan_t *plans, int n, const void *const *I, float *const *out,
+                            const int *H, const int *W, void *ws, size_t ws_bytes, void *stream);
+
+/* Plan introspection (host side; valid for BF_FLAG_HOST_ONLY plans too). */
+typedef struct {
+  int radius;         /* window radius r */
+  int n_range;        /* cosine terms kept */
+  int n_spatial;      /* Haar level groups kept */
+  int n_taps;         /* nonzero summed-area-table taps of the spatial expansion */
+  int n_tap_rows;     /* distinct tap row offsets */
+  int n_tap_cols;     /* distinct tap column offsets */
+  int n_images;       /* term images per filter call: 4 n_range - 3 */
+  int tile;           /* output tile edge */
+  int sat_shift;      /* q: term values are stored as round(v * 2^q) in int32 */
+  double T_s;         /* spatial truncation r + 1/2 */
+  double T_r;         /* K_r^{-1}(eps) */
+  double T;           /* range series half-interval max(T_r, span) */
+  double den_floor;   /* out = I where den <= den_floor (1e-7 sum |K~_s|) */
+} bf_plan_info_t;
+
+bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);
+
+/* Range terms: k[i], a[i] (coefficient a_k) and omega[i] = pi k / T, i < n_range. */
+bf_status_t bf_plan_range_terms(bf_plan_t plan, int *k, double *a, double *omega, int capacity);
+
+/* Sampled spatial expansion K~_s(dy, dx) for dy, dx in [-r, r]:
+ * K[(dy + r)(2r + 1) + dx + r], capacity >= (2r + 1)^2. */
+bf_status_t bf_plan_spatial_kernel(bf_plan_t plan, double *K, int capacity);
+
+/* Summed-area-table taps: corr(p) = sum_i w[i] S(p_y + dy[i], p_x + dx[i])
+ * with S the exclusive table S(Y, X) = sum_{y < Y, x < X} g(y, x), indices
+ * clamped to [0, H] x [0, W]. */
+bf_status_t bf_plan_taps(bf_plan_t plan, int *dy, int *dx, double *w, int capacity);
+
+/* Selected Haar level groups as (level_x, level_y) pairs, level -1 = phi. */
+bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, int capacity);
+
+/* Per-kernel timing for measurement.  While enabled, every filter call
+ * records HIP events around each of its kernels on the call's stream (all
+ * work still runs); bf_profile_read waits for the recorded events, returns
+ * the summed milliseconds and launch counts per kernel (index 0: summed-area
+ * tables, 1: tap lookup and normalisation) and clears them.  Process-wide,
+ * not thread-safe; for benchmarks. */
+bf_status_t bf_profile_enable(int on);
+bf_status_t bf_profile_read(double ms[2], int launches[2]);
+
+const char *bf_status_string(bf_status_t s);
+
+/* Library version string. */
+const char *bf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BF_H */

@@ -1,0 +1,263 @@
+"""ctypes binding of libbf.so (the C ABI of include/bf.h).
+
+Argument marshalling only: every step of the filter runs in the library's HIP
+kernels.  torch tensors are used for device memory and streams.  The library
+must have been built (paper_1803_00004_amd/build.py); importing this module
+without it raises, there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbf.so")
+
+BF_OK, BF_ERR_INVALID_ARG, BF_ERR_OUT_OF_MEMORY, BF_ERR_DEVICE, BF_ERR_UNSUPPORTED = range(5)
+BF_KERNEL_GAUSSIAN = 0
+BF_IN_F32, BF_IN_U8 = 0, 1
+BF_PREC_PLAIN, BF_PREC_REDUCED = 0, 1
+BF_FLAG_HOST_ONLY = 0x1
+
+EXPORTED = [
+    "bf_plan_create", "bf_plan_destroy", "bf_workspace_size", "bf_filter", "bf_filter_ws",
+    "bf_filter_parts", "bf_batch_workspace_size", "bf_filter_batch", "bf_plan_query",
+    "bf_plan_range_terms", "bf_plan_spatial_kernel", "bf_plan_taps", "bf_plan_spatial_groups",
+    "bf_profile_enable", "bf_profile_read", "bf_status_string", "bf_version",
+]
+
+
+class BFError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s failed: %s" % (what, status_string(status)))
+
+
+class _Terms(ctypes.Structure):
+    _fields_ = [("n_range", ctypes.c_int), ("n_spatial", ctypes.c_int)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("in_dtype", ctypes.c_int), ("precision", ctypes.c_int), ("eps", ctypes.c_double),
+                ("span", ctypes.c_double), ("tile", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("radius", ctypes.c_int), ("n_range", ctypes.c_int), ("n_spatial", ctypes.c_int),
+                ("n_taps", ctypes.c_int), ("n_tap_rows", ctypes.c_int), ("n_tap_cols", ctypes.c_int),
+                ("n_images", ctypes.c_int), ("tile", ctypes.c_int), ("sat_shift", ctypes.c_int),
+                ("T_s", ctypes.c_double), ("T_r", ctypes.c_double), ("T", ctypes.c_double),
+                ("den_floor", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libbf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libbf.so is not built: run python paper_1803_00004_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        ip, dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+        L.bf_plan_create.argtypes = [ctypes.POINTER(vp), i, i, d, d, i, _Terms, ctypes.POINTER(_Opts)]
+        L.bf_plan_destroy.argtypes = [vp]
+        L.bf_workspace_size.argtypes = [vp, i, i, ctypes.POINTER(sz)]
+        L.bf_filter.argtypes = [vp, vp, vp, i, i, vp]
+        L.bf_filter_ws.argtypes = [vp, vp, vp, i, i, vp, sz, vp]
+        L.bf_filter_parts.argtypes = [vp, vp, vp, vp, vp, i, i, vp, sz, vp]
+        L.bf_batch_workspace_size.argtypes = [ctypes.POINTER(vp), i, ip, ip, ctypes.POINTER(sz)]
+        L.bf_filter_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ip, ip, vp, sz, vp]
+        L.bf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.bf_plan_range_terms.argtypes = [vp, ip, dp, dp, i]
+        L.bf_plan_spatial_kernel.argtypes = [vp, dp, i]
+        L.bf_plan_taps.argtypes = [vp, ip, ip, dp, i]
+        L.bf_plan_spatial_groups.argtypes = [vp, ip, ip, i]
+        L.bf_profile_enable.argtypes = [i]
+        L.bf_profile_read.argtypes = [dp, ip]
+        L.bf_status_string.argtypes = [i]
+        L.bf_status_string.restype = ctypes.c_char_p
+        L.bf_version.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("bf_status_string", "bf_version"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def profile_enable(on=True):
+    _check(lib().bf_profile_enable(1 if on else 0), "bf_profile_enable")
+
+
+def profile_read():
+    """(ms[2], launches[2]) summed since the last read: [tables kernel, lookup kernel]."""
+    ms = (ctypes.c_double * 2)()
+    n = (ctypes.c_int * 2)()
+    _check(lib().bf_profile_read(ms, n), "bf_profile_read")
+    return list(ms), list(n)
+
+
+def status_string(s):
+    return lib().bf_status_string(int(s)).decode()
+
+
+def _check(status, what):
+    if status != BF_OK:
+        raise BFError(status, what)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A filter plan: both kernel expansions fitted (FP64, host) and uploaded."""
+
+    def __init__(self, sigma_s, sigma_r, radius=0, n_range=8, n_spatial=4, dtype="f32",
+                 precision="plain", eps=0.0, span=0.0, tile=0, host_only=False):
+        self._h = ctypes.c_void_p()
+        opts = _Opts(BF_IN_U8 if dtype == "u8" else BF_IN_F32,
+                     BF_PREC_REDUCED if precision == "reduced" else BF_PREC_PLAIN,
+                     float(eps), float(span), int(tile), BF_FLAG_HOST_ONLY if host_only else 0)
+        st = lib().bf_plan_create(ctypes.byref(self._h), BF_KERNEL_GAUSSIAN, BF_KERNEL_GAUSSIAN,
+                                  float(sigma_s), float(sigma_r), int(radius),
+                                  _Terms(int(n_range), int(n_spatial)), ctypes.byref(opts))
+        _check(st, "bf_plan_create")
+        self.dtype = dtype
+        self.info = self.query()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().bf_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self):
+        info = PlanInfo()
+        _check(lib().bf_plan_query(self._h, ctypes.byref(info)), "bf_plan_query")
+        return info
+
+    def range_terms(self):
+        n = self.info.n_range
+        k = (ctypes.c_int * n)()
+        a = (ctypes.c_double * n)()
+        w = (ctypes.c_double * n)()
+        _check(lib().bf_plan_range_terms(self._h, k, a, w, n), "bf_plan_range_terms")
+        return np.array(k[:]), np.array(a[:]), np.array(w[:])
+
+    def spatial_kernel(self):
+        r = self.info.radius
+        n = (2 * r + 1) ** 2
+        K = (ctypes.c_double * n)()
+        _check(lib().bf_plan_spatial_kernel(self._h, K, n), "bf_plan_spatial_kernel")
+        return np.array(K[:]).reshape(2 * r + 1, 2 * r + 1)
+
+    def taps(self):
+        n = self.info.n_taps
+        dy, dx, w = (ctypes.c_int * n)(), (ctypes.c_int * n)(), (ctypes.c_double * n)()
+        _check(lib().bf_plan_taps(self._h, dy, dx, w, n), "bf_plan_taps")
+        return np.array(dy[:]), np.array(dx[:]), np.array(w[:])
+
+    def spatial_groups(self):
+        n = self.info.n_spatial
+        lx, ly = (ctypes.c_int * n)(), (ctypes.c_int * n)()
+        _check(lib().bf_plan_spatial_groups(self._h, lx, ly, n), "bf_plan_spatial_groups")
+        return list(zip(lx[:], ly[:]))
+
+    def workspace_size(self, H, W):
+        b = ctypes.c_size_t()
+        _check(lib().bf_workspace_size(self._h, int(H), int(W), ctypes.byref(b)), "bf_workspace_size")
+        return b.value
+
+
+def _image_args(plan, I):
+    import torch
+    if not (isinstance(I, torch.Tensor) and I.is_cuda and I.dim() == 2 and I.is_contiguous()):
+        raise ValueError("I must be a contiguous 2-D CUDA tensor")
+    want = torch.uint8 if plan.dtype == "u8" else torch.float32
+    if I.dtype != want:
+        raise ValueError("plan expects %s input" % want)
+    return I.shape[0], I.shape[1]
+
+
+def workspace(plan, H, W, device=None):
+    """A device workspace tensor of the size bf_filter_ws needs."""
+    import torch
+    return torch.empty(max(1, plan.workspace_size(H, W)), dtype=torch.uint8,
+                       device=device or "cuda")
+
+
+def filter(plan, I, out=None, ws=None, stream=None, num=None, den=None):
+    """Filter one image (torch CUDA tensor).  With ws=None the plan's own
+    workspace is used (bf_filter); otherwise bf_filter_ws / bf_filter_parts."""
+    import torch
+    H, W = _image_args(plan, I)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=I.device)
+    s = _stream_handle(stream)
+    if ws is None and num is None and den is None:
+        st = lib().bf_filter(plan.handle, ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                             H, W, s)
+        _check(st, "bf_filter")
+        return out
+    if ws is None:
+        ws = workspace(plan, H, W, I.device)
+    nump = ctypes.c_void_p(num.data_ptr()) if num is not None else None
+    denp = ctypes.c_void_p(den.data_ptr()) if den is not None else None
+    st = lib().bf_filter_parts(plan.handle, ctypes.c_void_p(I.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), nump, denp, H, W,
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), s)
+    _check(st, "bf_filter_parts")
+    return out
+
+
+def batch_workspace_size(plans, shapes):
+    n = len(plans)
+    hs = (ctypes.c_int * n)(*[int(h) for h, _ in shapes])
+    wd = (ctypes.c_int * n)(*[int(w) for _, w in shapes])
+    hp = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    b = ctypes.c_size_t()
+    _check(lib().bf_batch_workspace_size(hp, n, hs, wd, ctypes.byref(b)), "bf_batch_workspace_size")
+    return b.value
+
+
+def filter_batch(plans, images, outs=None, ws=None, stream=None):
+    """Filter a list of images (torch CUDA tensors) with their plans."""
+    import torch
+    n = len(plans)
+    shapes = [_image_args(p, I) for p, I in zip(plans, images)]
+    if outs is None:
+        outs = [torch.empty(s, dtype=torch.float32, device=I.device) for s, I in zip(shapes, images)]
+    if ws is None:
+        ws = torch.empty(max(1, batch_workspace_size(plans, shapes)), dtype=torch.uint8,
+                         device=images[0].device)
+    hp = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    ip = (ctypes.c_void_p * n)(*[I.data_ptr() for I in images])
+    op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    hs = (ctypes.c_int * n)(*[h for h, _ in shapes])
+    wd = (ctypes.c_int * n)(*[w for _, w in shapes])
+    st = lib().bf_filter_batch(hp, n, ip, op, hs, wd, ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel() * ws.element_size(), _stream_handle(stream))
+    _check(st, "bf_filter_batch")
+    return outs

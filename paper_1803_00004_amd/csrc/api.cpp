@@ -1,0 +1,316 @@
+// C ABI of the library (declared in include/bf.h): plan lifetime, workspace
+// sizing, argument validation and kernel launches.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "bf.h"
+#include "bf_internal.h"
+
+namespace {
+
+constexpr int kMaxSide = 32768;
+
+bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + nb && b0 < a0 + na;
+}
+
+int choose_tile(int radius) { return radius <= 32 ? 256 : 512; }
+
+// q with (E - 1)^2 * 2^q * gmax <= 2^31 - 1 for tables of edge E.
+int choose_shift(int tile, int radius, double gmax) {
+  const double E = tile + 2.0 * radius;  // E_max - 1 summed rows/columns
+  const double lim = 2147483647.0 / (E * E * gmax);
+  int q = (int)std::floor(std::log2(lim));
+  return std::max(0, std::min(24, q));
+}
+
+bf::Geometry geometry_of(const bf_plan_s *p, int H, int W) {
+  return bf::make_geometry(H, W, p->tile, p->fit.radius, p->host_tables.n_images);
+}
+
+bf_status_t check_image(const bf_plan_s *p, const void *I, const float *out, int H, int W) {
+  if (!p || !I || !out) return BF_ERR_INVALID_ARG;
+  if (p->flags & BF_FLAG_HOST_ONLY) return BF_ERR_INVALID_ARG;
+  if (H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
+  const size_t n = (size_t)H * W;
+  const size_t in_bytes = n * (p->in_dtype == BF_IN_U8 ? 1 : 4);
+  if (ranges_overlap(I, in_bytes, out, n * 4)) return BF_ERR_INVALID_ARG;
+  return BF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, double sigma_s,
+                           double sigma_r, int radius, bf_terms_t N, const bf_plan_opts_t *opts) {
+  if (!plan) return BF_ERR_INVALID_ARG;
+  *plan = nullptr;
+  if (K_s != BF_KERNEL_GAUSSIAN || K_r != BF_KERNEL_GAUSSIAN) {
+    if ((int)K_s < 0 || (int)K_r < 0) return BF_ERR_INVALID_ARG;
+    return BF_ERR_UNSUPPORTED;
+  }
+  bf_plan_opts_t o{};
+  if (opts) o = *opts;
+  if (o.in_dtype != BF_IN_F32 && o.in_dtype != BF_IN_U8) return BF_ERR_INVALID_ARG;
+  if (o.precision != BF_PREC_PLAIN && o.precision != BF_PREC_REDUCED) return BF_ERR_INVALID_ARG;
+  if (o.precision == BF_PREC_REDUCED) return BF_ERR_UNSUPPORTED;
+  const double eps = o.eps == 0.0 ? 0.01 : o.eps;
+  const double span = o.span == 0.0 ? 1.0 : o.span;
+  if (!(span > 0) || !std::isfinite(span) || radius < 0) return BF_ERR_INVALID_ARG;
+  if (o.tile != 0 && (o.tile < 64 || o.tile > 2048 || o.tile % 64 != 0)) return BF_ERR_INVALID_ARG;
+
+  bf_plan_s *p = new (std::nothrow) bf_plan_s();
+  if (!p) return BF_ERR_OUT_OF_MEMORY;
+  bf_status_t st = bf::fit_plan(sigma_s, sigma_r, radius, N, eps, span, &p->fit);
+  if (st != BF_OK) {
+    delete p;
+    return st;
+  }
+  const bf::Fit &f = p->fit;
+  if ((int)f.row_off.size() > bf::kMaxTapAxis || (int)f.col_off.size() > bf::kMaxTapAxis) {
+    delete p;
+    return BF_ERR_UNSUPPORTED;
+  }
+  p->in_dtype = o.in_dtype;
+  p->precision = o.precision;
+  p->flags = o.flags;
+  p->tile = o.tile ? o.tile : choose_tile(f.radius);
+  const double gmax = o.in_dtype == BF_IN_U8 ? 1.0 : std::max(1.0, span);
+  p->sat_shift = choose_shift(p->tile, f.radius, gmax);
+
+  bf::DevTables &t = p->host_tables;
+  std::memset(&t, 0, sizeof t);
+  t.n_terms = (int)f.k.size();
+  t.n_ty = (int)f.row_off.size();
+  t.n_tx = (int)f.col_off.size();
+  for (int i = 0; i < t.n_ty; ++i) t.ty[i] = f.row_off[i];
+  for (int j = 0; j < t.n_tx; ++j) t.tx[j] = f.col_off[j];
+  for (int i = 0; i < t.n_ty; ++i)
+    for (int j = 0; j < t.n_tx; ++j) t.w[i * bf::kMaxTapAxis + j] = f.tap_grid[(size_t)i * t.n_tx + j];
+  // compact tap list with byte offsets for the table pitch of this plan
+  const bf::Geometry g0 = bf::make_geometry(1, 1, p->tile, f.radius, 1);
+  const int nt = (int)f.tap_w.size();
+  if (nt > bf::kMaxTaps - 3) {
+    delete p;
+    return BF_ERR_UNSUPPORTED;
+  }
+  t.pitch = g0.pitch;
+  t.n_taps4 = (nt + 3) / 4 * 4;
+  t.tap_dy_min = t.tap_dx_min = 1 << 30;
+  t.tap_dy_max = t.tap_dx_max = -(1 << 30);
+  t.tap_d_min = 1 << 30;
+  for (int i = 0; i < nt; ++i) {
+    t.tap_dy[i] = f.tap_dy[i];
+    t.tap_dx[i] = f.tap_dx[i];
+    t.tap_w[i] = f.tap_w[i];
+    t.tap_dy_min = std::min(t.tap_dy_min, f.tap_dy[i]);
+    t.tap_dy_max = std::max(t.tap_dy_max, f.tap_dy[i]);
+    t.tap_dx_min = std::min(t.tap_dx_min, f.tap_dx[i]);
+    t.tap_dx_max = std::max(t.tap_dx_max, f.tap_dx[i]);
+    t.tap_d_min = std::min(t.tap_d_min, f.tap_dy[i] * t.pitch + f.tap_dx[i]);
+  }
+  for (int i = nt; i < t.n_taps4; ++i) {  // padding: weight 0 at the first tap's position
+    t.tap_dy[i] = f.tap_dy[0];
+    t.tap_dx[i] = f.tap_dx[0];
+    t.tap_w[i] = 0.0;
+  }
+  for (int i = 0; i < t.n_taps4; ++i)
+    t.tap_boff[i] = 4 * (t.tap_dy[i] * t.pitch + t.tap_dx[i] - t.tap_d_min);
+  int slot = 0;
+  for (int i = 0; i < t.n_terms; ++i) {
+    double fk = f.k[i] / (2.0 * f.T);
+    if (o.in_dtype == BF_IN_U8) fk /= 255.0;
+    t.f_hi[i] = (float)fk;
+    t.f_lo[i] = (float)(fk - (double)t.f_hi[i]);
+    t.a[i] = f.a[i];
+    t.k_is_zero[i] = f.k[i] == 0;
+    t.slot[i] = slot;
+    slot += f.k[i] == 0 ? 1 : 4;
+  }
+  t.n_images = slot;
+  t.sat_scale = std::ldexp(1.0f, p->sat_shift);
+  t.inv_sat_scale = std::ldexp(1.0, -p->sat_shift);
+  t.gmax = (float)gmax;
+  t.den_floor = 1e-7 * f.sum_abs_K;
+  t.in_u8 = o.in_dtype == BF_IN_U8;
+
+  if (!(p->flags & BF_FLAG_HOST_ONLY)) {
+    if (hipGetDevice(&p->device) != hipSuccess) {
+      delete p;
+      return BF_ERR_DEVICE;
+    }
+    void *d = nullptr;
+    if (hipMalloc(&d, sizeof(bf::DevTables)) != hipSuccess) {
+      delete p;
+      return BF_ERR_OUT_OF_MEMORY;
+    }
+    if (hipMemcpy(d, &t, sizeof t, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d);
+      delete p;
+      return BF_ERR_DEVICE;
+    }
+    p->dev_tables = static_cast<bf::DevTables *>(d);
+  }
+  *plan = p;
+  return BF_OK;
+}
+
+bf_status_t bf_plan_destroy(bf_plan_t plan) {
+  if (!plan) return BF_OK;
+  if (plan->dev_tables) (void)hipFree(plan->dev_tables);
+  if (plan->own_ws) (void)hipFree(plan->own_ws);
+  delete plan;
+  return BF_OK;
+}
+
+bf_status_t bf_workspace_size(bf_plan_t plan, int H, int W, size_t *bytes) {
+  if (!plan || !bytes || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
+  *bytes = geometry_of(plan, H, W).bytes;
+  return BF_OK;
+}
+
+bf_status_t bf_filter_parts(bf_plan_t plan, const void *I, float *out, float *num, float *den,
+                            int H, int W, void *ws, size_t ws_bytes, void *stream) {
+  bf_status_t st = check_image(plan, I, out, H, W);
+  if (st != BF_OK) return st;
+  const bf::Geometry g = geometry_of(plan, H, W);
+  if (!ws || ws_bytes < g.bytes) return BF_ERR_INVALID_ARG;
+  return bf::launch_filter(plan->dev_tables, plan->host_tables, g, I, out, num, den,
+                           static_cast<int32_t *>(ws), stream);
+}
+
+bf_status_t bf_filter_ws(bf_plan_t plan, const void *I, float *out, int H, int W, void *ws,
+                         size_t ws_bytes, void *stream) {
+  return bf_filter_parts(plan, I, out, nullptr, nullptr, H, W, ws, ws_bytes, stream);
+}
+
+bf_status_t bf_filter(bf_plan_t plan, const void *I, float *out, int H, int W, void *stream) {
+  bf_status_t st = check_image(plan, I, out, H, W);
+  if (st != BF_OK) return st;
+  const bf::Geometry g = geometry_of(plan, H, W);
+  if (plan->own_ws_bytes < g.bytes) {
+    // the old workspace may still be read by queued work on `stream`
+    if (plan->own_ws) {
+      if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return BF_ERR_DEVICE;
+      (void)hipFree(plan->own_ws);
+      plan->own_ws = nullptr;
+      plan->own_ws_bytes = 0;
+    }
+    void *d = nullptr;
+    if (hipMalloc(&d, g.bytes) != hipSuccess) return BF_ERR_OUT_OF_MEMORY;
+    plan->own_ws = d;
+    plan->own_ws_bytes = g.bytes;
+  }
+  return bf::launch_filter(plan->dev_tables, plan->host_tables, g, I, out, nullptr, nullptr,
+                           static_cast<int32_t *>(plan->own_ws), stream);
+}
+
+bf_status_t bf_batch_workspace_size(const bf_plan_t *plans, int n, const int *H, const int *W,
+                                    size_t *bytes) {
+  if (!plans || !H || !W || !bytes || n < 0) return BF_ERR_INVALID_ARG;
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    size_t b = 0;
+    bf_status_t st = bf_workspace_size(plans[i], H[i], W[i], &b);
+    if (st != BF_OK) return st;
+    need = std::max(need, b);
+  }
+  *bytes = need;
+  return BF_OK;
+}
+
+bf_status_t bf_filter_batch(const bf_plan_t *plans, int n, const void *const *I, float *const *out,
+                            const int *H, const int *W, void *ws, size_t ws_bytes, void *stream) {
+  if (!plans || !I || !out || !H || !W || n < 0) return BF_ERR_INVALID_ARG;
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    bf_status_t st = check_image(plans[i], I[i], out[i], H[i], W[i]);
+    if (st != BF_OK) return st;
+    need = std::max(need, geometry_of(plans[i], H[i], W[i]).bytes);
+  }
+  if (n > 0 && (!ws || ws_bytes < need)) return BF_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    const bf::Geometry g = geometry_of(plans[i], H[i], W[i]);
+    bf_status_t st = bf::launch_filter(plans[i]->dev_tables, plans[i]->host_tables, g, I[i], out[i],
+                                       nullptr, nullptr, static_cast<int32_t *>(ws), stream);
+    if (st != BF_OK) return st;
+  }
+  return BF_OK;
+}
+
+bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
+  if (!plan || !info) return BF_ERR_INVALID_ARG;
+  const bf::Fit &f = plan->fit;
+  info->radius = f.radius;
+  info->n_range = (int)f.k.size();
+  info->n_spatial = (int)f.group_lx.size();
+  info->n_taps = (int)f.tap_w.size();
+  info->n_tap_rows = (int)f.row_off.size();
+  info->n_tap_cols = (int)f.col_off.size();
+  info->n_images = plan->host_tables.n_images;
+  info->tile = plan->tile;
+  info->sat_shift = plan->sat_shift;
+  info->T_s = f.T_s;
+  info->T_r = f.T_r;
+  info->T = f.T;
+  info->den_floor = plan->host_tables.den_floor;
+  return BF_OK;
+}
+
+bf_status_t bf_plan_range_terms(bf_plan_t plan, int *k, double *a, double *omega, int capacity) {
+  if (!plan || !k || !a || !omega || capacity < (int)plan->fit.k.size()) return BF_ERR_INVALID_ARG;
+  for (size_t i = 0; i < plan->fit.k.size(); ++i) {
+    k[i] = plan->fit.k[i];
+    a[i] = plan->fit.a[i];
+    omega[i] = plan->fit.omega[i];
+  }
+  return BF_OK;
+}
+
+bf_status_t bf_plan_spatial_kernel(bf_plan_t plan, double *K, int capacity) {
+  if (!plan || !K || capacity < (int)plan->fit.K.size()) return BF_ERR_INVALID_ARG;
+  std::copy(plan->fit.K.begin(), plan->fit.K.end(), K);
+  return BF_OK;
+}
+
+bf_status_t bf_plan_taps(bf_plan_t plan, int *dy, int *dx, double *w, int capacity) {
+  if (!plan || !dy || !dx || !w || capacity < (int)plan->fit.tap_w.size()) return BF_ERR_INVALID_ARG;
+  for (size_t i = 0; i < plan->fit.tap_w.size(); ++i) {
+    dy[i] = plan->fit.tap_dy[i];
+    dx[i] = plan->fit.tap_dx[i];
+    w[i] = plan->fit.tap_w[i];
+  }
+  return BF_OK;
+}
+
+bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, int capacity) {
+  if (!plan || !level_x || !level_y || capacity < (int)plan->fit.group_lx.size())
+    return BF_ERR_INVALID_ARG;
+  for (size_t i = 0; i < plan->fit.group_lx.size(); ++i) {
+    level_x[i] = plan->fit.group_lx[i];
+    level_y[i] = plan->fit.group_ly[i];
+  }
+  return BF_OK;
+}
+
+const char *bf_status_string(bf_status_t s) {
+  switch (s) {
+    case BF_OK: return "BF_OK";
+    case BF_ERR_INVALID_ARG: return "BF_ERR_INVALID_ARG";
+    case BF_ERR_OUT_OF_MEMORY: return "BF_ERR_OUT_OF_MEMORY";
+    case BF_ERR_DEVICE: return "BF_ERR_DEVICE";
+    case BF_ERR_UNSUPPORTED: return "BF_ERR_UNSUPPORTED";
+  }
+  return "BF_ERR_UNKNOWN";
+}
+
+const char *bf_version(void) { return "bf-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

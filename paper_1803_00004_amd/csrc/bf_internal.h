@@ -1,0 +1,103 @@
+// Internal structures shared by the host plan, the C ABI and the HIP kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "bf.h"
+
+namespace bf {
+
+// Compile-time capacities of the device tables.
+constexpr int kMaxTerms = 64;      // cosine terms per plan
+constexpr int kMaxTapAxis = 16;    // distinct tap offsets per axis (Haar levels <= 3)
+constexpr int kMaxTaps = 256;      // nonzero summed-area-table taps (padded to a multiple of 4)
+constexpr int kKA_Threads = 256;   // summed-area-table kernel block size (upper bound)
+
+// Host-side result of the FP64 fit (Sec. IV, App. A/B).
+struct Fit {
+  int radius = 0;
+  double T_s = 0, T_r = 0, T = 0, eps = 0.01, span = 1.0;
+  // spatial
+  std::vector<int> group_lx, group_ly;  // selected Haar level groups (-1 = phi)
+  std::vector<double> K;                // (2r+1)^2 sampled expansion, K[(dy+r)(2r+1) + dx+r]
+  // taps of the exclusive summed-area table: corr(p) = sum w S(p + (dy, dx))
+  std::vector<int> tap_dy, tap_dx;
+  std::vector<double> tap_w;
+  std::vector<int> row_off, col_off;   // distinct tap offsets per axis (sorted)
+  std::vector<double> tap_grid;        // [row_off.size()][col_off.size()] weights (0 = no tap)
+  double sum_abs_K = 0;
+  // range
+  std::vector<int> k;
+  std::vector<double> a, omega;
+};
+
+// Fit both expansions; returns BF_OK or BF_ERR_INVALID_ARG.
+bf_status_t fit_plan(double sigma_s, double sigma_r, int radius, bf_terms_t N, double eps,
+                     double span, Fit *out);
+
+// Device-side constant tables of a plan (one upload per plan).
+struct DevTables {
+  int n_terms;
+  int n_ty, n_tx;                      // tap grid shape
+  int ty[kMaxTapAxis], tx[kMaxTapAxis];
+  double w[kMaxTapAxis * kMaxTapAxis]; // tap weights on the grid, row stride kMaxTapAxis (0 = none)
+  // compact list of the nonzero taps, padded with zero-weight taps to n_taps4
+  int n_taps4;
+  int tap_dy[kMaxTaps], tap_dx[kMaxTaps];
+  double tap_w[kMaxTaps];
+  int tap_dy_min, tap_dy_max, tap_dx_min, tap_dx_max;
+  // byte offset of each tap relative to the smallest one, for the plan's
+  // table pitch: 4 ((dy - dy0) pitch + dx - dx0) with (dy0, dx0) the smallest
+  int tap_boff[kMaxTaps];
+  int tap_d_min;                       // min over taps of dy * pitch + dx
+  int pitch;                           // table row pitch (elements) for this plan
+  float f_hi[kMaxTerms], f_lo[kMaxTerms];  // f_k = k / (2T) (u8: k / (2T 255)) as two floats
+  double a[kMaxTerms];                 // a_k
+  int k_is_zero[kMaxTerms];            // term k = 0: one image (I), analytic denominator
+  int slot[kMaxTerms];                 // first table of the term
+  float sat_scale;                     // 2^q
+  double inv_sat_scale;                // 2^-q
+  float gmax;                          // |term value| clamp
+  double den_floor;
+  int in_u8;
+  int n_images;
+};
+
+// Geometry of one image under a plan: tiles of `tile` outputs with their
+// tile-relative summed-area tables of E_h x E_w (pitch P_w) int32 entries.
+struct Geometry {
+  int H, W, tile, radius;
+  int tiles_y, tiles_x, n_images;
+  int E_max, pitch;                 // max table edge (tile + 2r + 1) and padded row pitch
+  size_t table_elems;               // E_max * pitch per table
+  size_t bytes;                     // whole workspace
+};
+
+Geometry make_geometry(int H, int W, int tile, int radius, int n_images);
+
+// Launch the two kernels of one image on `stream` (hipStream_t): `dev` is
+// the device copy of `host`.
+bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geometry &g,
+                          const void *I, float *out, float *num, float *den, int32_t *ws,
+                          void *stream);
+
+// Optional per-kernel event recording (bf_profile_enable); kernel 0 / 1.
+void profile_mark(int kernel, int begin, void *stream);
+
+}  // namespace bf
+
+struct bf_plan_s {
+  bf::Fit fit;
+  bf_dtype_t in_dtype = BF_IN_F32;
+  bf_precision_t precision = BF_PREC_PLAIN;
+  int tile = 256;
+  int sat_shift = 14;
+  unsigned flags = 0;
+  bf::DevTables host_tables{};
+  bf::DevTables *dev_tables = nullptr;  // device copy
+  void *own_ws = nullptr;               // workspace grown by bf_filter
+  size_t own_ws_bytes = 0;
+  int device = 0;
+};

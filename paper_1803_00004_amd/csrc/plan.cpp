@@ -1,0 +1,248 @@
+// Host-side FP64 fit of the two kernel expansions and compilation of the
+// spatial expansion into summed-area-table taps.
+//
+//  * Spatial: best N-term approximation of the truncated Gaussian K_s on 2-D
+//    Haar functions (Sec. III-C Eqs. Haar_scaling / Haar_mother / Haar_set,
+//    2-D coefficients of Eq. Haar_2D_coefficients, selection of Eq.
+//    Haar_N_terms).  The kernel is selected in level groups (all functions of
+//    one level pair) ranked by L2 energy, point-sampled on the integer grid
+//    with half-open intervals, T_s = r + 1/2.
+//  * Taps: the sampled kernel is piecewise constant on rectangles (App. A,
+//    Table VI); its mixed second differences give the corners at which the
+//    four-reference box sums of Eq. sum_sat_sum_region_2D read the table.
+//  * Range: best N-term truncated cosine approximation (Sec. III-B, Eq.
+//    1D_truncated_cos; Sec. IV-C, Eq. trigonometric_N_terms), coefficients by
+//    composite Gauss-Legendre quadrature, the N largest |a_k| among the first
+//    20N (App. B), on [-T, T] with T = max(T_r, span) so that every intensity
+//    difference lies inside the series interval.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <numeric>
+#include <vector>
+
+#include "bf_internal.h"
+
+namespace bf {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Integral of exp(-t^2 / 2 sigma^2) over [a, b].
+double gauss_int(double a, double b, double sigma) {
+  const double s = sigma * std::sqrt(2.0);
+  return sigma * std::sqrt(kPi / 2.0) * (std::erf(b / s) - std::erf(a / s));
+}
+
+struct Haar {
+  int level;  // -1 = phi
+  int k;
+  double lo, mid, hi;
+  double sample(double d) const {
+    if (level < 0) return (d >= lo && d < hi) ? 1.0 : 0.0;
+    if (d >= lo && d < mid) return 1.0;
+    if (d >= mid && d < hi) return -1.0;
+    return 0.0;
+  }
+};
+
+std::vector<Haar> haar_family(double T, int J) {
+  std::vector<Haar> f;
+  f.push_back({-1, 0, -T, 0.0, T});
+  f.push_back({0, 0, -T, 0.0, T});
+  for (int j = 1; j <= J; ++j) {
+    const int half = 1 << (j - 1);
+    const double s = std::ldexp(1.0, -j);
+    for (int k = -half; k <= half; ++k) {
+      if (k == 0) continue;
+      const double Z = (k > 0 ? 1.0 : -1.0) * (2.0 * std::abs(k) - 1.0) * T;
+      f.push_back({j, k, s * (Z - T), s * Z, s * (Z + T)});
+    }
+  }
+  return f;
+}
+
+double round_sig12(double x) {
+  if (x == 0.0) return 0.0;
+  char buf[64];
+  std::snprintf(buf, sizeof buf, "%.11e", x);
+  return std::strtod(buf, nullptr);
+}
+
+// n-point Gauss-Legendre nodes/weights on [-1, 1] (Newton on P_n).
+void gauss_legendre(int n, std::vector<double> *x, std::vector<double> *w) {
+  x->assign(n, 0.0);
+  w->assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int m = 2; m <= n; ++m) {
+        const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int m = 2; m <= n; ++m) {
+      const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    (*x)[i] = z;
+    (*w)[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+}  // namespace
+
+bf_status_t fit_plan(double sigma_s, double sigma_r, int radius, bf_terms_t N, double eps,
+                     double span, Fit *out) {
+  if (!(sigma_s > 0) || !std::isfinite(sigma_s) || !(sigma_r > 0) || !std::isfinite(sigma_r) ||
+      !(eps > 0 && eps < 1) || !(span >= 0) || !std::isfinite(span))
+    return BF_ERR_INVALID_ARG;
+  if (radius == 0) radius = (int)std::ceil(sigma_s * std::sqrt(2.0 * std::log(1.0 / eps)));
+  if (radius < 1 || radius > 1024) return BF_ERR_INVALID_ARG;
+  if (N.n_range < 1 || N.n_range > kMaxTerms) return BF_ERR_INVALID_ARG;
+
+  Fit f;
+  f.radius = radius;
+  f.eps = eps;
+  f.span = span;
+
+  // ---------------- spatial ----------------
+  const double T = radius + 0.5;
+  f.T_s = T;
+  const int J = (int)std::floor(std::log2(T));
+  const int n_levels = J + 2;  // phi, 0..J
+  if (N.n_spatial < 1 || N.n_spatial > n_levels * n_levels) return BF_ERR_INVALID_ARG;
+  const std::vector<Haar> fam = haar_family(T, J);
+  std::vector<double> c(fam.size());
+  std::vector<double> e1(n_levels, 0.0);  // index level + 1
+  for (size_t i = 0; i < fam.size(); ++i) {
+    const Haar &h = fam[i];
+    if (h.level < 0)
+      c[i] = gauss_int(h.lo, h.hi, sigma_s) / (2.0 * T);
+    else
+      c[i] = std::ldexp(1.0, h.level) *
+             (gauss_int(h.lo, h.mid, sigma_s) - gauss_int(h.mid, h.hi, sigma_s)) / (2.0 * T);
+    e1[h.level + 1] += c[i] * c[i] * (h.hi - h.lo);
+  }
+  struct Group { double e; int lx, ly; };
+  std::vector<Group> groups;
+  for (int lx = -1; lx <= J; ++lx)
+    for (int ly = -1; ly <= J; ++ly)
+      groups.push_back({round_sig12(e1[lx + 1] * e1[ly + 1]), lx, ly});
+  std::sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) {
+    if (a.e != b.e) return a.e > b.e;
+    if (a.lx + a.ly != b.lx + b.ly) return a.lx + a.ly < b.lx + b.ly;
+    return a.lx < b.lx;
+  });
+  const int ks = 2 * radius + 1;
+  // u_l(d) = sum_{b in level l} c_b b(d), d in [-r, r]
+  std::vector<double> u((size_t)n_levels * ks, 0.0);
+  for (size_t i = 0; i < fam.size(); ++i)
+    for (int d = -radius; d <= radius; ++d)
+      u[(size_t)(fam[i].level + 1) * ks + d + radius] += c[i] * fam[i].sample((double)d);
+  f.K.assign((size_t)ks * ks, 0.0);
+  for (int g = 0; g < N.n_spatial; ++g) {
+    const int lx = groups[g].lx, ly = groups[g].ly;
+    f.group_lx.push_back(lx);
+    f.group_ly.push_back(ly);
+    const double *ux = &u[(size_t)(lx + 1) * ks], *uy = &u[(size_t)(ly + 1) * ks];
+    for (int iy = 0; iy < ks; ++iy)
+      for (int ix = 0; ix < ks; ++ix) f.K[(size_t)iy * ks + ix] += uy[iy] * ux[ix];
+  }
+  double kmax = 0;
+  f.sum_abs_K = 0;
+  for (double v : f.K) {
+    kmax = std::max(kmax, std::fabs(v));
+    f.sum_abs_K += std::fabs(v);
+  }
+  // Taps.  corr(p) = sum_q K(p - q) g(q) = sum_u D(u) S_incl(p - u) with
+  // D(u) = K(u) - K(u - e_y) - K(u - e_x) + K(u - e_y - e_x), u in [-r, r+1]^2
+  // (K zero outside the window) and S_incl(Y, X) = S(Y + 1, X + 1) for the
+  // exclusive table S; so the tap offset is (1 - u_y, 1 - u_x).
+  auto Kat = [&](int dy, int dx) -> double {
+    if (dy < -radius || dy > radius || dx < -radius || dx > radius) return 0.0;
+    return f.K[(size_t)(dy + radius) * ks + dx + radius];
+  };
+  std::vector<int> rows, cols;
+  for (int uy = -radius; uy <= radius + 1; ++uy)
+    for (int ux = -radius; ux <= radius + 1; ++ux) {
+      const double D = Kat(uy, ux) - Kat(uy - 1, ux) - Kat(uy, ux - 1) + Kat(uy - 1, ux - 1);
+      if (std::fabs(D) <= 1e-14 * kmax) continue;
+      f.tap_dy.push_back(1 - uy);
+      f.tap_dx.push_back(1 - ux);
+      f.tap_w.push_back(D);
+      rows.push_back(1 - uy);
+      cols.push_back(1 - ux);
+    }
+  std::sort(rows.begin(), rows.end());
+  rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+  std::sort(cols.begin(), cols.end());
+  cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+  f.row_off = rows;
+  f.col_off = cols;
+  f.tap_grid.assign(rows.size() * cols.size(), 0.0);
+  for (size_t t = 0; t < f.tap_w.size(); ++t) {
+    const size_t i = std::lower_bound(rows.begin(), rows.end(), f.tap_dy[t]) - rows.begin();
+    const size_t j = std::lower_bound(cols.begin(), cols.end(), f.tap_dx[t]) - cols.begin();
+    f.tap_grid[i * cols.size() + j] = f.tap_w[t];
+  }
+
+  // ---------------- range ----------------
+  f.T_r = sigma_r * std::sqrt(2.0 * std::log(1.0 / eps));
+  f.T = std::max(f.T_r, span);
+  const int M = std::max(20 * N.n_range, 2);
+  const int panels = std::max(256, 4 * M);
+  std::vector<double> gx, gw;
+  gauss_legendre(16, &gx, &gw);
+  std::vector<double> t, fw;
+  t.reserve((size_t)panels * 16);
+  fw.reserve((size_t)panels * 16);
+  const double h = 2.0 * f.T / panels;
+  for (int p = 0; p < panels; ++p) {
+    const double lo = -f.T + p * h;
+    for (int i = 0; i < 16; ++i) {
+      const double tt = lo + 0.5 * h * (gx[i] + 1.0);
+      t.push_back(tt);
+      fw.push_back(0.5 * h * gw[i] * std::exp(-tt * tt / (2.0 * sigma_r * sigma_r)));
+    }
+  }
+  std::vector<double> a(M);
+  for (int j = 0; j < M; ++j) {
+    double s = 0.0;
+    const double w = kPi * j / f.T;
+    for (size_t i = 0; i < t.size(); ++i) s += std::cos(w * t[i]) * fw[i];
+    a[j] = (j == 0 ? 0.5 : 1.0) * s / f.T;
+  }
+  double amax = 0;
+  for (double v : a) amax = std::max(amax, std::fabs(v));
+  std::vector<double> q(M);
+  for (int j = 0; j < M; ++j) q[j] = amax > 0 ? std::nearbyint(std::fabs(a[j]) / (1e-13 * amax)) : 0;
+  std::vector<int> order(M);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (q[x] != q[y]) return q[x] > q[y];
+    return x < y;
+  });
+  std::vector<int> sel(order.begin(), order.begin() + N.n_range);
+  std::sort(sel.begin(), sel.end());
+  for (int kk : sel) {
+    f.k.push_back(kk);
+    f.a.push_back(a[kk]);
+    f.omega.push_back(kPi * kk / f.T);
+  }
+  *out = std::move(f);
+  return BF_OK;
+}
+
+}  // namespace bf

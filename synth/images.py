@@ -18,10 +18,11 @@ def _gradient_noise(H, W, cell, rng):
     x0 = np.floor(xs).astype(np.int64)
     fx = xs - x0
     ux = _fade(fx)
-    # row by row keeps memory at O(W) temporaries for 4096-wide images
-    for y in range(H):
-        ys = y / cell
-        y0 = int(np.floor(ys))
+    # blocks of rows keep temporaries at O(block * W) for 4096-wide images
+    for ya in range(0, H, 256):
+        yb = min(H, ya + 256)
+        ys = np.arange(ya, yb, dtype=np.float64)[:, None] / cell
+        y0 = np.floor(ys).astype(np.int64)
         fy = ys - y0
         uy = _fade(fy)
         g00 = gy[y0, x0] * fy + gx[y0, x0] * fx
@@ -30,7 +31,7 @@ def _gradient_noise(H, W, cell, rng):
         g11 = gy[y0 + 1, x0 + 1] * (fy - 1.0) + gx[y0 + 1, x0 + 1] * (fx - 1.0)
         top = g00 + ux * (g01 - g00)
         bot = g10 + ux * (g11 - g10)
-        out[y] = top + uy * (bot - top)
+        out[ya:yb] = top + uy * (bot - top)
     return out
 
 
@@ -47,13 +48,31 @@ def gen_image(H, W, edges, noise_sd, seed):
         field += (0.5 ** o) * _gradient_noise(H, W, cell, rng)
     lo, hi = field.min(), field.max()
     field = (field - lo) / (hi - lo if hi > lo else 1.0)
-    yy = np.arange(H, dtype=np.float64)[:, None]
-    xx = np.arange(W, dtype=np.float64)[None, :]
+    # step edges: pixel (y, x) gets delta where (x - px) cos(th) + (y - py) sin(th) > 0;
+    # per row that is a half-line in x, accumulated in a difference array
+    diff = np.zeros((H, W + 1), dtype=np.float64)
+    yv = np.arange(H, dtype=np.float64)
+    rows = np.arange(H)
     for _ in range(int(edges)):
         py, px = rng.uniform(0, H), rng.uniform(0, W)
         th = rng.uniform(0.0, np.pi)
         d = rng.uniform(-0.2, 0.2)
-        field += d * (((xx - px) * np.cos(th) + (yy - py) * np.sin(th)) > 0)
+        cx, sy = np.cos(th), np.sin(th)
+        if abs(cx) < 1e-12:
+            on = (yv - py) * sy > 0
+            diff[on, 0] += d
+            diff[on, W] -= d
+            continue
+        thr = px - (yv - py) * sy / cx  # boundary x on each row
+        if cx > 0:  # x > thr
+            start = np.clip(np.floor(thr).astype(np.int64) + 1, 0, W)
+            np.add.at(diff, (rows, start), d)
+            diff[:, W] -= d
+        else:       # x < thr
+            stop = np.clip(np.ceil(thr).astype(np.int64), 0, W)
+            diff[:, 0] += d
+            np.add.at(diff, (rows, stop), -d)
+    field += np.cumsum(diff, axis=1)[:, :W]
     lo, hi = field.min(), field.max()
     field = 0.1 + 0.8 * (field - lo) / (hi - lo if hi > lo else 1.0)
     field += rng.normal(0.0, noise_sd, size=(H, W))

@@ -1,0 +1,200 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance: max-abs 1e-4 on [0, 1] intensities against the expanded form
+(oracle T3 on whole images, T2 on sampled pixels at 4096^2).  The plain path
+keeps exact int32 tables and FP64 tap sums, so its error is far below that;
+the tests also assert a tighter 5e-5 to catch regressions early.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.images import CONFIGS
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+TIGHT = 5e-5
+
+
+@pytest.fixture(scope="module")
+def torch_dev(gpu):
+    import torch
+    return torch
+
+
+def _bf():
+    from paper_1803_00004_amd import bf
+    return bf
+
+
+def _run(torch, plan, I, **kw):
+    bf = _bf()
+    dev = torch.from_numpy(np.ascontiguousarray(I)).cuda()
+    out = bf.filter(plan, dev, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def _plans(ss, r, ns, sr, nr, dtype="f32", tile=0):
+    bf = _bf()
+    return bf.Plan(ss, sr, r, nr, ns, dtype=dtype, tile=tile), oracle.make_plan(ss, r, ns, sr, nr)
+
+
+def _report(name, err):
+    print("[parity] %s max-abs %.3e" % (name, err), flush=True)
+
+
+def test_cfg1_full_image(torch_dev):
+    c = CONFIGS["cfg1_256"]
+    I = synth.config_image("cfg1_256")
+    gp, op = _plans(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"])
+    out = _run(torch_dev, gp, I)
+    ref = oracle.expanded_box(I, op)
+    err = np.abs(out - ref).max()
+    _report("cfg1 256^2 vs T3", err)
+    true_err = np.abs(out - oracle.true_bf(I, c["sigma_s"], c["radius"], c["sigma_r"])).max()
+    _report("cfg1 256^2 vs true BF (reported)", true_err)
+    assert err <= TIGHT
+
+
+@pytest.mark.parametrize("H,W,tile,ss,r,ns,sr,nr", [
+    (300, 700, 128, 3.0, 9, 4, 0.1, 8),     # several tiles, ragged tails
+    (197, 263, 64, 4.0, 12, 6, 0.2, 8),     # ragged, tile smaller than 2r+1 halo
+    (130, 129, 64, 2.0, 6, 4, 0.3, 8),
+    (7, 13, 0, 3.0, 9, 4, 0.1, 8),          # image smaller than the window
+    (1, 1, 0, 3.0, 9, 4, 0.1, 8),
+    (1, 77, 0, 2.0, 6, 4, 0.1, 8),
+    (77, 1, 0, 2.0, 6, 4, 0.1, 8),
+    (64, 64, 0, 3.0, 10, 3, 0.1, 5),        # odd N_s: asymmetric-free but 3 groups
+    (96, 80, 64, 2.0, 6, 9, 0.05, 32),      # many groups / terms
+])
+def test_shapes_vs_oracle(torch_dev, H, W, tile, ss, r, ns, sr, nr):
+    I = synth.gen_image(H, W, 5, 0.03, H * 1000 + W)
+    gp, op = _plans(ss, r, ns, sr, nr, tile=tile)
+    out = _run(torch_dev, gp, I)
+    ref = oracle.expanded_box(I, op)
+    err = np.abs(out - ref).max()
+    _report("%dx%d tile %d r %d" % (H, W, gp.info.tile, r), err)
+    assert err <= TIGHT
+
+
+def test_u8_input(torch_dev):
+    Iu = synth.gen_image_u8(200, 300, 8, 0.03, 9)
+    gp, op = _plans(3.0, 9, 4, 0.1, 8, dtype="u8", tile=128)
+    out = _run(torch_dev, gp, Iu)
+    ref = oracle.expanded_box(Iu, op)
+    err = np.abs(out - ref).max()
+    _report("u8 200x300", err)
+    assert err <= TIGHT
+
+
+def test_numerator_denominator(torch_dev):
+    import torch
+    bf = _bf()
+    I = synth.gen_image(150, 170, 5, 0.03, 3)
+    gp, op = _plans(4.0, 12, 6, 0.1, 16, tile=64)
+    dev = torch.from_numpy(I).cuda()
+    num = torch.empty_like(dev)
+    den = torch.empty_like(dev)
+    out = bf.filter(gp, dev, num=num, den=den)
+    torch.cuda.synchronize()
+    o3, n3, d3 = oracle.expanded_box(I, op, return_parts=True)
+    assert np.abs(den.cpu().numpy() - d3).max() <= 1e-6 * np.abs(d3).max()
+    assert np.abs(num.cpu().numpy() - n3).max() <= 1e-6 * np.abs(d3).max()
+    assert np.abs(out.cpu().numpy() - o3).max() <= TIGHT
+
+
+def test_constant_image(torch_dev):
+    I = np.full((90, 110), 0.37, dtype=np.float32)
+    gp, _ = _plans(3.0, 9, 4, 0.1, 8, tile=64)
+    out = _run(torch_dev, gp, I)
+    assert np.abs(out - 0.37).max() <= 1e-6
+
+
+def test_sigma_r_infinity_is_spatial_filter(torch_dev):
+    from scipy import signal
+    I = synth.gen_image(120, 90, 4, 0.02, 5)
+    gp, op = _plans(3.0, 9, 4, 1e6, 4, tile=64)
+    out = _run(torch_dev, gp, I)
+    K = op.Ks[::-1, ::-1]
+    Id = I.astype(np.float64)
+    ref = signal.correlate2d(Id, K, mode="same") / signal.correlate2d(np.ones_like(Id), K, mode="same")
+    assert np.abs(out - ref).max() <= TIGHT
+
+
+def test_determinism_and_batch_equals_single(torch_dev):
+    import torch
+    bf = _bf()
+    specs = [(3.0, 9, 4, 0.1, 8, 140, 210), (4.0, 12, 4, 0.2, 8, 300, 90), (2.0, 6, 4, 0.05, 32, 64, 64)]
+    plans, imgs, singles = [], [], []
+    for ss, r, ns, sr, nr, H, W in specs:
+        p = bf.Plan(ss, sr, r, nr, ns)
+        I = torch.from_numpy(synth.gen_image(H, W, 4, 0.03, H + W)).cuda()
+        a = bf.filter(p, I)
+        b = bf.filter(p, I)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        plans.append(p)
+        imgs.append(I)
+        singles.append(a.clone())
+    outs = bf.filter_batch(plans, imgs)
+    torch.cuda.synchronize()
+    for o, s in zip(outs, singles):
+        assert torch.equal(o, s)
+
+
+def test_cfg2_full_image(torch_dev):
+    c = CONFIGS["cfg2_1080p"]
+    I = synth.config_image("cfg2_1080p")
+    gp, op = _plans(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"])
+    out = _run(torch_dev, gp, I)
+    ref = oracle.expanded_box(I, op)
+    err = np.abs(out - ref).max()
+    _report("cfg2 1920x1080 vs T3", err)
+    assert err <= TIGHT
+
+
+def _sample_pixels(H, W, n, seed):
+    rng = np.random.default_rng(seed)
+    ys = rng.integers(0, H, n)
+    xs = rng.integers(0, W, n)
+    edge_y = [0, 0, H - 1, H - 1, 1, H - 2, H // 2, 48, H - 49, 511, 512]
+    edge_x = [0, W - 1, 0, W - 1, W // 2, 1, W - 1, 47, 512, W - 2, 513]
+    return np.concatenate([ys, edge_y]).astype(np.int32), np.concatenate([xs, edge_x]).astype(np.int32)
+
+
+@pytest.mark.parametrize("name", ["cfg3_4096", "cfg5_4096_u8"])
+def test_4096_sampled(torch_dev, name):
+    c = CONFIGS[name]
+    I = synth.config_image(name)
+    gp, op = _plans(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"], dtype=c["dtype"])
+    out = _run(torch_dev, gp, I)
+    ys, xs = _sample_pixels(4096, 4096, 1500, 7)
+    ref = oracle.expanded_brute(I, op, ys, xs)
+    err = np.abs(out[ys, xs] - ref).max()
+    _report("%s sampled vs T2" % name, err)
+    assert np.isfinite(out).all()
+    assert out.min() >= -1e-3 and out.max() <= 1.0 + 1e-3
+    assert err <= TIGHT
+
+
+def test_argument_errors_on_device(torch_dev):
+    import ctypes
+    import torch
+    bf = _bf()
+    p = bf.Plan(3.0, 0.1, 9, 8, 4)
+    I = torch.rand(64, 64, device="cuda")
+    out = torch.empty_like(I)
+    need = p.workspace_size(64, 64)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    L = bf.lib()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert L.bf_filter_ws(p.handle, ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                          64, 64, ctypes.c_void_p(ws.data_ptr()), need - 1, s) == bf.BF_ERR_INVALID_ARG
+    assert L.bf_filter(p.handle, ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(I.data_ptr() + 64),
+                       64, 64, s) == bf.BF_ERR_INVALID_ARG
+    assert L.bf_filter_ws(p.handle, ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                          64, 64, ctypes.c_void_p(ws.data_ptr()), need, s) == bf.BF_OK
+    torch.cuda.synchronize()

@@ -1,0 +1,135 @@
+"""Host-side tests of the library (no GPU): symbols, plan tables against the
+oracle's independently computed tables, the tap convention, argument checks."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1803_00004_amd import bf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CONFIGS = [(3.0, 9, 4, 0.1, 8), (8.0, 24, 6, 0.1, 16), (16.0, 48, 8, 0.05, 32),
+           (2.0, 6, 4, 0.3, 8), (4.0, 12, 4, 0.2, 8), (3.0, 10, 3, 0.1, 5), (2.0, 6, 9, 0.05, 32)]
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "bf.h")).read()
+    declared = set(re.findall(r"^\s*(?:bf_status_t|const char \*)\s*(bf_\w+)\s*\(", hdr, re.M))
+    assert {"bf_plan_create", "bf_filter", "bf_filter_batch"} <= declared
+    L = bf.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared <= set(bf.EXPORTED)
+    assert bf.lib().bf_version().decode().startswith("bf-mi355x")
+
+
+@pytest.mark.parametrize("ss,r,ns,sr,nr", CONFIGS)
+def test_plan_tables_match_oracle(ss, r, ns, sr, nr):
+    p = bf.Plan(ss, sr, r, nr, ns, host_only=True)
+    o = oracle.make_plan(ss, r, ns, sr, nr)
+    assert p.spatial_groups() == o.spatial.selected
+    assert np.abs(p.spatial_kernel() - o.Ks).max() <= 1e-13
+    k, a, w = p.range_terms()
+    assert k.tolist() == o.range.k.tolist()
+    assert np.abs(a - o.a).max() <= 1e-13
+    assert np.abs(w - o.omega).max() <= 1e-13
+    info = p.info
+    assert info.n_images == sum(1 if kk == 0 else 4 for kk in k)
+    assert abs(info.T - o.range.T) < 1e-15 and abs(info.T_s - (r + 0.5)) < 1e-15
+    assert abs(info.den_floor - o.den_floor) <= 1e-12 * o.den_floor
+
+
+def test_config_tap_counts():
+    """Tap counts of the three workloads' spatial expansions: 16 / 32 / 48."""
+    for (ss, r, ns), P in zip([(3.0, 9, 4), (8.0, 24, 6), (16.0, 48, 8)], [16, 32, 48]):
+        assert bf.Plan(ss, 0.1, r, 8, ns, host_only=True).info.n_taps == P
+
+
+def _excl_sat(g):
+    H, W = g.shape
+    S = np.zeros((H + 1, W + 1))
+    S[1:, 1:] = np.cumsum(np.cumsum(g, axis=0), axis=1)
+    return S
+
+
+@pytest.mark.parametrize("ss,r,ns,sr,nr", CONFIGS[:5])
+def test_taps_reproduce_oracle_correlation(ss, r, ns, sr, nr):
+    """corr(p) = sum_i w_i S(clamp(p + d_i)) over the plan's taps equals the
+    oracle's rectangle correlation, with a global table and with the
+    tile-relative tables the kernels build (origin max(y0 - r, 0))."""
+    p = bf.Plan(ss, sr, r, nr, ns, host_only=True)
+    o = oracle.make_plan(ss, r, ns, sr, nr)
+    dy, dx, w = p.taps()
+    assert dy.min() >= -r and dy.max() <= r + 1 and dx.min() >= -r and dx.max() <= r + 1
+    H, W = 70, 83
+    g = synth.gen_image(H, W, 4, 0.05, 17).astype(np.float64) - 0.3
+    ref = oracle.correlate_rects(g, o.rects)
+    S = _excl_sat(g)
+    ys, xs = np.mgrid[0:H, 0:W]
+    corr = np.zeros((H, W))
+    for a, b, c in zip(dy, dx, w):
+        corr += c * S[np.clip(ys + a, 0, H), np.clip(xs + b, 0, W)]
+    assert np.abs(corr - ref).max() < 1e-10
+    tile = 32
+    for ty in range(0, H, tile):
+        for tx in range(0, W, tile):
+            y1, x1 = min(H, ty + tile), min(W, tx + tile)
+            oy, ox = max(ty - r, 0), max(tx - r, 0)
+            ye, xe = min(y1 + r, H), min(x1 + r, W)
+            St = _excl_sat(g[oy:ye, ox:xe])
+            yy, xx = np.mgrid[ty:y1, tx:x1]
+            c2 = np.zeros(yy.shape)
+            for a, b, c in zip(dy, dx, w):
+                c2 += c * St[np.clip(yy + a, 0, H) - oy, np.clip(xx + b, 0, W) - ox]
+            assert np.abs(c2 - ref[ty:y1, tx:x1]).max() < 1e-10
+
+
+def test_sat_shift_bounds_tables():
+    """q keeps every tile table inside int32: (tile + 2r)^2 2^q <= 2^31 - 1."""
+    for ss, r, ns, sr, nr in CONFIGS:
+        for tile in (0, 128, 512):
+            info = bf.Plan(ss, sr, r, nr, ns, tile=tile, host_only=True).info
+            E = info.tile + 2 * r
+            assert E * E * 2.0 ** info.sat_shift <= 2 ** 31 - 1
+            assert E * E * 2.0 ** (info.sat_shift + 1) > 2 ** 31 - 1 or info.sat_shift == 24
+
+
+@pytest.mark.parametrize("kw", [dict(sigma_s=0.0, sigma_r=0.1), dict(sigma_s=3.0, sigma_r=-1.0),
+                                dict(sigma_s=float("nan"), sigma_r=0.1),
+                                dict(sigma_s=3.0, sigma_r=0.1, n_range=0),
+                                dict(sigma_s=3.0, sigma_r=0.1, n_range=65),
+                                dict(sigma_s=3.0, sigma_r=0.1, n_spatial=0),
+                                dict(sigma_s=3.0, sigma_r=0.1, radius=9, n_spatial=26),
+                                dict(sigma_s=3.0, sigma_r=0.1, radius=-1),
+                                dict(sigma_s=3.0, sigma_r=0.1, tile=100)])
+def test_invalid_plan_arguments(kw):
+    kw.setdefault("radius", 9)
+    with pytest.raises(bf.BFError) as e:
+        bf.Plan(host_only=True, **kw)
+    assert e.value.status == bf.BF_ERR_INVALID_ARG
+
+
+def test_default_radius_and_unsupported():
+    p = bf.Plan(3.0, 0.1, 0, 8, 4, host_only=True)
+    assert p.info.radius == int(np.ceil(3.0 * np.sqrt(2 * np.log(100))))
+    h = ctypes.c_void_p()
+    st = bf.lib().bf_plan_create(ctypes.byref(h), 1, 0, 3.0, 0.1, 9, bf._Terms(8, 4), None)
+    assert st == bf.BF_ERR_UNSUPPORTED
+
+
+def test_filter_rejects_bad_calls_without_touching_the_device():
+    p = bf.Plan(3.0, 0.1, 9, 8, 4, host_only=True)
+    L = bf.lib()
+    buf_in, buf_out = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x90000)
+    assert L.bf_filter(p.handle, buf_in, buf_out, 16, 16, None) == bf.BF_ERR_INVALID_ARG  # host-only plan
+    assert L.bf_filter(None, buf_in, buf_out, 16, 16, None) == bf.BF_ERR_INVALID_ARG
+    assert L.bf_workspace_size(p.handle, 0, 5, ctypes.byref(ctypes.c_size_t())) == bf.BF_ERR_INVALID_ARG
+    assert L.bf_workspace_size(p.handle, 40000, 5, ctypes.byref(ctypes.c_size_t())) == bf.BF_ERR_INVALID_ARG
+    n = ctypes.c_size_t()
+    assert L.bf_workspace_size(p.handle, 1080, 1920, ctypes.byref(n)) == bf.BF_OK and n.value > 0
+    assert L.bf_plan_destroy(None) == bf.BF_OK
+    assert bf.status_string(bf.BF_ERR_DEVICE) == "BF_ERR_DEVICE"
