@@ -59,6 +59,9 @@ def main():
     ap.add_argument("--workload", default="cfg2_1080p",
                     choices=["cfg1_256", "cfg2_1080p", "cfg3_4096", "cfg5_4096_u8"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (no error check)")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="also run one device copy of MIB MiB (a reference kernel of known "
+                         "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the filter has no multi-GPU path in this build "
@@ -92,6 +95,15 @@ def main():
     for _ in range(args.warmup):
         bf.filter(plan, I, out=out, ws=ws, stream=stream)
     torch.cuda.synchronize()
+    if args.calib_copy > 0:
+        n = args.calib_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: %d MiB read + %d MiB written" % (args.calib_copy, args.calib_copy))
+        del a, b
 
     bf.profile_enable(True)
     bf.profile_read()
