@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "bf.h"
 #include "bf_internal.h"
@@ -64,7 +65,7 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   const double eps = o.eps == 0.0 ? 0.01 : o.eps;
   const double span = o.span == 0.0 ? 1.0 : o.span;
   if (!(span > 0) || !std::isfinite(span) || radius < 0) return BF_ERR_INVALID_ARG;
-  if (o.tile != 0 && (o.tile < 64 || o.tile > 2048 || o.tile % 64 != 0)) return BF_ERR_INVALID_ARG;
+  if (o.tile != 0 && (o.tile < 64 || o.tile > 1024 || o.tile % 64 != 0)) return BF_ERR_INVALID_ARG;
 
   bf_plan_s *p = new (std::nothrow) bf_plan_s();
   if (!p) return BF_ERR_OUT_OF_MEMORY;
@@ -82,6 +83,10 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   p->precision = o.precision;
   p->flags = o.flags;
   p->tile = o.tile ? o.tile : choose_tile(f.radius);
+  if (p->tile + 2 * f.radius + 1 > 256 * bf::kMaxChunks) {  // one table row must fit 8 chunks
+    delete p;
+    return BF_ERR_UNSUPPORTED;
+  }
   const double gmax = o.in_dtype == BF_IN_U8 ? 1.0 : std::max(1.0, span);
   p->sat_shift = choose_shift(p->tile, f.radius, gmax);
 
@@ -123,6 +128,45 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   }
   for (int i = 0; i < t.n_taps4; ++i)
     t.tap_boff[i] = 4 * (t.tap_dy[i] * t.pitch + t.tap_dx[i] - t.tap_d_min);
+  // quadruplets for the LDS tile kernel: region of 64 + (dx_max - dx_min) columns
+  t.lds_pitch = bf::lds_pitch_for(64 + t.tap_dx_max - t.tap_dx_min);
+  {
+    auto weight_at = [&](int dy, int dx, double *w) {
+      for (int i = 0; i < nt; ++i)
+        if (f.tap_dy[i] == dy && f.tap_dx[i] == dx) {
+          *w = f.tap_w[i];
+          return true;
+        }
+      return false;
+    };
+    auto loff = [&](int dy, int dx) { return (dy - t.tap_dy_min) * t.lds_pitch + (dx - t.tap_dx_min); };
+    std::vector<char> used(nt, 0);
+    for (int i = 0; i < nt; ++i) {
+      const int dy = f.tap_dy[i], dx = f.tap_dx[i];
+      if (used[i] || dy < 1 || dx < 1) continue;  // representative has dy >= 1, dx >= 1
+      double wb, wc, wd;
+      const double wa = f.tap_w[i];
+      if (weight_at(1 - dy, dx, &wb) && weight_at(dy, 1 - dx, &wc) && weight_at(1 - dy, 1 - dx, &wd) &&
+          wb == -wa && wc == -wa && wd == wa) {
+        const int q = t.n_quads++;
+        t.quad_off[q][0] = loff(dy, dx);
+        t.quad_off[q][1] = loff(1 - dy, dx);
+        t.quad_off[q][2] = loff(dy, 1 - dx);
+        t.quad_off[q][3] = loff(1 - dy, 1 - dx);
+        t.quad_w[q] = wa;
+        for (int j = 0; j < nt; ++j) {
+          const int ey = f.tap_dy[j], ex = f.tap_dx[j];
+          if ((ey == dy || ey == 1 - dy) && (ex == dx || ex == 1 - dx)) used[j] = 1;
+        }
+      }
+    }
+    for (int i = 0; i < nt; ++i)
+      if (!used[i]) {
+        t.single_off[t.n_single] = loff(f.tap_dy[i], f.tap_dx[i]);
+        t.single_w[t.n_single] = f.tap_w[i];
+        ++t.n_single;
+      }
+  }
   int slot = 0;
   for (int i = 0; i < t.n_terms; ++i) {
     double fk = f.k[i] / (2.0 * f.T);
@@ -132,7 +176,12 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
     t.a[i] = f.a[i];
     t.k_is_zero[i] = f.k[i] == 0;
     t.slot[i] = slot;
-    slot += f.k[i] == 0 ? 1 : 4;
+    const int nparts = f.k[i] == 0 ? 1 : 4;
+    for (int q = 0; q < nparts; ++q) {
+      t.slot_term[slot + q] = i;
+      t.slot_part[slot + q] = f.k[i] == 0 ? 4 : q;
+    }
+    slot += nparts;
   }
   t.n_images = slot;
   t.sat_scale = std::ldexp(1.0f, p->sat_shift);

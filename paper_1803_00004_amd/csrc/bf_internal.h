@@ -13,6 +13,8 @@ namespace bf {
 constexpr int kMaxTerms = 64;      // cosine terms per plan
 constexpr int kMaxTapAxis = 16;    // distinct tap offsets per axis (Haar levels <= 3)
 constexpr int kMaxTaps = 256;      // nonzero summed-area-table taps (padded to a multiple of 4)
+constexpr int kMaxImages = 4 * kMaxTerms;  // term images (tables) per filter call
+constexpr int kMaxChunks = 8;      // 256-column chunks of one table row (table width <= 2048)
 constexpr int kKA_Threads = 256;   // summed-area-table kernel block size (upper bound)
 
 // Host-side result of the FP64 fit (Sec. IV, App. A/B).
@@ -53,10 +55,24 @@ struct DevTables {
   int tap_boff[kMaxTaps];
   int tap_d_min;                       // min over taps of dy * pitch + dx
   int pitch;                           // table row pitch (elements) for this plan
+  // Taps grouped for the LDS tile kernel.  A symmetric kernel has taps
+  // (dy, dx), (1-dy, dx), (dy, 1-dx), (1-dy, 1-dx) with weights w, -w, -w, w:
+  // one box sum of the table, differenced exactly in int32, times w.
+  // lds_off[] are element offsets into the staged region of row pitch
+  // lds_pitch: corner a = (dy, dx), b = (1-dy, dx), c = (dy, 1-dx), d = (1-dy, 1-dx).
+  int lds_pitch;                       // 0: no LDS tile kernel for this plan
+  int n_quads;
+  int quad_off[kMaxTaps / 4][4];
+  double quad_w[kMaxTaps / 4];
+  int n_single;                        // taps without a symmetric quadruplet
+  int single_off[kMaxTaps];
+  double single_w[kMaxTaps];
   float f_hi[kMaxTerms], f_lo[kMaxTerms];  // f_k = k / (2T) (u8: k / (2T 255)) as two floats
   double a[kMaxTerms];                 // a_k
   int k_is_zero[kMaxTerms];            // term k = 0: one image (I), analytic denominator
   int slot[kMaxTerms];                 // first table of the term
+  // table -> (term, part); part 0: C*I, 1: S*I, 2: C, 3: S, 4: I (k = 0)
+  int slot_term[kMaxImages], slot_part[kMaxImages];
   float sat_scale;                     // 2^q
   double inv_sat_scale;                // 2^-q
   float gmax;                          // |term value| clamp
@@ -76,6 +92,10 @@ struct Geometry {
 };
 
 Geometry make_geometry(int H, int W, int tile, int radius, int n_images);
+
+// Row pitch (int32 elements) of the LDS tile kernel's staged table region for
+// a region `width` columns wide: one of the compiled pitches, or 0 if none fits.
+int lds_pitch_for(int width);
 
 // Launch the two kernels of one image on `stream` (hipStream_t): `dev` is
 // the device copy of `host`.

@@ -59,104 +59,123 @@ __device__ __forceinline__ int quantize(float v, float gmax, float scale) {
   return __float2int_rn(v * scale);
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave.
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: partial
+// sums within each 16-lane row (row_shr 1, 2, 3, then 4 and 8 on the upper
+// banks), then the row totals carried by row_bcast:15 and row_bcast:31.
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int u = __shfl_up(v, d, 64);
-    if (lane >= d) v += u;
-  }
-  return v;
+  int x = v;
+  x += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, v, 0x113, 0xf, 0xf, true);   // row_shr:3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xe, false);  // row_shr:4, lanes 4..15 of a row
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xc, false);  // row_shr:8, lanes 8..15 of a row
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+  return x;
 }
 
 // ---------------------------------------------------------------------------
-// K-A: tile-relative int32 summed-area tables of the term images of one k.
-// Block: one tile x one term; thread t owns table columns [t*CPT, t*CPT+CPT).
+// K-A: tile-relative int32 summed-area table of one term image per wave.
+// Lane l owns the 4-column groups [4l + 256g, 4l + 256g + 4), g < G, so each
+// int4 store of a row writes 1 KB of contiguous memory; the row prefix is an
+// in-lane prefix plus one DPP wave scan per 256-column chunk, the column
+// accumulation lives in registers, and the image rows are prefetched PF rows
+// ahead.  No barriers: waves are independent.
 // ---------------------------------------------------------------------------
-template <int CPT, bool U8>
-__global__ __launch_bounds__(512) void ka_sat(const void *__restrict__ I, ImageParams p,
+constexpr int kPF = 4;
+
+template <int G, bool U8>
+__global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageParams p,
                                              const DevTables *__restrict__ tab,
                                              int32_t *__restrict__ ws) {
-  __shared__ int wave_tot[2][8][4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = blockIdx.y * 4 + wave;
+  if (slot >= p.n_images) return;
   const int tile_id = blockIdx.x;
-  const int term = blockIdx.y;
   const int ty = tile_id / p.tiles_x, tx = tile_id - ty * p.tiles_x;
   const int y0 = ty * p.tile, x0 = tx * p.tile;
   const int y1 = min(p.H, y0 + p.tile), x1 = min(p.W, x0 + p.tile);
   const int oy = max(y0 - p.radius, 0), ox = max(x0 - p.radius, 0);
   const int Eh = min(y1 + p.radius, p.H) - oy + 1;
   const int Ew = min(x1 + p.radius, p.W) - ox + 1;
-  const bool k0 = tab->k_is_zero[term] != 0;
-  const int nimg = k0 ? 1 : 4;
-  int32_t *base = ws + ((long long)tile_id * p.n_images + tab->slot[term]) * p.table_elems;
+  const int term = tab->slot_term[slot], part = tab->slot_part[slot];
   const float f_hi = tab->f_hi[term], f_lo = tab->f_lo[term];
   const float gmax = tab->gmax, scale = tab->sat_scale;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nwaves = blockDim.x >> 6;
-  const int c0 = threadIdx.x * CPT;
+  int32_t *base = ws + ((long long)tile_id * p.n_images + slot) * p.table_elems;
 
-  int acc[4][CPT];
+  // raw pixel values (u8 as integer-valued float) of the rows i .. i + kPF - 1
+  float pf[kPF][G][4];
+  auto load_row = [&](int i, float (&dst)[G][4]) {
+    const long long row = (long long)(oy + i - 1) * p.W;
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+    for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) acc[m][c] = 0;
+      for (int c = 0; c < 4; ++c) {
+        const int j = 4 * lane + 256 * g + c;
+        float v = 0.0f;
+        if (i < Eh && j >= 1 && j < Ew) {
+          const long long idx = row + (ox + j - 1);
+          v = U8 ? (float)static_cast<const uint8_t *>(I)[idx] : static_cast<const float *>(I)[idx];
+        }
+        dst[g][c] = v;
+      }
+  };
+#pragma unroll
+  for (int q = 0; q < kPF; ++q) load_row(1 + q, pf[q]);
 
-  // row 0 of every table is zero
-  for (int m = 0; m < nimg; ++m)
+  int acc[G][4];
 #pragma unroll
-    for (int c = 0; c < CPT; ++c)
-      if (c0 + c < Ew) base[(long long)m * p.table_elems + c0 + c] = 0;
+  for (int g = 0; g < G; ++g) {
+    acc[g][0] = acc[g][1] = acc[g][2] = acc[g][3] = 0;
+    const int j0 = 4 * lane + 256 * g;
+    if (j0 < p.pitch) *reinterpret_cast<int4 *>(base + j0) = make_int4(0, 0, 0, 0);
+  }
 
   for (int i = 1; i < Eh; ++i) {
-    const int yy = oy + i - 1;
-    int v[4][CPT];
+    float cur[G][4];
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      const int j = c0 + c;
-      if (j >= 1 && j < Ew) {
-        float px, x;
-        load_pixel<U8>(I, (long long)yy * p.W + (ox + j - 1), &px, &x);
-        if (k0) {
-          v[0][c] = quantize(x, gmax, scale);
-          v[1][c] = v[2][c] = v[3][c] = 0;
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cur[g][c] = pf[0][g][c];
+#pragma unroll
+    for (int q = 0; q + 1 < kPF; ++q)
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pf[q][g][c] = pf[q + 1][g][c];
+    load_row(i + kPF, pf[kPF - 1]);
+
+    int carry = 0;
+    int32_t *row = base + (long long)i * p.pitch;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      int v[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float px = cur[g][c];
+        const float x = U8 ? px * (1.0f / 255.0f) : px;
+        float val;
+        if (part == 4) {
+          val = x;
         } else {
           const float fr = phase_rev(f_hi, f_lo, px);
-          const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
-          v[0][c] = quantize(C * x, gmax, scale);
-          v[1][c] = quantize(S * x, gmax, scale);
-          v[2][c] = quantize(C, gmax, scale);
-          v[3][c] = quantize(S, gmax, scale);
+          const float cs = (part & 1) ? __builtin_amdgcn_sinf(fr) : __builtin_amdgcn_cosf(fr);
+          val = (part < 2) ? cs * x : cs;
         }
-      } else {
-        v[0][c] = v[1][c] = v[2][c] = v[3][c] = 0;
+        // the zero padding column j = 0 and columns past the table read 0
+        v[c] = quantize(val, gmax, scale);
       }
-    }
-    // in-thread inclusive prefix, wave scan of thread totals, cross-wave carry
-    int tot[4];
+      v[1] += v[0];
+      v[2] += v[1];
+      v[3] += v[2];
+      const int incl = wave_inclusive_scan(v[3]);
+      const int excl = incl - v[3] + carry;
+      carry += __builtin_amdgcn_readlane(incl, 63);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-#pragma unroll
-      for (int c = 1; c < CPT; ++c) v[m][c] += v[m][c - 1];
-      const int incl = wave_inclusive_scan(v[m][CPT - 1]);
-      tot[m] = incl - v[m][CPT - 1];  // exclusive within the wave
-      if (lane == 63) wave_tot[i & 1][wave][m] = incl;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      int carry = 0;
-      for (int w = 0; w < wave; ++w) carry += wave_tot[i & 1][w][m];
-      tot[m] += carry;
-    }
-    (void)nwaves;
-    int32_t *row = base + (long long)i * p.pitch;
-    for (int m = 0; m < nimg; ++m) {
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        acc[m][c] += v[m][c] + tot[m];
-        if (c0 + c < Ew) row[(long long)m * p.table_elems + c0 + c] = acc[m][c];
-      }
+      for (int c = 0; c < 4; ++c) acc[g][c] += v[c] + excl;
+      const int j0 = 4 * lane + 256 * g;
+      if (j0 < p.pitch)
+        *reinterpret_cast<int4 *>(row + j0) = make_int4(acc[g][0], acc[g][1], acc[g][2], acc[g][3]);
     }
   }
 }
@@ -278,15 +297,204 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
 }
 
 // ---------------------------------------------------------------------------
+// K-B (LDS tile form): one block per 64 x 64 output tile; tables are the
+// outer loop.  For each table the block stages the region its taps read --
+// (64 + dy span) rows x (64 + dx span) columns, with the border clamp applied
+// while staging -- into LDS once, then every pixel reads its taps from LDS.
+// Symmetric quadruplets of taps are one box sum differenced exactly in int32
+// and one FP64 FMA.  The tile's numerators and denominators stay in
+// registers across all terms.  PITCH is the LDS row pitch, so the per-pixel
+// row offsets are instruction immediates.
+// ---------------------------------------------------------------------------
+template <int PITCH, int NT, int NQ, bool U8>
+__global__ __launch_bounds__(NT) void kb_tile(const void *__restrict__ I, ImageParams p,
+                                              const DevTables *__restrict__ tab,
+                                              const int32_t *__restrict__ ws,
+                                              float *__restrict__ out, float *__restrict__ num_out,
+                                              float *__restrict__ den_out) {
+  constexpr int NW = NT / 64;                 // waves
+  constexpr int PX = 64 / NW;                 // rows of the tile per thread
+  constexpr int CC = (PITCH + 63) / 64;       // 64-column chunks of a staged row
+  constexpr int RR = (PITCH + NW - 1) / NW;   // staged rows per wave (region rows <= PITCH)
+  extern __shared__ int lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // XCD-aware order: blocks are dispatched round-robin over the 8 XCDs, so
+  // XCD k (blockIdx % 8) takes the k-th contiguous eighth of the tiles, walked
+  // in patches of 8 x 4 tiles; the tiles one XCD runs at the same time are
+  // neighbours whose staged halos overlap in that XCD's L2.
+  const int ntx = (p.W + 63) / 64, nty = (p.H + 63) / 64;
+  const int n_tiles = ntx * nty;
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (L >= n_tiles) return;
+  // patch rows of PH tile rows (the last may be shorter); within one, patches
+  // of PW tile columns (the last may be narrower); tiles row-major in a patch
+  constexpr int PW = 8, PH = 4;
+  const int pr = L / (PH * ntx);
+  const int rem = L - pr * PH * ntx;
+  const int ph = min(PH, nty - pr * PH);
+  const int pc = rem / (PW * ph);
+  const int in = rem - pc * PW * ph;
+  const int pw = min(PW, ntx - pc * PW);
+  const int bx = pc * PW + in % pw, by = pr * PH + in / pw;
+  const int x0 = bx * 64, y0 = by * 64;
+  const int ty = y0 / p.tile, tx = x0 / p.tile;
+  const int tile_id = ty * p.tiles_x + tx;
+  const int oy = max(ty * p.tile - p.radius, 0), ox = max(tx * p.tile - p.radius, 0);
+  const int dy0 = tab->tap_dy_min, dx0 = tab->tap_dx_min;
+  const int RH = 64 + tab->tap_dy_max - dy0, RW = 64 + tab->tap_dx_max - dx0;
+  const uint32_t te4 = (uint32_t)p.table_elems * 4u;
+  const __amdgpu_buffer_rsrc_t rsrc =
+      make_rsrc(ws + (long long)tile_id * p.n_images * p.table_elems, te4 * (uint32_t)p.n_images);
+  const int x = x0 + lane;
+  const bool xin = x < p.W;
+
+  // staging geometry: wave w stages region rows w, w + NW, ...; lane l columns
+  // l, l + 64, ...  The row part of each table offset is wave-uniform and goes
+  // in the buffer load's scalar offset; the clamped column offset is fixed per
+  // lane, so staging needs no vector address arithmetic.
+  uint32_t xoff4[CC];
+#pragma unroll
+  for (int c = 0; c < CC; ++c) xoff4[c] = (uint32_t)(min(max(x0 + dx0 + lane + 64 * c, 0), p.W) - ox) * 4u;
+  auto stage_load = [&](int m, int (&pre)[RR][CC]) {
+    const uint32_t soff = (uint32_t)m * te4;
+#pragma unroll
+    for (int rr = 0; rr < RR; ++rr) {
+      const int r = wave + NW * rr;
+      const int Y = min(max(y0 + dy0 + r, 0), p.H) - oy;
+      const uint32_t srow = soff + (uint32_t)(Y * p.pitch) * 4u;
+#pragma unroll
+      for (int c = 0; c < CC; ++c) {
+        pre[rr][c] = 0;
+        if (r < RH && lane + 64 * c < RW) pre[rr][c] = load_i32(rsrc, xoff4[c], srow);
+      }
+    }
+  };
+
+  float pxv[PX];
+  double num[PX], den[PX];
+#pragma unroll
+  for (int i = 0; i < PX; ++i) {
+    const int y = y0 + wave + NW * i;
+    pxv[i] = 0.0f;
+    if (xin && y < p.H) {
+      float px, v;
+      load_pixel<U8>(I, (long long)y * p.W + x, &px, &v);
+      pxv[i] = px;
+    }
+    num[i] = 0.0;
+    den[i] = 0.0;
+  }
+  const double inv = tab->inv_sat_scale;
+  // LDS element offset of this thread's first pixel: region row r holds image
+  // row y0 + dy0 + r, so tap (dy, dx) of the pixel in tile row yl, column lane
+  // is at (yl + dy - dy0) * PITCH + lane + dx - dx0 = yl * PITCH + lane + off(dy, dx)
+  const int lbase = wave * PITCH + lane;
+
+  int pre[RR][CC];
+  stage_load(0, pre);
+  float cs[PX], sn[PX];
+  for (int m = 0; m < p.n_images; ++m) {
+    const int t = tab->slot_term[m], part = tab->slot_part[m];
+    __syncthreads();  // every thread is done reading the previous table
+#pragma unroll
+    for (int rr = 0; rr < RR; ++rr)
+#pragma unroll
+      for (int c = 0; c < CC; ++c) {
+        const int r = wave + NW * rr, col = lane + 64 * c;
+        if (r < RH && col < RW) lds[r * PITCH + col] = pre[rr][c];
+      }
+    __syncthreads();
+    if (m + 1 < p.n_images) stage_load(m + 1, pre);  // in flight while this table is read
+
+    if (part == 0) {
+#pragma unroll
+      for (int i = 0; i < PX; ++i) {
+        const float fr = phase_rev(tab->f_hi[t], tab->f_lo[t], pxv[i]);
+        cs[i] = __builtin_amdgcn_cosf(fr);
+        sn[i] = __builtin_amdgcn_sinf(fr);
+      }
+    }
+    double s[PX];
+#pragma unroll
+    for (int i = 0; i < PX; ++i) s[i] = 0.0;
+#pragma unroll 2
+    for (int q = 0; q < tab->n_quads; ++q) {
+      const int *qa = lds + lbase + tab->quad_off[q][0];
+      const int *qb = lds + lbase + tab->quad_off[q][1];
+      const int *qc = lds + lbase + tab->quad_off[q][2];
+      const int *qd = lds + lbase + tab->quad_off[q][3];
+      const double w = tab->quad_w[q];
+#pragma unroll
+      for (int i = 0; i < PX; ++i) {
+        const int o = NW * i * PITCH;
+        const int box = (qa[o] - qb[o]) - (qc[o] - qd[o]);
+        s[i] = __builtin_fma(w, (double)box, s[i]);
+      }
+    }
+    for (int q = 0; q < tab->n_single; ++q) {
+      const int *qa = lds + lbase + tab->single_off[q];
+      const double w = tab->single_w[q];
+#pragma unroll
+      for (int i = 0; i < PX; ++i) s[i] = __builtin_fma(w, (double)qa[NW * i * PITCH], s[i]);
+    }
+    const double ai = tab->a[t] * inv;
+#pragma unroll
+    for (int i = 0; i < PX; ++i) {
+      if (part == 4) {
+        num[i] = __builtin_fma(ai, s[i], num[i]);
+      } else if (part == 0) {
+        num[i] = __builtin_fma(ai * cs[i], s[i], num[i]);
+      } else if (part == 1) {
+        num[i] = __builtin_fma(ai * sn[i], s[i], num[i]);
+      } else if (part == 2) {
+        den[i] = __builtin_fma(ai * cs[i], s[i], den[i]);
+      } else {
+        den[i] = __builtin_fma(ai * sn[i], s[i], den[i]);
+      }
+    }
+    if (part == 4) {
+      // denominator of the k = 0 term: a_0 (K * 1) from the clamped corners
+      // (the table of ones is (Y - oy)(X - ox))
+#pragma unroll
+      for (int i = 0; i < PX; ++i) {
+        const int y = y0 + wave + NW * i;
+        double d0 = 0.0;
+        for (int q = 0; q < tab->n_taps4; ++q) {
+          const int Y = min(max(y + tab->tap_dy[q], 0), p.H) - oy;
+          const int X = min(max(x + tab->tap_dx[q], 0), p.W) - ox;
+          d0 = __builtin_fma(tab->tap_w[q], (double)(Y * X), d0);
+        }
+        den[i] = __builtin_fma(tab->a[t], d0, den[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PX; ++i) {
+    const int y = y0 + wave + NW * i;
+    if (!xin || y >= p.H) continue;
+    const long long idx = (long long)y * p.W + x;
+    const float xv = U8 ? pxv[i] * (1.0f / 255.0f) : pxv[i];
+    out[idx] = den[i] > tab->den_floor ? (float)(num[i] / den[i]) : xv;
+    if (num_out) num_out[idx] = (float)num[i];
+    if (den_out) den_out[idx] = (float)den[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 template <bool U8>
-static hipError_t launch_ka(int cpt, dim3 grid, dim3 block, hipStream_t s, const void *I,
+static hipError_t launch_ka(int G, dim3 grid, dim3 block, hipStream_t s, const void *I,
                             ImageParams p, const DevTables *tab, int32_t *ws) {
-  switch (cpt) {
+  switch (G) {
     case 1: hipLaunchKernelGGL((ka_sat<1, U8>), grid, block, 0, s, I, p, tab, ws); break;
     case 2: hipLaunchKernelGGL((ka_sat<2, U8>), grid, block, 0, s, I, p, tab, ws); break;
+    case 3: hipLaunchKernelGGL((ka_sat<3, U8>), grid, block, 0, s, I, p, tab, ws); break;
     case 4: hipLaunchKernelGGL((ka_sat<4, U8>), grid, block, 0, s, I, p, tab, ws); break;
+    case 5: hipLaunchKernelGGL((ka_sat<5, U8>), grid, block, 0, s, I, p, tab, ws); break;
+    case 6: hipLaunchKernelGGL((ka_sat<6, U8>), grid, block, 0, s, I, p, tab, ws); break;
+    case 7: hipLaunchKernelGGL((ka_sat<7, U8>), grid, block, 0, s, I, p, tab, ws); break;
     default: hipLaunchKernelGGL((ka_sat<8, U8>), grid, block, 0, s, I, p, tab, ws); break;
   }
   return hipGetLastError();
@@ -298,6 +506,48 @@ static hipError_t launch_kb(dim3 grid, dim3 block, hipStream_t s, const void *I,
                             float *den) {
   hipLaunchKernelGGL((kb_lookup<U8>), grid, block, 0, s, I, p, tab, ws, out, num, den);
   return hipGetLastError();
+}
+
+static const int kLdsPitches[] = {96, 128, 160, 176, 192};
+
+int lds_pitch_for(int width) {
+  for (int pch : kLdsPitches)
+    if (width <= pch) return pch;
+  return 0;
+}
+
+template <int PITCH, int NQ, bool U8>
+static hipError_t launch_kb_tile(dim3 grid, size_t lds, hipStream_t s, const void *I,
+                                 ImageParams p, const DevTables *tab, const int32_t *ws, float *out,
+                                 float *num, float *den) {
+  auto k = kb_tile<PITCH, 1024, NQ, U8>;
+  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, grid, dim3(1024), lds, s, I, p, tab, ws, out, num, den);
+  return hipGetLastError();
+}
+
+template <int PITCH, bool U8>
+static hipError_t launch_kb_tile_nq(int nq, dim3 grid, size_t lds, hipStream_t s, const void *I,
+                                    ImageParams p, const DevTables *tab, const int32_t *ws,
+                                    float *out, float *num, float *den) {
+  if (nq <= 4) return launch_kb_tile<PITCH, 4, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+  if (nq <= 8) return launch_kb_tile<PITCH, 8, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+  if (nq <= 12) return launch_kb_tile<PITCH, 12, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+  return launch_kb_tile<PITCH, 16, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+}
+
+template <bool U8>
+static hipError_t launch_kb_tile_any(int pitch, int nq, dim3 grid, size_t lds, hipStream_t s,
+                                     const void *I, ImageParams p, const DevTables *tab,
+                                     const int32_t *ws, float *out, float *num, float *den) {
+  switch (pitch) {
+    case 96: return launch_kb_tile_nq<96, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    case 128: return launch_kb_tile_nq<128, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    case 160: return launch_kb_tile_nq<160, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    case 176: return launch_kb_tile_nq<176, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    default: return launch_kb_tile_nq<192, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+  }
 }
 
 Geometry make_geometry(int H, int W, int tile, int radius, int n_images) {
@@ -331,21 +581,28 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
   p.n_terms = host.n_terms;
   p.table_elems = (long long)g.table_elems;
   const int Ew = std::min(g.tile + 2 * g.radius + 1, g.W + 1);
-  int cpt = 1;
-  while (cpt < 8 && (Ew + cpt - 1) / cpt > 512) cpt *= 2;
-  int threads = (Ew + cpt - 1) / cpt;
-  threads = (threads + 63) / 64 * 64;
-  if (threads > 512) return BF_ERR_UNSUPPORTED;
-  dim3 ga(g.tiles_y * g.tiles_x, host.n_terms), ba(threads);
+  const int G = (Ew + 255) / 256;
+  if (G > kMaxChunks) return BF_ERR_UNSUPPORTED;
+  dim3 ga(g.tiles_y * g.tiles_x, (host.n_images + 3) / 4), ba(256);
   profile_mark(0, 1, stream);
-  hipError_t e = host.in_u8 ? launch_ka<true>(cpt, ga, ba, s, I, p, dev, ws)
-                            : launch_ka<false>(cpt, ga, ba, s, I, p, dev, ws);
+  hipError_t e = host.in_u8 ? launch_ka<true>(G, ga, ba, s, I, p, dev, ws)
+                            : launch_ka<false>(G, ga, ba, s, I, p, dev, ws);
   profile_mark(0, 0, stream);
   if (e != hipSuccess) return BF_ERR_DEVICE;
-  dim3 gb((g.W + 63) / 64, (g.H + 3) / 4), bb(256);
+  // LDS tile kernel when the staged region fits, else the per-pixel kernel
+  const int RH = 64 + host.tap_dy_max - host.tap_dy_min;
+  const size_t lds = (size_t)RH * host.lds_pitch * sizeof(int32_t);
   profile_mark(1, 1, stream);
-  e = host.in_u8 ? launch_kb<true>(gb, bb, s, I, p, dev, ws, out, num, den)
-                 : launch_kb<false>(gb, bb, s, I, p, dev, ws, out, num, den);
+  if (host.lds_pitch > 0 && lds <= 160 * 1024 && host.n_quads <= 16) {
+    const int n_tiles = ((g.W + 63) / 64) * ((g.H + 63) / 64);
+    dim3 gt(8 * ((n_tiles + 7) / 8));
+    e = host.in_u8 ? launch_kb_tile_any<true>(host.lds_pitch, host.n_quads, gt, lds, s, I, p, dev, ws, out, num, den)
+                   : launch_kb_tile_any<false>(host.lds_pitch, host.n_quads, gt, lds, s, I, p, dev, ws, out, num, den);
+  } else {
+    dim3 gb((g.W + 63) / 64, (g.H + 3) / 4), bb(256);
+    e = host.in_u8 ? launch_kb<true>(gb, bb, s, I, p, dev, ws, out, num, den)
+                   : launch_kb<false>(gb, bb, s, I, p, dev, ws, out, num, den);
+  }
   profile_mark(1, 0, stream);
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
 }
