@@ -77,7 +77,8 @@ typedef struct {
   bf_precision_t precision; /* default BF_PREC_PLAIN */
   double eps;               /* kernel truncation level (Sec. IV-A); 0 -> 0.01 */
   double span;              /* intensity span D; range series on [-T, T], T = max(T_r, D); 0 -> 1 */
-  int tile;                 /* output tile edge of the summed-area tables; 0 -> automatic */
+  int tile;                 /* output tile edge of the summed-area tables (multiple of 64);
+                               0 -> chosen per image (see bf_image_geometry) */
   unsigned flags;           /* BF_FLAG_* */
 } bf_plan_opts_t;
 
@@ -137,8 +138,8 @@ typedef struct {
   int n_tap_rows;     /* distinct tap row offsets */
   int n_tap_cols;     /* distinct tap column offsets */
   int n_images;       /* term images per filter call: 4 n_range - 3 */
-  int tile;           /* output tile edge */
-  int sat_shift;      /* q: term values are stored as round(v * 2^q) in int32 */
+  int tile;           /* fixed output tile edge, 0 when chosen per image */
+  int sat_shift;      /* -1: q is chosen per image (bf_image_geometry) */
   double T_s;         /* spatial truncation r + 1/2 */
   double T_r;         /* K_r^{-1}(eps) */
   double T;           /* range series half-interval max(T_r, span) */
@@ -146,6 +147,12 @@ typedef struct {
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);
+
+/* Tiling of an H x W image under a plan: the table tile edge, the shift q
+ * (term values are stored as round(v * 2^q) in int32; (tile + 2r)^2 2^q is
+ * kept below 2^31) and the workspace bytes.  Any pointer may be NULL. */
+bf_status_t bf_image_geometry(bf_plan_t plan, int H, int W, int *tile, int *sat_shift,
+                              size_t *ws_bytes);
 
 /* Range terms: k[i], a[i] (coefficient a_k) and omega[i] = pi k / T, i < n_range. */
 bf_status_t bf_plan_range_terms(bf_plan_t plan, int *k, double *a, double *omega, int capacity);

@@ -22,7 +22,7 @@ BF_FLAG_HOST_ONLY = 0x1
 EXPORTED = [
     "bf_plan_create", "bf_plan_destroy", "bf_workspace_size", "bf_filter", "bf_filter_ws",
     "bf_filter_parts", "bf_batch_workspace_size", "bf_filter_batch", "bf_plan_query",
-    "bf_plan_range_terms", "bf_plan_spatial_kernel", "bf_plan_taps", "bf_plan_spatial_groups",
+    "bf_image_geometry", "bf_plan_range_terms", "bf_plan_spatial_kernel", "bf_plan_taps", "bf_plan_spatial_groups",
     "bf_profile_enable", "bf_profile_read", "bf_status_string", "bf_version",
 ]
 
@@ -76,6 +76,7 @@ def lib():
         L.bf_filter_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ip, ip, vp, sz, vp]
         L.bf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.bf_image_geometry.argtypes = [vp, i, i, ip, ip, ctypes.POINTER(sz)]
         L.bf_plan_range_terms.argtypes = [vp, ip, dp, dp, i]
         L.bf_plan_spatial_kernel.argtypes = [vp, dp, i]
         L.bf_plan_taps.argtypes = [vp, ip, ip, dp, i]
@@ -184,6 +185,13 @@ class Plan:
         lx, ly = (ctypes.c_int * n)(), (ctypes.c_int * n)()
         _check(lib().bf_plan_spatial_groups(self._h, lx, ly, n), "bf_plan_spatial_groups")
         return list(zip(lx[:], ly[:]))
+
+    def geometry(self, H, W):
+        """(table tile edge, fixed-point shift q, workspace bytes) for an H x W image."""
+        t, q, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        _check(lib().bf_image_geometry(self._h, int(H), int(W), ctypes.byref(t), ctypes.byref(q),
+                                       ctypes.byref(b)), "bf_image_geometry")
+        return t.value, q.value, b.value
 
     def workspace_size(self, H, W):
         b = ctypes.c_size_t()

@@ -21,18 +21,10 @@ bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
   return a0 < b0 + nb && b0 < a0 + na;
 }
 
-int choose_tile(int radius) { return radius <= 32 ? 256 : 512; }
-
-// q with (E - 1)^2 * 2^q * gmax <= 2^31 - 1 for tables of edge E.
-int choose_shift(int tile, int radius, double gmax) {
-  const double E = tile + 2.0 * radius;  // E_max - 1 summed rows/columns
-  const double lim = 2147483647.0 / (E * E * gmax);
-  int q = (int)std::floor(std::log2(lim));
-  return std::max(0, std::min(24, q));
-}
-
 bf::Geometry geometry_of(const bf_plan_s *p, int H, int W) {
-  return bf::make_geometry(H, W, p->tile, p->fit.radius, p->host_tables.n_images);
+  int tile = 0, q = 0;
+  bf::choose_tiling(H, W, p->fit.radius, p->host_tables.n_terms, p->tile, p->gmax, &tile, &q);
+  return bf::make_geometry(H, W, tile, p->fit.radius, p->host_tables.n_images, q);
 }
 
 bf_status_t check_image(const bf_plan_s *p, const void *I, const float *out, int H, int W) {
@@ -82,13 +74,13 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   p->in_dtype = o.in_dtype;
   p->precision = o.precision;
   p->flags = o.flags;
-  p->tile = o.tile ? o.tile : choose_tile(f.radius);
-  if (p->tile + 2 * f.radius + 1 > 256 * bf::kMaxChunks) {  // one table row must fit 8 chunks
-    delete p;
+  p->tile = o.tile;
+  if (64 + 2 * f.radius + 1 > 768 || (p->tile && p->tile + 2 * f.radius + 1 > 768)) {
+    delete p;  // a table row must fit three 256-column chunks
     return BF_ERR_UNSUPPORTED;
   }
   const double gmax = o.in_dtype == BF_IN_U8 ? 1.0 : std::max(1.0, span);
-  p->sat_shift = choose_shift(p->tile, f.radius, gmax);
+  p->gmax = gmax;
 
   bf::DevTables &t = p->host_tables;
   std::memset(&t, 0, sizeof t);
@@ -99,18 +91,15 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   for (int j = 0; j < t.n_tx; ++j) t.tx[j] = f.col_off[j];
   for (int i = 0; i < t.n_ty; ++i)
     for (int j = 0; j < t.n_tx; ++j) t.w[i * bf::kMaxTapAxis + j] = f.tap_grid[(size_t)i * t.n_tx + j];
-  // compact tap list with byte offsets for the table pitch of this plan
-  const bf::Geometry g0 = bf::make_geometry(1, 1, p->tile, f.radius, 1);
+  // compact tap list
   const int nt = (int)f.tap_w.size();
   if (nt > bf::kMaxTaps - 3) {
     delete p;
     return BF_ERR_UNSUPPORTED;
   }
-  t.pitch = g0.pitch;
   t.n_taps4 = (nt + 3) / 4 * 4;
   t.tap_dy_min = t.tap_dx_min = 1 << 30;
   t.tap_dy_max = t.tap_dx_max = -(1 << 30);
-  t.tap_d_min = 1 << 30;
   for (int i = 0; i < nt; ++i) {
     t.tap_dy[i] = f.tap_dy[i];
     t.tap_dx[i] = f.tap_dx[i];
@@ -119,15 +108,12 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
     t.tap_dy_max = std::max(t.tap_dy_max, f.tap_dy[i]);
     t.tap_dx_min = std::min(t.tap_dx_min, f.tap_dx[i]);
     t.tap_dx_max = std::max(t.tap_dx_max, f.tap_dx[i]);
-    t.tap_d_min = std::min(t.tap_d_min, f.tap_dy[i] * t.pitch + f.tap_dx[i]);
   }
   for (int i = nt; i < t.n_taps4; ++i) {  // padding: weight 0 at the first tap's position
     t.tap_dy[i] = f.tap_dy[0];
     t.tap_dx[i] = f.tap_dx[0];
     t.tap_w[i] = 0.0;
   }
-  for (int i = 0; i < t.n_taps4; ++i)
-    t.tap_boff[i] = 4 * (t.tap_dy[i] * t.pitch + t.tap_dx[i] - t.tap_d_min);
   // quadruplets for the LDS tile kernel: region of 64 + (dx_max - dx_min) columns
   t.lds_pitch = bf::lds_pitch_for(64 + t.tap_dx_max - t.tap_dx_min);
   {
@@ -184,8 +170,6 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
     slot += nparts;
   }
   t.n_images = slot;
-  t.sat_scale = std::ldexp(1.0f, p->sat_shift);
-  t.inv_sat_scale = std::ldexp(1.0, -p->sat_shift);
   t.gmax = (float)gmax;
   t.den_floor = 1e-7 * f.sum_abs_K;
   t.in_u8 = o.in_dtype == BF_IN_U8;
@@ -305,11 +289,21 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   info->n_tap_cols = (int)f.col_off.size();
   info->n_images = plan->host_tables.n_images;
   info->tile = plan->tile;
-  info->sat_shift = plan->sat_shift;
+  info->sat_shift = -1;
   info->T_s = f.T_s;
   info->T_r = f.T_r;
   info->T = f.T;
   info->den_floor = plan->host_tables.den_floor;
+  return BF_OK;
+}
+
+bf_status_t bf_image_geometry(bf_plan_t plan, int H, int W, int *tile, int *sat_shift,
+                              size_t *ws_bytes) {
+  if (!plan || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
+  const bf::Geometry g = geometry_of(plan, H, W);
+  if (tile) *tile = g.tile;
+  if (sat_shift) *sat_shift = g.sat_shift;
+  if (ws_bytes) *ws_bytes = g.bytes;
   return BF_OK;
 }
 

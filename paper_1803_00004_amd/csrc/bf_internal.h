@@ -50,11 +50,6 @@ struct DevTables {
   int tap_dy[kMaxTaps], tap_dx[kMaxTaps];
   double tap_w[kMaxTaps];
   int tap_dy_min, tap_dy_max, tap_dx_min, tap_dx_max;
-  // byte offset of each tap relative to the smallest one, for the plan's
-  // table pitch: 4 ((dy - dy0) pitch + dx - dx0) with (dy0, dx0) the smallest
-  int tap_boff[kMaxTaps];
-  int tap_d_min;                       // min over taps of dy * pitch + dx
-  int pitch;                           // table row pitch (elements) for this plan
   // Taps grouped for the LDS tile kernel.  A symmetric kernel has taps
   // (dy, dx), (1-dy, dx), (dy, 1-dx), (1-dy, 1-dx) with weights w, -w, -w, w:
   // one box sum of the table, differenced exactly in int32, times w.
@@ -73,9 +68,7 @@ struct DevTables {
   int slot[kMaxTerms];                 // first table of the term
   // table -> (term, part); part 0: C*I, 1: S*I, 2: C, 3: S, 4: I (k = 0)
   int slot_term[kMaxImages], slot_part[kMaxImages];
-  float sat_scale;                     // 2^q
-  double inv_sat_scale;                // 2^-q
-  float gmax;                          // |term value| clamp
+  float gmax;                          // bound of |term value| for [0, span] input
   double den_floor;
   int in_u8;
   int n_images;
@@ -85,13 +78,22 @@ struct DevTables {
 // tile-relative summed-area tables of E_h x E_w (pitch P_w) int32 entries.
 struct Geometry {
   int H, W, tile, radius;
+  int sat_shift;                    // q: term values stored as round(v * 2^q)
   int tiles_y, tiles_x, n_images;
   int E_max, pitch;                 // max table edge (tile + 2r + 1) and padded row pitch
   size_t table_elems;               // E_max * pitch per table
   size_t bytes;                     // whole workspace
 };
 
-Geometry make_geometry(int H, int W, int tile, int radius, int n_images);
+Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat_shift);
+
+// Table tile and fixed-point shift for one image: `fixed_tile` if nonzero,
+// else the largest of 512, 256, 128, 64 that gives >= 2048 term waves with a
+// table row of <= 768 columns (the smallest such tile otherwise); q is the
+// largest shift with (tile + 2r)^2 2^q gmax <= 2^31 - 1, at most 24.
+// A pure function of its arguments, so every call path tiles an image alike.
+void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int *tile,
+                   int *sat_shift);
 
 // Row pitch (int32 elements) of the LDS tile kernel's staged table region for
 // a region `width` columns wide: one of the compiled pitches, or 0 if none fits.
@@ -112,8 +114,8 @@ struct bf_plan_s {
   bf::Fit fit;
   bf_dtype_t in_dtype = BF_IN_F32;
   bf_precision_t precision = BF_PREC_PLAIN;
-  int tile = 256;
-  int sat_shift = 14;
+  int tile = 0;        // fixed table tile, 0 = chosen per image
+  double gmax = 1.0;
   unsigned flags = 0;
   bf::DevTables host_tables{};
   bf::DevTables *dev_tables = nullptr;  // device copy

@@ -27,6 +27,8 @@ namespace bf {
 struct ImageParams {
   int H, W, tile, radius, tiles_x, n_images, pitch, n_terms;
   long long table_elems;
+  float sat_scale;       // 2^q
+  double inv_sat_scale;  // 2^-q
 };
 
 // Phase of term k at intensity x in revolutions, reduced to about [-0.5, 0.5]:
@@ -54,11 +56,6 @@ __device__ __forceinline__ void load_pixel(const void *I, long long idx, float *
   }
 }
 
-__device__ __forceinline__ int quantize(float v, float gmax, float scale) {
-  v = fminf(fmaxf(v, -gmax), gmax);
-  return __float2int_rn(v * scale);
-}
-
 // Inclusive prefix sum over the 64 lanes of a wave with DPP moves: partial
 // sums within each 16-lane row (row_shr 1, 2, 3, then 4 and 8 on the upper
 // banks), then the row totals carried by row_bcast:15 and row_bcast:31.
@@ -75,12 +72,15 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
 }
 
 // ---------------------------------------------------------------------------
-// K-A: tile-relative int32 summed-area table of one term image per wave.
-// Lane l owns the 4-column groups [4l + 256g, 4l + 256g + 4), g < G, so each
-// int4 store of a row writes 1 KB of contiguous memory; the row prefix is an
-// in-lane prefix plus one DPP wave scan per 256-column chunk, the column
-// accumulation lives in registers, and the image rows are prefetched PF rows
-// ahead.  No barriers: waves are independent.
+// K-A: tile-relative int32 summed-area tables of one range term per wave
+// (the four term images C*I, S*I, C, S share one phase and one sin/cos; the
+// k = 0 term has the single image I).  Lane l owns the 4-column groups
+// [4l + 256g, 4l + 256g + 4), g < G, so each int4 store of a row writes 1 KB
+// of contiguous memory; the row prefix is an in-lane prefix plus one DPP wave
+// scan per 256-column chunk; the column accumulation lives in registers and
+// the image rows are prefetched kPF rows ahead.  No barriers: waves are
+// independent.  Term values are quantised as round(v * 2^q); values outside
+// [-gmax, gmax] (inputs outside [0, span]) are not clamped.
 // ---------------------------------------------------------------------------
 constexpr int kPF = 4;
 
@@ -89,8 +89,8 @@ __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageP
                                              const DevTables *__restrict__ tab,
                                              int32_t *__restrict__ ws) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int slot = blockIdx.y * 4 + wave;
-  if (slot >= p.n_images) return;
+  const int term = blockIdx.y * 4 + wave;
+  if (term >= p.n_terms) return;
   const int tile_id = blockIdx.x;
   const int ty = tile_id / p.tiles_x, tx = tile_id - ty * p.tiles_x;
   const int y0 = ty * p.tile, x0 = tx * p.tile;
@@ -98,10 +98,12 @@ __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageP
   const int oy = max(y0 - p.radius, 0), ox = max(x0 - p.radius, 0);
   const int Eh = min(y1 + p.radius, p.H) - oy + 1;
   const int Ew = min(x1 + p.radius, p.W) - ox + 1;
-  const int term = tab->slot_term[slot], part = tab->slot_part[slot];
+  const bool k0 = tab->k_is_zero[term] != 0;
+  const int nimg = k0 ? 1 : 4;
   const float f_hi = tab->f_hi[term], f_lo = tab->f_lo[term];
-  const float gmax = tab->gmax, scale = tab->sat_scale;
-  int32_t *base = ws + ((long long)tile_id * p.n_images + slot) * p.table_elems;
+  const float scale = p.sat_scale;
+  int32_t *base = ws + ((long long)tile_id * p.n_images + tab->slot[term]) * p.table_elems;
+  const long long te = p.table_elems;
 
   // raw pixel values (u8 as integer-valued float) of the rows i .. i + kPF - 1
   float pf[kPF][G][4];
@@ -123,12 +125,16 @@ __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageP
 #pragma unroll
   for (int q = 0; q < kPF; ++q) load_row(1 + q, pf[q]);
 
-  int acc[G][4];
+  int acc[4][G][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[m][g][0] = acc[m][g][1] = acc[m][g][2] = acc[m][g][3] = 0;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    acc[g][0] = acc[g][1] = acc[g][2] = acc[g][3] = 0;
     const int j0 = 4 * lane + 256 * g;
-    if (j0 < p.pitch) *reinterpret_cast<int4 *>(base + j0) = make_int4(0, 0, 0, 0);
+    if (j0 < p.pitch)
+      for (int m = 0; m < nimg; ++m) *reinterpret_cast<int4 *>(base + m * te + j0) = make_int4(0, 0, 0, 0);
   }
 
   for (int i = 1; i < Eh; ++i) {
@@ -145,37 +151,43 @@ __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageP
         for (int c = 0; c < 4; ++c) pf[q][g][c] = pf[q + 1][g][c];
     load_row(i + kPF, pf[kPF - 1]);
 
-    int carry = 0;
+    int carry[4] = {0, 0, 0, 0};
     int32_t *row = base + (long long)i * p.pitch;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      int v[4];
+      int v[4][4];  // [image][column]
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const float px = cur[g][c];
-        const float x = U8 ? px * (1.0f / 255.0f) : px;
-        float val;
-        if (part == 4) {
-          val = x;
+        const float xs = (U8 ? px * (1.0f / 255.0f) : px) * scale;  // I * 2^q
+        if (k0) {
+          v[0][c] = __float2int_rn(xs);
+          v[1][c] = v[2][c] = v[3][c] = 0;
         } else {
           const float fr = phase_rev(f_hi, f_lo, px);
-          const float cs = (part & 1) ? __builtin_amdgcn_sinf(fr) : __builtin_amdgcn_cosf(fr);
-          val = (part < 2) ? cs * x : cs;
+          const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
+          v[0][c] = __float2int_rn(C * xs);
+          v[1][c] = __float2int_rn(S * xs);
+          v[2][c] = __float2int_rn(C * scale);
+          v[3][c] = __float2int_rn(S * scale);
         }
-        // the zero padding column j = 0 and columns past the table read 0
-        v[c] = quantize(val, gmax, scale);
       }
-      v[1] += v[0];
-      v[2] += v[1];
-      v[3] += v[2];
-      const int incl = wave_inclusive_scan(v[3]);
-      const int excl = incl - v[3] + carry;
-      carry += __builtin_amdgcn_readlane(incl, 63);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[g][c] += v[c] + excl;
       const int j0 = 4 * lane + 256 * g;
-      if (j0 < p.pitch)
-        *reinterpret_cast<int4 *>(row + j0) = make_int4(acc[g][0], acc[g][1], acc[g][2], acc[g][3]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (m >= nimg) break;
+        v[m][1] += v[m][0];
+        v[m][2] += v[m][1];
+        v[m][3] += v[m][2];
+        const int incl = wave_inclusive_scan(v[m][3]);
+        const int excl = incl - v[m][3] + carry[m];
+        carry[m] += __builtin_amdgcn_readlane(incl, 63);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[m][g][c] += v[m][c] + excl;
+        if (j0 < p.pitch)
+          *reinterpret_cast<int4 *>(row + m * te + j0) =
+              make_int4(acc[m][g][0], acc[m][g][1], acc[m][g][2], acc[m][g][3]);
+      }
     }
   }
 }
@@ -218,12 +230,17 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
       make_rsrc(ws + (long long)tile_id * p.n_images * p.table_elems, te4 * (uint32_t)p.n_images);
   const int n4 = tab->n_taps4;
   const int yr = y - oy, xr = x - ox;
-  // interior: element offset of the tap with the smallest dy * pitch + dx
-  const uint32_t voff0 = (uint32_t)(yr * p.pitch + xr + tab->tap_d_min) * 4u;
+  // interior: the thread's offset at tap (dy_min, dx_min); each tap adds the
+  // uniform, non-negative (dy - dy_min) * pitch + dx - dx_min
+  const int dy0 = tab->tap_dy_min, dx0 = tab->tap_dx_min;
+  const uint32_t voff0 = (uint32_t)((yr + dy0) * p.pitch + xr + dx0) * 4u;
+  auto tap_soff = [&](int i) {
+    return (uint32_t)((tab->tap_dy[i] - dy0) * p.pitch + (tab->tap_dx[i] - dx0)) * 4u;
+  };
 
   float px, xv;
   load_pixel<U8>(I, (long long)y * p.W + x, &px, &xv);
-  const double inv = tab->inv_sat_scale;
+  const double inv = p.inv_sat_scale;
   double num = 0.0, den = 0.0;
   for (int t = 0; t < p.n_terms; ++t) {
     const uint32_t sb = (uint32_t)tab->slot[t] * te4;
@@ -236,7 +253,7 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
         const int Y = min(max(y + tab->tap_dy[i], 0), p.H) - oy;
         const int X = min(max(x + tab->tap_dx[i], 0), p.W) - ox;
         const double w = tab->tap_w[i];
-        const int v = interior ? load_i32(rsrc, voff0, sb + (uint32_t)tab->tap_boff[i])
+        const int v = interior ? load_i32(rsrc, voff0, sb + tap_soff(i))
                                : load_i32(rsrc, (uint32_t)(Y * p.pitch + X) * 4u, sb);
         c0 = __builtin_fma(w, (double)v, c0);
         d0 = __builtin_fma(w, (double)(Y * X), d0);
@@ -251,7 +268,7 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
         int v[4][4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const uint32_t so = sb + (uint32_t)tab->tap_boff[i + j];
+          const uint32_t so = sb + tap_soff(i + j);
 #pragma unroll
           for (int m = 0; m < 4; ++m) v[j][m] = load_i32(rsrc, voff0, so + (uint32_t)m * te4);
         }
@@ -385,7 +402,7 @@ __global__ __launch_bounds__(NT) void kb_tile(const void *__restrict__ I, ImageP
     num[i] = 0.0;
     den[i] = 0.0;
   }
-  const double inv = tab->inv_sat_scale;
+  const double inv = p.inv_sat_scale;
   // LDS element offset of this thread's first pixel: region row r holds image
   // row y0 + dy0 + r, so tap (dy, dx) of the pixel in tile row yl, column lane
   // is at (yl + dy - dy0) * PITCH + lane + dx - dx0 = yl * PITCH + lane + off(dy, dx)
@@ -550,8 +567,27 @@ static hipError_t launch_kb_tile_any(int pitch, int nq, dim3 grid, size_t lds, h
   }
 }
 
-Geometry make_geometry(int H, int W, int tile, int radius, int n_images) {
+void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int *tile,
+                   int *sat_shift) {
+  int t = fixed_tile;
+  if (!t) {
+    t = 64;
+    for (int c : {512, 256, 128, 64}) {
+      if (c + 2 * radius + 1 > 768) continue;
+      const long long waves = (long long)((H + c - 1) / c) * ((W + c - 1) / c) * n_terms;
+      t = c;
+      if (waves >= 2048) break;
+    }
+  }
+  const double E = t + 2.0 * radius;
+  int q = (int)std::floor(std::log2(2147483647.0 / (E * E * gmax)));
+  *tile = t;
+  *sat_shift = std::max(0, std::min(24, q));
+}
+
+Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat_shift) {
   Geometry g;
+  g.sat_shift = sat_shift;
   g.H = H;
   g.W = W;
   g.tile = tile;
@@ -580,10 +616,12 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
   p.pitch = g.pitch;
   p.n_terms = host.n_terms;
   p.table_elems = (long long)g.table_elems;
+  p.sat_scale = std::ldexp(1.0f, g.sat_shift);
+  p.inv_sat_scale = std::ldexp(1.0, -g.sat_shift);
   const int Ew = std::min(g.tile + 2 * g.radius + 1, g.W + 1);
   const int G = (Ew + 255) / 256;
   if (G > kMaxChunks) return BF_ERR_UNSUPPORTED;
-  dim3 ga(g.tiles_y * g.tiles_x, (host.n_images + 3) / 4), ba(256);
+  dim3 ga(g.tiles_y * g.tiles_x, (host.n_terms + 3) / 4), ba(256);
   profile_mark(0, 1, stream);
   hipError_t e = host.in_u8 ? launch_ka<true>(G, ga, ba, s, I, p, dev, ws)
                             : launch_ka<false>(G, ga, ba, s, I, p, dev, ws);

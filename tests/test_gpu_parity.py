@@ -76,7 +76,7 @@ def test_shapes_vs_oracle(torch_dev, H, W, tile, ss, r, ns, sr, nr):
     out = _run(torch_dev, gp, I)
     ref = oracle.expanded_box(I, op)
     err = np.abs(out - ref).max()
-    _report("%dx%d tile %d r %d" % (H, W, gp.info.tile, r), err)
+    _report("%dx%d tile %d r %d" % (H, W, gp.geometry(H, W)[0], r), err)
     assert err <= TIGHT
 
 

@@ -88,14 +88,21 @@ def test_taps_reproduce_oracle_correlation(ss, r, ns, sr, nr):
             assert np.abs(c2 - ref[ty:y1, tx:x1]).max() < 1e-10
 
 
-def test_sat_shift_bounds_tables():
-    """q keeps every tile table inside int32: (tile + 2r)^2 2^q <= 2^31 - 1."""
+def test_tiling_keeps_tables_in_int32():
+    """Per-image tiling: q keeps every tile table inside int32 ((tile + 2r)^2 2^q
+    <= 2^31 - 1, and q is the largest such shift up to 24); the tile is a
+    multiple of 64, fixed when the plan fixes it, and a pure function of the
+    image size."""
     for ss, r, ns, sr, nr in CONFIGS:
-        for tile in (0, 128, 512):
-            info = bf.Plan(ss, sr, r, nr, ns, tile=tile, host_only=True).info
-            E = info.tile + 2 * r
-            assert E * E * 2.0 ** info.sat_shift <= 2 ** 31 - 1
-            assert E * E * 2.0 ** (info.sat_shift + 1) > 2 ** 31 - 1 or info.sat_shift == 24
+        for fixed in (0, 128, 256):
+            p = bf.Plan(ss, sr, r, nr, ns, tile=fixed, host_only=True)
+            for H, W in ((1, 1), (256, 256), (1080, 1920), (4096, 4096), (37, 3000)):
+                tile, q, nbytes = p.geometry(H, W)
+                assert tile % 64 == 0 and (fixed == 0 or tile == fixed)
+                E = tile + 2 * r
+                assert E * E * 2.0 ** q <= 2 ** 31 - 1
+                assert E * E * 2.0 ** (q + 1) > 2 ** 31 - 1 or q == 24
+                assert nbytes == p.workspace_size(H, W) and p.geometry(H, W) == (tile, q, nbytes)
 
 
 @pytest.mark.parametrize("kw", [dict(sigma_s=0.0, sigma_r=0.1), dict(sigma_s=3.0, sigma_r=-1.0),
