@@ -132,14 +132,18 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
       if (used[i] || dy < 1 || dx < 1) continue;  // representative has dy >= 1, dx >= 1
       double wb, wc, wd;
       const double wa = f.tap_w[i];
+      // the expansion is symmetric under u -> -u on each axis, so the four
+      // taps carry +-w up to the rounding of the fit; 1e-12 relative admits
+      // exactly that
+      const double tol = 1e-12 * std::fabs(wa);
       if (weight_at(1 - dy, dx, &wb) && weight_at(dy, 1 - dx, &wc) && weight_at(1 - dy, 1 - dx, &wd) &&
-          wb == -wa && wc == -wa && wd == wa) {
+          std::fabs(wb + wa) <= tol && std::fabs(wc + wa) <= tol && std::fabs(wd - wa) <= tol) {
         const int q = t.n_quads++;
         t.quad_off[q][0] = loff(dy, dx);
         t.quad_off[q][1] = loff(1 - dy, dx);
         t.quad_off[q][2] = loff(dy, 1 - dx);
         t.quad_off[q][3] = loff(1 - dy, 1 - dx);
-        t.quad_w[q] = wa;
+        t.quad_w[q] = 0.25 * ((wa + wd) - (wb + wc));
         for (int j = 0; j < nt; ++j) {
           const int ey = f.tap_dy[j], ex = f.tap_dx[j];
           if ((ey == dy || ey == 1 - dy) && (ex == dx || ex == 1 - dx)) used[j] = 1;

@@ -88,7 +88,8 @@ template <int G, bool U8>
 __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageParams p,
                                              const DevTables *__restrict__ tab,
                                              int32_t *__restrict__ ws) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is uniform; saying so keeps per-term loads scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int term = blockIdx.y * 4 + wave;
   if (term >= p.n_terms) return;
   const int tile_id = blockIdx.x;
@@ -334,7 +335,8 @@ __global__ __launch_bounds__(NT) void kb_tile(const void *__restrict__ I, ImageP
   constexpr int CC = (PITCH + 63) / 64;       // 64-column chunks of a staged row
   constexpr int RR = (PITCH + NW - 1) / NW;   // staged rows per wave (region rows <= PITCH)
   extern __shared__ int lds[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // uniform wave index: the staging row offsets are scalar buffer offsets
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // XCD-aware order: blocks are dispatched round-robin over the 8 XCDs, so
   // XCD k (blockIdx % 8) takes the k-th contiguous eighth of the tiles, walked
   // in patches of 8 x 4 tiles; the tiles one XCD runs at the same time are
