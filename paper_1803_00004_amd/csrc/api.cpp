@@ -125,7 +125,6 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
         }
       return false;
     };
-    auto loff = [&](int dy, int dx) { return (dy - t.tap_dy_min) * t.lds_pitch + (dx - t.tap_dx_min); };
     std::vector<char> used(nt, 0);
     for (int i = 0; i < nt; ++i) {
       const int dy = f.tap_dy[i], dx = f.tap_dx[i];
@@ -139,10 +138,8 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
       if (weight_at(1 - dy, dx, &wb) && weight_at(dy, 1 - dx, &wc) && weight_at(1 - dy, 1 - dx, &wd) &&
           std::fabs(wb + wa) <= tol && std::fabs(wc + wa) <= tol && std::fabs(wd - wa) <= tol) {
         const int q = t.n_quads++;
-        t.quad_off[q][0] = loff(dy, dx);
-        t.quad_off[q][1] = loff(1 - dy, dx);
-        t.quad_off[q][2] = loff(dy, 1 - dx);
-        t.quad_off[q][3] = loff(1 - dy, 1 - dx);
+        t.quad_dy[q] = dy;
+        t.quad_dx[q] = dx;
         t.quad_w[q] = 0.25 * ((wa + wd) - (wb + wc));
         for (int j = 0; j < nt; ++j) {
           const int ey = f.tap_dy[j], ex = f.tap_dx[j];
@@ -152,7 +149,8 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
     }
     for (int i = 0; i < nt; ++i)
       if (!used[i]) {
-        t.single_off[t.n_single] = loff(f.tap_dy[i], f.tap_dx[i]);
+        t.single_dy[t.n_single] = f.tap_dy[i];
+        t.single_dx[t.n_single] = f.tap_dx[i];
         t.single_w[t.n_single] = f.tap_w[i];
         ++t.n_single;
       }

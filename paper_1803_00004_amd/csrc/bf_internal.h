@@ -52,15 +52,14 @@ struct DevTables {
   int tap_dy_min, tap_dy_max, tap_dx_min, tap_dx_max;
   // Taps grouped for the LDS tile kernel.  A symmetric kernel has taps
   // (dy, dx), (1-dy, dx), (dy, 1-dx), (1-dy, 1-dx) with weights w, -w, -w, w:
-  // one box sum of the table, differenced exactly in int32, times w.
-  // lds_off[] are element offsets into the staged region of row pitch
-  // lds_pitch: corner a = (dy, dx), b = (1-dy, dx), c = (dy, 1-dx), d = (1-dy, 1-dx).
-  int lds_pitch;                       // 0: no LDS tile kernel for this plan
+  // one box sum of the table, differenced exactly in int32, times w.  Each
+  // quadruplet is stored as its representative (dy >= 1, dx >= 1).
+  int lds_pitch;                       // staged region row pitch; 0: no LDS tile kernel
   int n_quads;
-  int quad_off[kMaxTaps / 4][4];
+  int quad_dy[kMaxTaps / 4], quad_dx[kMaxTaps / 4];
   double quad_w[kMaxTaps / 4];
   int n_single;                        // taps without a symmetric quadruplet
-  int single_off[kMaxTaps];
+  int single_dy[kMaxTaps], single_dx[kMaxTaps];
   double single_w[kMaxTaps];
   float f_hi[kMaxTerms], f_lo[kMaxTerms];  // f_k = k / (2T) (u8: k / (2T 255)) as two floats
   double a[kMaxTerms];                 // a_k

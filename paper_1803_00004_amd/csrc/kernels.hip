@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "bf_internal.h"
 
@@ -316,26 +317,38 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
 
 // ---------------------------------------------------------------------------
 // K-B (LDS tile form): one block per 64 x 64 output tile; tables are the
-// outer loop.  For each table the block stages the region its taps read --
-// (64 + dy span) rows x (64 + dx span) columns, with the border clamp applied
-// while staging -- into LDS once, then every pixel reads its taps from LDS.
-// Symmetric quadruplets of taps are one box sum differenced exactly in int32
-// and one FP64 FMA.  The tile's numerators and denominators stay in
-// registers across all terms.  PITCH is the LDS row pitch, so the per-pixel
-// row offsets are instruction immediates.
+// outer loop.  For each table the block copies the region its taps read --
+// (64 + dy span) rows x (64 + dx span) columns, border clamp applied through
+// the per-lane source columns -- from the workspace straight into LDS with
+// buffer-to-LDS loads (no registers, no vector instructions), then every
+// pixel reads its taps from LDS.  Symmetric quadruplets of taps are one box
+// sum differenced exactly in int32 and one FP64 FMA.  Each thread owns the
+// pixels (wave + 16 i, lane), i < 4, of the tile: one precomputed LDS address
+// per quadruplet corner serves all four through instruction offsets.  When
+// two regions fit in LDS they are double-buffered with their rows
+// interleaved (row r of buffer b at (2r + b) * PITCH), so the second buffer
+// is an instruction offset too and each table costs one barrier; the copy of
+// table m + 1 runs while table m is read.
 // ---------------------------------------------------------------------------
-template <int PITCH, int NT, int NQ, bool U8>
-__global__ __launch_bounds__(NT) void kb_tile(const void *__restrict__ I, ImageParams p,
-                                              const DevTables *__restrict__ tab,
-                                              const int32_t *__restrict__ ws,
-                                              float *__restrict__ out, float *__restrict__ num_out,
-                                              float *__restrict__ den_out) {
-  constexpr int NW = NT / 64;                 // waves
-  constexpr int PX = 64 / NW;                 // rows of the tile per thread
-  constexpr int CC = (PITCH + 63) / 64;       // 64-column chunks of a staged row
-  constexpr int RR = (PITCH + NW - 1) / NW;   // staged rows per wave (region rows <= PITCH)
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+__device__ __forceinline__ int lds_ld(const int *lds, uint32_t byte_addr) {
+  return *reinterpret_cast<const int *>(reinterpret_cast<const char *>(lds) + byte_addr);
+}
+
+template <int PITCH, int NQ, bool DB, bool U8>
+__global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, ImageParams p,
+                                               const DevTables *__restrict__ tab,
+                                               const int32_t *__restrict__ ws,
+                                               float *__restrict__ out, float *__restrict__ num_out,
+                                               float *__restrict__ den_out) {
+  constexpr int NW = 16;                          // waves
+  constexpr int PX = 64 / NW;                     // rows of the tile per thread
+  constexpr int RS = DB ? 2 * PITCH : PITCH;      // LDS row stride (int32 elements)
+  constexpr int CC = (PITCH + 63) / 64;           // 64-column chunks of a staged row
+  constexpr uint32_t PSTEP = NW * RS * 4;         // bytes between a thread's pixels
+  constexpr uint32_t BSTEP = PITCH * 4;           // bytes from buffer 0 to buffer 1
   extern __shared__ int lds[];
-  // uniform wave index: the staging row offsets are scalar buffer offsets
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // XCD-aware order: blocks are dispatched round-robin over the 8 XCDs, so
   // XCD k (blockIdx % 8) takes the k-th contiguous eighth of the tiles, walked
@@ -368,27 +381,51 @@ __global__ __launch_bounds__(NT) void kb_tile(const void *__restrict__ I, ImageP
   const int x = x0 + lane;
   const bool xin = x < p.W;
 
-  // staging geometry: wave w stages region rows w, w + NW, ...; lane l columns
-  // l, l + 64, ...  The row part of each table offset is wave-uniform and goes
-  // in the buffer load's scalar offset; the clamped column offset is fixed per
-  // lane, so staging needs no vector address arithmetic.
+  // staging: wave w copies region rows w, w + NW, ...; lane l columns l,
+  // l + 64, ...  The clamped source column is fixed per lane (vector offset),
+  // the table and row part is wave-uniform (scalar offset), the LDS target is
+  // the wave-uniform row start plus 4 bytes per lane.
   uint32_t xoff4[CC];
 #pragma unroll
   for (int c = 0; c < CC; ++c) xoff4[c] = (uint32_t)(min(max(x0 + dx0 + lane + 64 * c, 0), p.W) - ox) * 4u;
-  auto stage_load = [&](int m, int (&pre)[RR][CC]) {
-    const uint32_t soff = (uint32_t)m * te4;
-#pragma unroll
-    for (int rr = 0; rr < RR; ++rr) {
-      const int r = wave + NW * rr;
+  const uint32_t gp4 = (uint32_t)p.pitch * 4u;
+  auto stage = [&](int m, int buf) {
+    const uint32_t sm = (uint32_t)m * te4;
+    for (int r = wave; r < RH; r += NW) {
       const int Y = min(max(y0 + dy0 + r, 0), p.H) - oy;
-      const uint32_t srow = soff + (uint32_t)(Y * p.pitch) * 4u;
+      const uint32_t soff = sm + (uint32_t)Y * gp4;
+      int *dst = lds + r * RS + buf * PITCH;
 #pragma unroll
-      for (int c = 0; c < CC; ++c) {
-        pre[rr][c] = 0;
-        if (r < RH && lane + 64 * c < RW) pre[rr][c] = load_i32(rsrc, xoff4[c], srow);
-      }
+      for (int c = 0; c < CC; ++c)
+        if (lane + 64 * c < RW)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)(dst + 64 * c), 4, xoff4[c], soff, 0, 0);
     }
   };
+
+  // LDS byte address of each quadruplet corner for this thread's pixel 0 in
+  // buffer 0: region row r holds image row y0 + dy0 + r, so tap (dy, dx) of
+  // the pixel in tile row wave, column lane is at element
+  // (wave + dy - dy0) * RS + lane + dx - dx0.  Padding quadruplets read one
+  // valid element four times with weight 0.
+  const uint32_t lb = (uint32_t)(wave * RS + lane) * 4u;
+  const int nq = tab->n_quads;
+  uint32_t qa[NQ][4];
+  double qw[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q < nq) {
+      const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
+      const int ra = dy - dy0, rb = 1 - dy - dy0, ca = dx - dx0, cb = 1 - dx - dx0;
+      qa[q][0] = lb + (uint32_t)(ra * RS + ca) * 4u;
+      qa[q][1] = lb + (uint32_t)(rb * RS + ca) * 4u;
+      qa[q][2] = lb + (uint32_t)(ra * RS + cb) * 4u;
+      qa[q][3] = lb + (uint32_t)(rb * RS + cb) * 4u;
+      qw[q] = tab->quad_w[q];
+    } else {
+      qa[q][0] = qa[q][1] = qa[q][2] = qa[q][3] = lb;
+      qw[q] = 0.0;
+    }
+  }
 
   float pxv[PX];
   double num[PX], den[PX];
@@ -405,27 +442,13 @@ __global__ __launch_bounds__(NT) void kb_tile(const void *__restrict__ I, ImageP
     den[i] = 0.0;
   }
   const double inv = p.inv_sat_scale;
-  // LDS element offset of this thread's first pixel: region row r holds image
-  // row y0 + dy0 + r, so tap (dy, dx) of the pixel in tile row yl, column lane
-  // is at (yl + dy - dy0) * PITCH + lane + dx - dx0 = yl * PITCH + lane + off(dy, dx)
-  const int lbase = wave * PITCH + lane;
-
-  int pre[RR][CC];
-  stage_load(0, pre);
   float cs[PX], sn[PX];
-  for (int m = 0; m < p.n_images; ++m) {
-    const int t = tab->slot_term[m], part = tab->slot_part[m];
-    __syncthreads();  // every thread is done reading the previous table
-#pragma unroll
-    for (int rr = 0; rr < RR; ++rr)
-#pragma unroll
-      for (int c = 0; c < CC; ++c) {
-        const int r = wave + NW * rr, col = lane + 64 * c;
-        if (r < RH && col < RW) lds[r * PITCH + col] = pre[rr][c];
-      }
-    __syncthreads();
-    if (m + 1 < p.n_images) stage_load(m + 1, pre);  // in flight while this table is read
 
+  // one table: box sums of every quadruplet (and lone taps), then the fold of
+  // Eq. 1D_N_terms into the numerator / denominator
+  auto body = [&](int m, auto BUF) {
+    constexpr uint32_t bo = decltype(BUF)::value * BSTEP;
+    const int t = tab->slot_term[m], part = tab->slot_part[m];
     if (part == 0) {
 #pragma unroll
       for (int i = 0; i < PX; ++i) {
@@ -437,25 +460,22 @@ __global__ __launch_bounds__(NT) void kb_tile(const void *__restrict__ I, ImageP
     double s[PX];
 #pragma unroll
     for (int i = 0; i < PX; ++i) s[i] = 0.0;
-#pragma unroll 2
-    for (int q = 0; q < tab->n_quads; ++q) {
-      const int *qa = lds + lbase + tab->quad_off[q][0];
-      const int *qb = lds + lbase + tab->quad_off[q][1];
-      const int *qc = lds + lbase + tab->quad_off[q][2];
-      const int *qd = lds + lbase + tab->quad_off[q][3];
-      const double w = tab->quad_w[q];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
 #pragma unroll
       for (int i = 0; i < PX; ++i) {
-        const int o = NW * i * PITCH;
-        const int box = (qa[o] - qb[o]) - (qc[o] - qd[o]);
-        s[i] = __builtin_fma(w, (double)box, s[i]);
+        const uint32_t o = i * PSTEP + bo;
+        const int box = (lds_ld(lds, qa[q][0] + o) - lds_ld(lds, qa[q][1] + o)) -
+                        (lds_ld(lds, qa[q][2] + o) - lds_ld(lds, qa[q][3] + o));
+        s[i] = __builtin_fma(qw[q], (double)box, s[i]);
       }
     }
     for (int q = 0; q < tab->n_single; ++q) {
-      const int *qa = lds + lbase + tab->single_off[q];
+      const uint32_t a =
+          lb + (uint32_t)((tab->single_dy[q] - dy0) * RS + tab->single_dx[q] - dx0) * 4u + bo;
       const double w = tab->single_w[q];
 #pragma unroll
-      for (int i = 0; i < PX; ++i) s[i] = __builtin_fma(w, (double)qa[NW * i * PITCH], s[i]);
+      for (int i = 0; i < PX; ++i) s[i] = __builtin_fma(w, (double)lds_ld(lds, a + i * PSTEP), s[i]);
     }
     const double ai = tab->a[t] * inv;
 #pragma unroll
@@ -486,6 +506,35 @@ __global__ __launch_bounds__(NT) void kb_tile(const void *__restrict__ I, ImageP
         }
         den[i] = __builtin_fma(tab->a[t], d0, den[i]);
       }
+    }
+  };
+
+  const int n = p.n_images;
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
+  if (DB) {
+    stage(0, 0);
+    for (int m = 0; m < n; m += 2) {
+      // this wave's copy of table m has landed; after the barrier every
+      // wave's has, and every wave is done reading buffer 1 (table m - 1)
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (m + 1 < n) stage(m + 1, 1);
+      body(m, B0{});
+      if (m + 1 < n) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (m + 2 < n) stage(m + 2, 0);
+        body(m + 1, B1{});
+      }
+    }
+  } else {
+    for (int m = 0; m < n; ++m) {
+      __syncthreads();  // every wave is done reading table m - 1
+      stage(m, 0);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      body(m, B0{});
     }
   }
 #pragma unroll
@@ -527,7 +576,9 @@ static hipError_t launch_kb(dim3 grid, dim3 block, hipStream_t s, const void *I,
   return hipGetLastError();
 }
 
-static const int kLdsPitches[] = {96, 128, 160, 176, 192};
+// Staged-region row pitches: 128 double-buffered (two regions of up to 128 x
+// 128 take at most 128 KB), wider regions single-buffered.
+static const int kLdsPitches[] = {128, 160, 176, 192};
 
 int lds_pitch_for(int width) {
   for (int pch : kLdsPitches)
@@ -535,37 +586,46 @@ int lds_pitch_for(int width) {
   return 0;
 }
 
-template <int PITCH, int NQ, bool U8>
+static size_t kb_region_bytes(const DevTables &h) {
+  return (size_t)(64 + h.tap_dy_max - h.tap_dy_min) * h.lds_pitch * sizeof(int32_t);
+}
+static bool kb_double_buffered(const DevTables &h) {
+  return h.lds_pitch == 128 && 2 * kb_region_bytes(h) <= 160 * 1024;
+}
+
+template <int PITCH, int NQ, bool DB, bool U8>
 static hipError_t launch_kb_tile(dim3 grid, size_t lds, hipStream_t s, const void *I,
                                  ImageParams p, const DevTables *tab, const int32_t *ws, float *out,
                                  float *num, float *den) {
-  auto k = kb_tile<PITCH, 1024, NQ, U8>;
+  auto k = kb_tile<PITCH, NQ, DB, U8>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, grid, dim3(1024), lds, s, I, p, tab, ws, out, num, den);
   return hipGetLastError();
 }
 
-template <int PITCH, bool U8>
+template <int PITCH, bool DB, bool U8>
 static hipError_t launch_kb_tile_nq(int nq, dim3 grid, size_t lds, hipStream_t s, const void *I,
                                     ImageParams p, const DevTables *tab, const int32_t *ws,
                                     float *out, float *num, float *den) {
-  if (nq <= 4) return launch_kb_tile<PITCH, 4, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
-  if (nq <= 8) return launch_kb_tile<PITCH, 8, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
-  if (nq <= 12) return launch_kb_tile<PITCH, 12, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
-  return launch_kb_tile<PITCH, 16, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+  if (nq <= 4) return launch_kb_tile<PITCH, 4, DB, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+  if (nq <= 8) return launch_kb_tile<PITCH, 8, DB, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+  return launch_kb_tile<PITCH, 12, DB, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
 }
 
 template <bool U8>
-static hipError_t launch_kb_tile_any(int pitch, int nq, dim3 grid, size_t lds, hipStream_t s,
-                                     const void *I, ImageParams p, const DevTables *tab,
-                                     const int32_t *ws, float *out, float *num, float *den) {
-  switch (pitch) {
-    case 96: return launch_kb_tile_nq<96, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
-    case 128: return launch_kb_tile_nq<128, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
-    case 160: return launch_kb_tile_nq<160, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
-    case 176: return launch_kb_tile_nq<176, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
-    default: return launch_kb_tile_nq<192, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+static hipError_t launch_kb_tile_any(const DevTables &h, dim3 grid, hipStream_t s, const void *I,
+                                     ImageParams p, const DevTables *tab, const int32_t *ws,
+                                     float *out, float *num, float *den) {
+  const size_t lds = kb_region_bytes(h);
+  const int nq = h.n_quads;
+  if (kb_double_buffered(h))
+    return launch_kb_tile_nq<128, true, U8>(nq, grid, 2 * lds, s, I, p, tab, ws, out, num, den);
+  switch (h.lds_pitch) {
+    case 128: return launch_kb_tile_nq<128, false, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    case 160: return launch_kb_tile_nq<160, false, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    case 176: return launch_kb_tile_nq<176, false, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    default: return launch_kb_tile_nq<192, false, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
   }
 }
 
@@ -629,15 +689,14 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
                             : launch_ka<false>(G, ga, ba, s, I, p, dev, ws);
   profile_mark(0, 0, stream);
   if (e != hipSuccess) return BF_ERR_DEVICE;
-  // LDS tile kernel when the staged region fits, else the per-pixel kernel
-  const int RH = 64 + host.tap_dy_max - host.tap_dy_min;
-  const size_t lds = (size_t)RH * host.lds_pitch * sizeof(int32_t);
+  // LDS tile kernel when the staged region fits and the quadruplets' corner
+  // addresses fit in registers, else the per-pixel kernel
   profile_mark(1, 1, stream);
-  if (host.lds_pitch > 0 && lds <= 160 * 1024 && host.n_quads <= 16) {
+  if (host.lds_pitch > 0 && kb_region_bytes(host) <= 160 * 1024 && host.n_quads <= 12) {
     const int n_tiles = ((g.W + 63) / 64) * ((g.H + 63) / 64);
     dim3 gt(8 * ((n_tiles + 7) / 8));
-    e = host.in_u8 ? launch_kb_tile_any<true>(host.lds_pitch, host.n_quads, gt, lds, s, I, p, dev, ws, out, num, den)
-                   : launch_kb_tile_any<false>(host.lds_pitch, host.n_quads, gt, lds, s, I, p, dev, ws, out, num, den);
+    e = host.in_u8 ? launch_kb_tile_any<true>(host, gt, s, I, p, dev, ws, out, num, den)
+                   : launch_kb_tile_any<false>(host, gt, s, I, p, dev, ws, out, num, den);
   } else {
     dim3 gb((g.W + 63) / 64, (g.H + 3) / 4), bb(256);
     e = host.in_u8 ? launch_kb<true>(gb, bb, s, I, p, dev, ws, out, num, den)
