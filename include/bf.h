@@ -139,18 +139,25 @@ typedef struct {
   int n_tap_cols;     /* distinct tap column offsets */
   int n_images;       /* term images per filter call: 4 n_range - 3 */
   int tile;           /* fixed output tile edge, 0 when chosen per image */
-  int sat_shift;      /* -1: q is chosen per image (bf_image_geometry) */
+  int sat_shift;      /* q (term values stored as round(v 2^q)); -1: chosen per image */
   double T_s;         /* spatial truncation r + 1/2 */
   double T_r;         /* K_r^{-1}(eps) */
   double T;           /* range series half-interval max(T_r, span) */
   double den_floor;   /* out = I where den <= den_floor (1e-7 sum |K~_s|) */
+  int n_quads;        /* taps grouped in symmetric quadruplets (one box sum each) */
+  int n_single;       /* taps outside any quadruplet */
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);
 
 /* Tiling of an H x W image under a plan: the table tile edge, the shift q
- * (term values are stored as round(v * 2^q) in int32; (tile + 2r)^2 2^q is
- * kept below 2^31) and the workspace bytes.  Any pointer may be NULL. */
+ * and the workspace bytes.  Term values are stored as round(v 2^q) in int32
+ * tables summed with wrapping 32-bit adds; the kernels use only box
+ * differences of a table, exact modulo 2^32, so q is the largest shift with
+ * (2r + 1)^2 (gmax 2^q + 1) <= 2^31 - 1 (at most 24) and does not depend on
+ * the tile.  For a plan with lone taps (bf_plan_info_t.n_single > 0) raw table
+ * values are read and q instead keeps (tile + 2r)^2 (gmax 2^q + 1) in range.
+ * Any pointer may be NULL. */
 bf_status_t bf_image_geometry(bf_plan_t plan, int H, int W, int *tile, int *sat_shift,
                               size_t *ws_bytes);
 

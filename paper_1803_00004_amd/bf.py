@@ -47,7 +47,7 @@ class PlanInfo(ctypes.Structure):
                 ("n_taps", ctypes.c_int), ("n_tap_rows", ctypes.c_int), ("n_tap_cols", ctypes.c_int),
                 ("n_images", ctypes.c_int), ("tile", ctypes.c_int), ("sat_shift", ctypes.c_int),
                 ("T_s", ctypes.c_double), ("T_r", ctypes.c_double), ("T", ctypes.c_double),
-                ("den_floor", ctypes.c_double)]
+                ("den_floor", ctypes.c_double), ("n_quads", ctypes.c_int), ("n_single", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -23,7 +23,8 @@ bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 bf::Geometry geometry_of(const bf_plan_s *p, int H, int W) {
   int tile = 0, q = 0;
-  bf::choose_tiling(H, W, p->fit.radius, p->host_tables.n_terms, p->tile, p->gmax, &tile, &q);
+  const int box_edge = p->host_tables.n_single == 0 ? 2 * p->fit.radius + 1 : 0;
+  bf::choose_tiling(H, W, p->fit.radius, p->host_tables.n_terms, p->tile, p->gmax, box_edge, &tile, &q);
   return bf::make_geometry(H, W, tile, p->fit.radius, p->host_tables.n_images, q);
 }
 
@@ -247,15 +248,17 @@ bf_status_t bf_filter(bf_plan_t plan, const void *I, float *out, int H, int W, v
                            static_cast<int32_t *>(plan->own_ws), stream);
 }
 
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
 bf_status_t bf_batch_workspace_size(const bf_plan_t *plans, int n, const int *H, const int *W,
                                     size_t *bytes) {
   if (!plans || !H || !W || !bytes || n < 0) return BF_ERR_INVALID_ARG;
-  size_t need = 0;
+  size_t need = bf::kBatchHeadBytes;
   for (int i = 0; i < n; ++i) {
     size_t b = 0;
     bf_status_t st = bf_workspace_size(plans[i], H[i], W[i], &b);
     if (st != BF_OK) return st;
-    need = std::max(need, b);
+    need += align256(b);
   }
   *bytes = need;
   return BF_OK;
@@ -264,20 +267,27 @@ bf_status_t bf_batch_workspace_size(const bf_plan_t *plans, int n, const int *H,
 bf_status_t bf_filter_batch(const bf_plan_t *plans, int n, const void *const *I, float *const *out,
                             const int *H, const int *W, void *ws, size_t ws_bytes, void *stream) {
   if (!plans || !I || !out || !H || !W || n < 0) return BF_ERR_INVALID_ARG;
-  size_t need = 0;
+  if (n == 0) return BF_OK;
+  std::vector<bf::BatchItem> items(n);
+  size_t off = bf::kBatchHeadBytes;
   for (int i = 0; i < n; ++i) {
     bf_status_t st = check_image(plans[i], I[i], out[i], H[i], W[i]);
     if (st != BF_OK) return st;
-    need = std::max(need, geometry_of(plans[i], H[i], W[i]).bytes);
+    bf::BatchItem &it = items[i];
+    it.dev = plans[i]->dev_tables;
+    it.host = &plans[i]->host_tables;
+    it.g = geometry_of(plans[i], H[i], W[i]);
+    it.I = I[i];
+    it.out = out[i];
+    it.ws = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + off);
+    off += align256(it.g.bytes);
   }
-  if (n > 0 && (!ws || ws_bytes < need)) return BF_ERR_INVALID_ARG;
-  for (int i = 0; i < n; ++i) {
-    const bf::Geometry g = geometry_of(plans[i], H[i], W[i]);
-    bf_status_t st = bf::launch_filter(plans[i]->dev_tables, plans[i]->host_tables, g, I[i], out[i],
-                                       nullptr, nullptr, static_cast<int32_t *>(ws), stream);
-    if (st != BF_OK) return st;
-  }
-  return BF_OK;
+  if (!ws || ws_bytes < off) return BF_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i)  // outputs must not overlap each other
+    for (int j = i + 1; j < n; ++j)
+      if (ranges_overlap(out[i], (size_t)H[i] * W[i] * 4, out[j], (size_t)H[j] * W[j] * 4))
+        return BF_ERR_INVALID_ARG;
+  return bf::launch_batch(items.data(), n, static_cast<uint32_t *>(ws), stream);
 }
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
@@ -291,7 +301,15 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   info->n_tap_cols = (int)f.col_off.size();
   info->n_images = plan->host_tables.n_images;
   info->tile = plan->tile;
-  info->sat_shift = -1;
+  info->n_quads = plan->host_tables.n_quads;
+  info->n_single = plan->host_tables.n_single;
+  if (plan->host_tables.n_single == 0) {  // q depends on r and gmax only
+    int tile = 0, q = 0;
+    bf::choose_tiling(64, 64, f.radius, plan->host_tables.n_terms, 64, plan->gmax, 2 * f.radius + 1, &tile, &q);
+    info->sat_shift = q;
+  } else {
+    info->sat_shift = -1;
+  }
   info->T_s = f.T_s;
   info->T_r = f.T_r;
   info->T = f.T;

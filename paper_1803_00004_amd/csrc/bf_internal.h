@@ -16,6 +16,8 @@ constexpr int kMaxTaps = 256;      // nonzero summed-area-table taps (padded to 
 constexpr int kMaxImages = 4 * kMaxTerms;  // term images (tables) per filter call
 constexpr int kMaxChunks = 8;      // 256-column chunks of one table row (table width <= 2048)
 constexpr int kKA_Threads = 256;   // summed-area-table kernel block size (upper bound)
+constexpr int kMaxBatch = 24;      // images per batched launch (descriptors travel as kernel arguments)
+constexpr size_t kBatchHeadBytes = 256;  // batch workspace prefix: the K-B work-queue heads
 
 // Host-side result of the FP64 fit (Sec. IV, App. A/B).
 struct Fit {
@@ -88,11 +90,17 @@ Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat
 
 // Table tile and fixed-point shift for one image: `fixed_tile` if nonzero,
 // else the largest of 512, 256, 128, 64 that gives >= 2048 term waves with a
-// table row of <= 768 columns (the smallest such tile otherwise); q is the
-// largest shift with (tile + 2r)^2 2^q gmax <= 2^31 - 1, at most 24.
+// table row of <= 768 columns (the smallest such tile otherwise).  Term values
+// are stored as round(v * 2^q) in int32 and tables are summed with wrapping
+// 32-bit adds.  When every tap belongs to a symmetric quadruplet
+// (box_edge = 2r + 1 > 0) the kernels only ever use box differences, which
+// are exact modulo 2^32, so q is the largest shift with
+// box_edge^2 (gmax 2^q + 1) <= 2^31 - 1 and does not depend on the tile; with
+// lone taps (box_edge = 0) raw table values are used and q keeps the whole
+// tile table in range: (tile + 2r)^2 (gmax 2^q + 1) <= 2^31 - 1.  q <= 24.
 // A pure function of its arguments, so every call path tiles an image alike.
-void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int *tile,
-                   int *sat_shift);
+void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int box_edge,
+                   int *tile, int *sat_shift);
 
 // Row pitch (int32 elements) of the LDS tile kernel's staged table region for
 // a region `width` columns wide: one of the compiled pitches, or 0 if none fits.
@@ -103,6 +111,22 @@ int lds_pitch_for(int width);
 bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geometry &g,
                           const void *I, float *out, float *num, float *den, int32_t *ws,
                           void *stream);
+
+// One image of a batch: its plan tables (device and host copies), geometry,
+// buffers and its own region of the batch workspace.
+struct BatchItem {
+  const DevTables *dev;
+  const DevTables *host;
+  Geometry g;
+  const void *I;
+  float *out;
+  int32_t *ws;
+};
+
+// Launch a batch on `stream`: one K-A and one K-B launch per group of at most
+// kMaxBatch images of one input type.  `heads` is kBatchHeadBytes of device
+// memory for the K-B work queues.
+bf_status_t launch_batch(const BatchItem *items, int n, uint32_t *heads, void *stream);
 
 // Optional per-kernel event recording (bf_profile_enable); kernel 0 / 1.
 void profile_mark(int kernel, int begin, void *stream);

@@ -18,7 +18,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "bf_internal.h"
 
@@ -60,15 +62,16 @@ __device__ __forceinline__ void load_pixel(const void *I, long long idx, float *
 // Inclusive prefix sum over the 64 lanes of a wave with DPP moves: partial
 // sums within each 16-lane row (row_shr 1, 2, 3, then 4 and 8 on the upper
 // banks), then the row totals carried by row_bcast:15 and row_bcast:31.
-__device__ __forceinline__ int wave_inclusive_scan(int v) {
-  int x = v;
-  x += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
-  x += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
-  x += __builtin_amdgcn_update_dpp(0, v, 0x113, 0xf, 0xf, true);   // row_shr:3
-  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xe, false);  // row_shr:4, lanes 4..15 of a row
-  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xc, false);  // row_shr:8, lanes 8..15 of a row
-  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
-  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+// Sums wrap modulo 2^32 (unsigned arithmetic).
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  uint32_t x = v;
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);   // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);   // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x113, 0xf, 0xf, true);   // row_shr:3
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xe, false);  // row_shr:4, lanes 4..15 of a row
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xc, false);  // row_shr:8, lanes 8..15 of a row
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
   return x;
 }
 
@@ -86,14 +89,13 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
 constexpr int kPF = 4;
 
 template <int G, bool U8>
-__global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageParams p,
-                                             const DevTables *__restrict__ tab,
-                                             int32_t *__restrict__ ws) {
+__device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageParams &p,
+                                        const DevTables *__restrict__ tab, int32_t *__restrict__ ws,
+                                        int tile_id, int term_group) {
   // the wave index is uniform; saying so keeps per-term loads scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int term = blockIdx.y * 4 + wave;
+  const int term = term_group * 4 + wave;
   if (term >= p.n_terms) return;
-  const int tile_id = blockIdx.x;
   const int ty = tile_id / p.tiles_x, tx = tile_id - ty * p.tiles_x;
   const int y0 = ty * p.tile, x0 = tx * p.tile;
   const int y1 = min(p.H, y0 + p.tile), x1 = min(p.W, x0 + p.tile);
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageP
 #pragma unroll
   for (int q = 0; q < kPF; ++q) load_row(1 + q, pf[q]);
 
-  int acc[4][G][4];
+  uint32_t acc[4][G][4];  // column sums, wrapping modulo 2^32
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -153,25 +155,25 @@ __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageP
         for (int c = 0; c < 4; ++c) pf[q][g][c] = pf[q + 1][g][c];
     load_row(i + kPF, pf[kPF - 1]);
 
-    int carry[4] = {0, 0, 0, 0};
+    uint32_t carry[4] = {0, 0, 0, 0};
     int32_t *row = base + (long long)i * p.pitch;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      int v[4][4];  // [image][column]
+      uint32_t v[4][4];  // [image][column]
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const float px = cur[g][c];
         const float xs = (U8 ? px * (1.0f / 255.0f) : px) * scale;  // I * 2^q
         if (k0) {
-          v[0][c] = __float2int_rn(xs);
+          v[0][c] = (uint32_t)__float2int_rn(xs);
           v[1][c] = v[2][c] = v[3][c] = 0;
         } else {
           const float fr = phase_rev(f_hi, f_lo, px);
           const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
-          v[0][c] = __float2int_rn(C * xs);
-          v[1][c] = __float2int_rn(S * xs);
-          v[2][c] = __float2int_rn(C * scale);
-          v[3][c] = __float2int_rn(S * scale);
+          v[0][c] = (uint32_t)__float2int_rn(C * xs);
+          v[1][c] = (uint32_t)__float2int_rn(S * xs);
+          v[2][c] = (uint32_t)__float2int_rn(C * scale);
+          v[3][c] = (uint32_t)__float2int_rn(S * scale);
         }
       }
       const int j0 = 4 * lane + 256 * g;
@@ -181,27 +183,33 @@ __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageP
         v[m][1] += v[m][0];
         v[m][2] += v[m][1];
         v[m][3] += v[m][2];
-        const int incl = wave_inclusive_scan(v[m][3]);
-        const int excl = incl - v[m][3] + carry[m];
-        carry[m] += __builtin_amdgcn_readlane(incl, 63);
+        const uint32_t incl = wave_inclusive_scan(v[m][3]);
+        const uint32_t excl = incl - v[m][3] + carry[m];
+        carry[m] += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[m][g][c] += v[m][c] + excl;
         if (j0 < p.pitch)
           *reinterpret_cast<int4 *>(row + m * te + j0) =
-              make_int4(acc[m][g][0], acc[m][g][1], acc[m][g][2], acc[m][g][3]);
+              make_int4((int)acc[m][g][0], (int)acc[m][g][1], (int)acc[m][g][2], (int)acc[m][g][3]);
       }
     }
   }
 }
 
+template <int G, bool U8>
+__global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageParams p,
+                                             const DevTables *__restrict__ tab,
+                                             int32_t *__restrict__ ws) {
+  ka_body<G, U8>(I, p, tab, ws, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
-// K-B: taps, accumulation over range terms, normalisation.
-// Block 64 x 4 pixels, never straddling a tile (tile % 64 == 0).  Table reads
-// are raw buffer loads: the per-thread byte offset stays in a VGPR and the
-// per-tap / per-image offset is a uniform scalar, so addressing costs no
-// vector instructions; loads out of the tile's table range return 0.  Blocks
-// whose taps all fall inside the image take the unclamped path; border
-// blocks clamp every tap to [0, H] x [0, W].
+// K-B, per-pixel form (plans whose staged region or quadruplet count exceeds
+// the LDS tile kernel): one thread per pixel, block 64 x 4 pixels, never
+// straddling a tile (tile % 64 == 0).  Table reads are raw buffer loads with
+// the table offset as a scalar; corners are clamped to [0, H] x [0, W].
+// Quadruplets are box sums differenced in int32 like the tile kernel; lone
+// taps use the table value itself.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
   // raw buffer (stride 0), word 3 = 0x00020000 on gfx9-family targets
@@ -210,6 +218,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint3
 
 __device__ __forceinline__ int load_i32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   return (int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
+
+// Box sum from the four corners of a quadruplet, (a - b) - (c - d) modulo
+// 2^32: exact whenever the box itself fits in int32, even where table
+// entries have wrapped.
+__device__ __forceinline__ int box_of(int a, int b, int c, int d) {
+  return (int)(((uint32_t)a - (uint32_t)b) - ((uint32_t)c - (uint32_t)d));
 }
 
 template <bool U8>
@@ -225,20 +240,14 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
   const int ty = by0 / p.tile, tx = bx0 / p.tile;
   const int tile_id = ty * p.tiles_x + tx;
   const int oy = max(ty * p.tile - p.radius, 0), ox = max(tx * p.tile - p.radius, 0);
-  const bool interior = by0 + tab->tap_dy_min >= 0 && by0 + 3 + tab->tap_dy_max <= p.H &&
-                        bx0 + tab->tap_dx_min >= 0 && bx0 + 63 + tab->tap_dx_max <= p.W;
   const uint32_t te4 = (uint32_t)p.table_elems * 4u;
   const __amdgpu_buffer_rsrc_t rsrc =
       make_rsrc(ws + (long long)tile_id * p.n_images * p.table_elems, te4 * (uint32_t)p.n_images);
-  const int n4 = tab->n_taps4;
-  const int yr = y - oy, xr = x - ox;
-  // interior: the thread's offset at tap (dy_min, dx_min); each tap adds the
-  // uniform, non-negative (dy - dy_min) * pitch + dx - dx_min
-  const int dy0 = tab->tap_dy_min, dx0 = tab->tap_dx_min;
-  const uint32_t voff0 = (uint32_t)((yr + dy0) * p.pitch + xr + dx0) * 4u;
-  auto tap_soff = [&](int i) {
-    return (uint32_t)((tab->tap_dy[i] - dy0) * p.pitch + (tab->tap_dx[i] - dx0)) * 4u;
+  auto corner = [&](int dy, int dx) {
+    const int Y = min(max(y + dy, 0), p.H) - oy, X = min(max(x + dx, 0), p.W) - ox;
+    return (uint32_t)(Y * p.pitch + X) * 4u;
   };
+  const int nq = tab->n_quads, ns = tab->n_single;
 
   float px, xv;
   load_pixel<U8>(I, (long long)y * p.W + x, &px, &xv);
@@ -246,68 +255,50 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
   double num = 0.0, den = 0.0;
   for (int t = 0; t < p.n_terms; ++t) {
     const uint32_t sb = (uint32_t)tab->slot[t] * te4;
+    const bool k0 = tab->k_is_zero[t] != 0;
+    const int nimg = k0 ? 1 : 4;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < nq; ++q) {
+      const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
+      const uint32_t oa = corner(dy, dx), ob = corner(1 - dy, dx);
+      const uint32_t oc = corner(dy, 1 - dx), od = corner(1 - dy, 1 - dx);
+      const double w = tab->quad_w[q];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (m >= nimg) break;
+        const uint32_t so = sb + (uint32_t)m * te4;
+        const int box = box_of(load_i32(rsrc, oa, so), load_i32(rsrc, ob, so), load_i32(rsrc, oc, so),
+                               load_i32(rsrc, od, so));
+        s[m] = __builtin_fma(w, (double)box, s[m]);
+      }
+    }
+    for (int q = 0; q < ns; ++q) {
+      const uint32_t o = corner(tab->single_dy[q], tab->single_dx[q]);
+      const double w = tab->single_w[q];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (m >= nimg) break;
+        s[m] = __builtin_fma(w, (double)load_i32(rsrc, o, sb + (uint32_t)m * te4), s[m]);
+      }
+    }
     const double a = tab->a[t];
-    if (tab->k_is_zero[t]) {
+    if (k0) {
       // numerator a_0 (K * I); denominator a_0 (K * 1) from the clamped corner
       // coordinates (the table of ones is (Y - oy)(X - ox))
-      double c0 = 0.0, d0 = 0.0;
-      for (int i = 0; i < n4; ++i) {
+      double d0 = 0.0;
+      for (int i = 0; i < tab->n_taps4; ++i) {
         const int Y = min(max(y + tab->tap_dy[i], 0), p.H) - oy;
         const int X = min(max(x + tab->tap_dx[i], 0), p.W) - ox;
-        const double w = tab->tap_w[i];
-        const int v = interior ? load_i32(rsrc, voff0, sb + tap_soff(i))
-                               : load_i32(rsrc, (uint32_t)(Y * p.pitch + X) * 4u, sb);
-        c0 = __builtin_fma(w, (double)v, c0);
-        d0 = __builtin_fma(w, (double)(Y * X), d0);
+        d0 = __builtin_fma(tab->tap_w[i], (double)(Y * X), d0);
       }
-      num = __builtin_fma(a, c0 * inv, num);
+      num = __builtin_fma(a * inv, s[0], num);
       den = __builtin_fma(a, d0, den);
       continue;
     }
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    if (interior) {
-      for (int i = 0; i < n4; i += 4) {
-        int v[4][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t so = sb + tap_soff(i + j);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) v[j][m] = load_i32(rsrc, voff0, so + (uint32_t)m * te4);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const double w = tab->tap_w[i + j];
-          s0 = __builtin_fma(w, (double)v[j][0], s0);
-          s1 = __builtin_fma(w, (double)v[j][1], s1);
-          s2 = __builtin_fma(w, (double)v[j][2], s2);
-          s3 = __builtin_fma(w, (double)v[j][3], s3);
-        }
-      }
-    } else {
-      for (int i = 0; i < n4; i += 4) {
-        int v[4][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int Y = min(max(y + tab->tap_dy[i + j], 0), p.H) - oy;
-          const int X = min(max(x + tab->tap_dx[i + j], 0), p.W) - ox;
-          const uint32_t vo = (uint32_t)(Y * p.pitch + X) * 4u;
-#pragma unroll
-          for (int m = 0; m < 4; ++m) v[j][m] = load_i32(rsrc, vo, sb + (uint32_t)m * te4);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const double w = tab->tap_w[i + j];
-          s0 = __builtin_fma(w, (double)v[j][0], s0);
-          s1 = __builtin_fma(w, (double)v[j][1], s1);
-          s2 = __builtin_fma(w, (double)v[j][2], s2);
-          s3 = __builtin_fma(w, (double)v[j][3], s3);
-        }
-      }
-    }
     const float fr = phase_rev(tab->f_hi[t], tab->f_lo[t], px);
     const double C = (double)__builtin_amdgcn_cosf(fr), S = (double)__builtin_amdgcn_sinf(fr);
-    num = __builtin_fma(a * inv, C * s0 + S * s1, num);
-    den = __builtin_fma(a * inv, C * s2 + S * s3, den);
+    num = __builtin_fma(a * inv, C * s[0] + S * s[1], num);
+    den = __builtin_fma(a * inv, C * s[2] + S * s[3], den);
   }
   const long long idx = (long long)y * p.W + x;
   out[idx] = den > tab->den_floor ? (float)(num / den) : xv;
@@ -336,12 +327,14 @@ __device__ __forceinline__ int lds_ld(const int *lds, uint32_t byte_addr) {
   return *reinterpret_cast<const int *>(reinterpret_cast<const char *>(lds) + byte_addr);
 }
 
+// One 64 x 64 output tile of one image; L is the tile's index in the
+// XCD-aware order (below).  Every thread of the block calls it.
 template <int PITCH, int NQ, bool DB, bool U8>
-__global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, ImageParams p,
-                                               const DevTables *__restrict__ tab,
-                                               const int32_t *__restrict__ ws,
-                                               float *__restrict__ out, float *__restrict__ num_out,
-                                               float *__restrict__ den_out) {
+__device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageParams &p,
+                                        const DevTables *__restrict__ tab,
+                                        const int32_t *__restrict__ ws, float *__restrict__ out,
+                                        float *__restrict__ num_out, float *__restrict__ den_out,
+                                        int L) {
   constexpr int NW = 16;                          // waves
   constexpr int PX = 64 / NW;                     // rows of the tile per thread
   constexpr int RS = DB ? 2 * PITCH : PITCH;      // LDS row stride (int32 elements)
@@ -350,15 +343,11 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
   constexpr uint32_t BSTEP = PITCH * 4;           // bytes from buffer 0 to buffer 1
   extern __shared__ int lds[];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // XCD-aware order: blocks are dispatched round-robin over the 8 XCDs, so
-  // XCD k (blockIdx % 8) takes the k-th contiguous eighth of the tiles, walked
-  // in patches of 8 x 4 tiles; the tiles one XCD runs at the same time are
-  // neighbours whose staged halos overlap in that XCD's L2.
+  // XCD-aware order: XCD k takes the k-th contiguous eighth of the tiles
+  // (L in [k per_xcd, (k + 1) per_xcd)), walked in patches of 8 x 4 tiles, so
+  // the tiles one XCD runs at the same time are neighbours whose staged
+  // halos overlap in that XCD's L2.
   const int ntx = (p.W + 63) / 64, nty = (p.H + 63) / 64;
-  const int n_tiles = ntx * nty;
-  const int per_xcd = (n_tiles + 7) / 8;
-  const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (L >= n_tiles) return;
   // patch rows of PH tile rows (the last may be shorter); within one, patches
   // of PW tile columns (the last may be narrower); tiles row-major in a patch
   constexpr int PW = 8, PH = 4;
@@ -465,8 +454,8 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
 #pragma unroll
       for (int i = 0; i < PX; ++i) {
         const uint32_t o = i * PSTEP + bo;
-        const int box = (lds_ld(lds, qa[q][0] + o) - lds_ld(lds, qa[q][1] + o)) -
-                        (lds_ld(lds, qa[q][2] + o) - lds_ld(lds, qa[q][3] + o));
+        const int box = box_of(lds_ld(lds, qa[q][0] + o), lds_ld(lds, qa[q][1] + o),
+                               lds_ld(lds, qa[q][2] + o), lds_ld(lds, qa[q][3] + o));
         s[i] = __builtin_fma(qw[q], (double)box, s[i]);
       }
     }
@@ -546,6 +535,94 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
     out[idx] = den[i] > tab->den_floor ? (float)(num[i] / den[i]) : xv;
     if (num_out) num_out[idx] = (float)num[i];
     if (den_out) den_out[idx] = (float)den[i];
+  }
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs: block b runs on XCD
+// b % 8 and takes the (b / 8)-th tile of that XCD's eighth.
+template <int PITCH, int NQ, bool DB, bool U8>
+__global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, ImageParams p,
+                                               const DevTables *__restrict__ tab,
+                                               const int32_t *__restrict__ ws,
+                                               float *__restrict__ out, float *__restrict__ num_out,
+                                               float *__restrict__ den_out) {
+  const int n_tiles = ((p.W + 63) / 64) * ((p.H + 63) / 64);
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (L >= n_tiles) return;
+  kb_body<PITCH, NQ, DB, U8>(I, p, tab, ws, out, num_out, den_out, L);
+}
+
+// ---------------------------------------------------------------------------
+// Batches: every image of a batch runs in one launch per kernel.  The
+// per-image descriptors travel by value in the kernel arguments (nothing to
+// allocate, copy or keep alive, so a batch can be captured in a graph).
+// K-A: one flat grid over all images' (tile, term group) blocks.  K-B: a
+// persistent grid of one block per CU with 8 work queues, one per XCD: queue
+// k holds, image after image, the k-th eighth of each image's tiles in the
+// XCD-aware order, so an XCD keeps working on neighbouring tiles; a block
+// drains its own XCD's queue, then takes from the others, and exits when all
+// eight are empty.  The queue heads live in the workspace and are zeroed by
+// the K-A launch that precedes every K-B launch on the stream.  Both launches
+// run the same per-image bodies as the single-image kernels, so every output
+// is bitwise the one a single-image call produces.
+// ---------------------------------------------------------------------------
+struct BatchImage {
+  const void *I;
+  float *out;
+  const int32_t *ws;
+  const DevTables *tab;
+  int ka_blocks;  // tiles * term groups
+  int n_tiles;    // 64 x 64 output tiles
+  int per_xcd;    // ceil(n_tiles / 8)
+  ImageParams p;
+};
+
+struct BatchArgs {
+  int n;
+  uint32_t *heads;  // 8 queue heads
+  int ka_start[kMaxBatch + 1];
+  BatchImage img[kMaxBatch];
+};
+
+template <int G, bool U8>
+__global__ __launch_bounds__(256) void ka_batch(BatchArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x < 8) a.heads[threadIdx.x] = 0u;
+  const int b = blockIdx.x;
+  int i = 0;
+  while (i + 1 < a.n && b >= a.ka_start[i + 1]) ++i;
+  const BatchImage &im = a.img[i];
+  const int lb = b - a.ka_start[i];
+  const int tiles = im.p.tiles_x * ((im.p.H + im.p.tile - 1) / im.p.tile);
+  ka_body<G, U8>(im.I, im.p, im.tab, const_cast<int32_t *>(im.ws), lb % tiles, lb / tiles);
+}
+
+template <int PITCH, int NQ, bool DB, bool U8>
+__global__ __launch_bounds__(1024) void kb_batch(BatchArgs a) {
+  __shared__ int item_sh;
+  int q = blockIdx.x & 7;
+  for (int exhausted = 0; exhausted < 8;) {
+    __syncthreads();  // the previous tile is done with LDS and item_sh
+    if (threadIdx.x == 0) item_sh = (int)atomicAdd(&a.heads[q], 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(item_sh);
+    int found = -1, L = 0, base = 0;
+    for (int i = 0; i < a.n; ++i) {
+      const int c = min(max(a.img[i].n_tiles - q * a.img[i].per_xcd, 0), a.img[i].per_xcd);
+      if (item < base + c) {
+        found = i;
+        L = q * a.img[i].per_xcd + (item - base);
+        break;
+      }
+      base += c;
+    }
+    if (found < 0) {  // queue q is empty: move on to the next XCD's queue
+      q = (q + 1) & 7;
+      ++exhausted;
+      continue;
+    }
+    const BatchImage &im = a.img[found];
+    kb_body<PITCH, NQ, DB, U8>(im.I, im.p, im.tab, im.ws, im.out, nullptr, nullptr, L);
   }
 }
 
@@ -629,8 +706,8 @@ static hipError_t launch_kb_tile_any(const DevTables &h, dim3 grid, hipStream_t 
   }
 }
 
-void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int *tile,
-                   int *sat_shift) {
+void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int box_edge,
+                   int *tile, int *sat_shift) {
   int t = fixed_tile;
   if (!t) {
     t = 64;
@@ -641,10 +718,12 @@ void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double
       if (waves >= 2048) break;
     }
   }
-  const double E = t + 2.0 * radius;
-  int q = (int)std::floor(std::log2(2147483647.0 / (E * E * gmax)));
+  const double E = box_edge > 0 ? (double)box_edge : t + 2.0 * radius;
+  const double lim = 2147483647.0 / (E * E);  // bound of |round(v 2^q)| per entry
+  int q = 0;
+  while (q < 24 && gmax * std::ldexp(1.0, q + 1) + 1.0 <= lim) ++q;
   *tile = t;
-  *sat_shift = std::max(0, std::min(24, q));
+  *sat_shift = q;
 }
 
 Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat_shift) {
@@ -664,10 +743,7 @@ Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat
   return g;
 }
 
-bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geometry &g,
-                          const void *I, float *out, float *num, float *den, int32_t *ws,
-                          void *stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
+static ImageParams image_params(const DevTables &host, const Geometry &g) {
   ImageParams p;
   p.H = g.H;
   p.W = g.W;
@@ -680,8 +756,25 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
   p.table_elems = (long long)g.table_elems;
   p.sat_scale = std::ldexp(1.0f, g.sat_shift);
   p.inv_sat_scale = std::ldexp(1.0, -g.sat_shift);
+  return p;
+}
+
+// 256-column chunks of one K-A wave row (the table row of this image)
+static int ka_chunks(const Geometry &g) {
   const int Ew = std::min(g.tile + 2 * g.radius + 1, g.W + 1);
-  const int G = (Ew + 255) / 256;
+  return (Ew + 255) / 256;
+}
+
+static bool kb_tile_eligible(const DevTables &h) {
+  return h.lds_pitch > 0 && kb_region_bytes(h) <= 160 * 1024 && h.n_quads <= 12;
+}
+
+bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geometry &g,
+                          const void *I, float *out, float *num, float *den, int32_t *ws,
+                          void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const ImageParams p = image_params(host, g);
+  const int G = ka_chunks(g);
   if (G > kMaxChunks) return BF_ERR_UNSUPPORTED;
   dim3 ga(g.tiles_y * g.tiles_x, (host.n_terms + 3) / 4), ba(256);
   profile_mark(0, 1, stream);
@@ -692,7 +785,7 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
   // LDS tile kernel when the staged region fits and the quadruplets' corner
   // addresses fit in registers, else the per-pixel kernel
   profile_mark(1, 1, stream);
-  if (host.lds_pitch > 0 && kb_region_bytes(host) <= 160 * 1024 && host.n_quads <= 12) {
+  if (kb_tile_eligible(host)) {
     const int n_tiles = ((g.W + 63) / 64) * ((g.H + 63) / 64);
     dim3 gt(8 * ((n_tiles + 7) / 8));
     e = host.in_u8 ? launch_kb_tile_any<true>(host, gt, s, I, p, dev, ws, out, num, den)
@@ -704,6 +797,151 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
   }
   profile_mark(1, 0, stream);
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
+}
+
+template <bool U8>
+static hipError_t launch_ka_batch(int G, int blocks, hipStream_t s, const BatchArgs &a) {
+  dim3 grid(blocks), block(256);
+  switch (G) {
+    case 1: hipLaunchKernelGGL((ka_batch<1, U8>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((ka_batch<2, U8>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((ka_batch<3, U8>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((ka_batch<4, U8>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((ka_batch<5, U8>), grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((ka_batch<6, U8>), grid, block, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((ka_batch<7, U8>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((ka_batch<8, U8>), grid, block, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <int PITCH, int NQ, bool DB, bool U8>
+static hipError_t launch_kb_batch1(int blocks, size_t lds, hipStream_t s, const BatchArgs &a) {
+  auto k = kb_batch<PITCH, NQ, DB, U8>;
+  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(1024), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int PITCH, bool DB, bool U8>
+static hipError_t launch_kb_batch_nq(int nq, int blocks, size_t lds, hipStream_t s, const BatchArgs &a) {
+  if (nq <= 4) return launch_kb_batch1<PITCH, 4, DB, U8>(blocks, lds, s, a);
+  if (nq <= 8) return launch_kb_batch1<PITCH, 8, DB, U8>(blocks, lds, s, a);
+  return launch_kb_batch1<PITCH, 12, DB, U8>(blocks, lds, s, a);
+}
+
+template <bool U8>
+static hipError_t launch_kb_batch(int pitch, bool db, int nq, int blocks, size_t lds, hipStream_t s,
+                                  const BatchArgs &a) {
+  if (db) return launch_kb_batch_nq<128, true, U8>(nq, blocks, lds, s, a);
+  switch (pitch) {
+    case 128: return launch_kb_batch_nq<128, false, U8>(nq, blocks, lds, s, a);
+    case 160: return launch_kb_batch_nq<160, false, U8>(nq, blocks, lds, s, a);
+    case 176: return launch_kb_batch_nq<176, false, U8>(nq, blocks, lds, s, a);
+    default: return launch_kb_batch_nq<192, false, U8>(nq, blocks, lds, s, a);
+  }
+}
+
+// One chunk of at most kMaxBatch images of one input type.
+static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, int n, uint32_t *heads,
+                                      hipStream_t s) {
+  const bool u8 = items[idx[0]].host->in_u8 != 0;
+  BatchArgs ka{};
+  ka.n = n;
+  ka.heads = heads;
+  int G = 1, blocks = 0;
+  for (int j = 0; j < n; ++j) {
+    const BatchItem &it = items[idx[j]];
+    BatchImage &im = ka.img[j];
+    im.I = it.I;
+    im.out = it.out;
+    im.ws = it.ws;
+    im.tab = it.dev;
+    im.p = image_params(*it.host, it.g);
+    im.ka_blocks = it.g.tiles_y * it.g.tiles_x * ((it.host->n_terms + 3) / 4);
+    im.n_tiles = ((it.g.W + 63) / 64) * ((it.g.H + 63) / 64);
+    im.per_xcd = (im.n_tiles + 7) / 8;
+    ka.ka_start[j] = blocks;
+    blocks += im.ka_blocks;
+    G = std::max(G, ka_chunks(it.g));
+  }
+  ka.ka_start[n] = blocks;
+  if (G > kMaxChunks) return BF_ERR_UNSUPPORTED;
+  profile_mark(0, 1, s);
+  hipError_t e = u8 ? launch_ka_batch<true>(G, blocks, s, ka) : launch_ka_batch<false>(G, blocks, s, ka);
+  profile_mark(0, 0, s);
+  if (e != hipSuccess) return BF_ERR_DEVICE;
+
+  // K-B: images the LDS tile kernel takes go in one persistent launch at the
+  // widest pitch and largest quadruplet count among them; the others run
+  // the per-pixel kernel one by one.
+  BatchArgs kb{};
+  kb.heads = heads;
+  int pitch = 0, nq = 0, tiles = 0, rh = 0;
+  bool db = true;
+  for (int j = 0; j < n; ++j) {
+    const DevTables &h = *items[idx[j]].host;
+    if (!kb_tile_eligible(h)) continue;
+    kb.img[kb.n++] = ka.img[j];
+    pitch = std::max(pitch, h.lds_pitch);
+    nq = std::max(nq, h.n_quads);
+    rh = std::max(rh, 64 + h.tap_dy_max - h.tap_dy_min);
+    db = db && kb_double_buffered(h);
+    tiles += ka.img[j].n_tiles;
+  }
+  profile_mark(1, 1, s);
+  if (kb.n > 0) {
+    db = db && pitch == 128;
+    const size_t lds = (size_t)rh * pitch * sizeof(int32_t) * (db ? 2 : 1);
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      int v = 0;
+      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+    }
+    const int grid = std::min(8 * ((tiles + 7) / 8), 8 * ((n_cu + 7) / 8));
+    e = u8 ? launch_kb_batch<true>(pitch, db, nq, grid, lds, s, kb)
+           : launch_kb_batch<false>(pitch, db, nq, grid, lds, s, kb);
+    if (e != hipSuccess) {
+      profile_mark(1, 0, s);
+      return BF_ERR_DEVICE;
+    }
+  }
+  for (int j = 0; j < n; ++j) {
+    const BatchItem &it = items[idx[j]];
+    if (kb_tile_eligible(*it.host)) continue;
+    const BatchImage &im = ka.img[j];
+    dim3 gb((it.g.W + 63) / 64, (it.g.H + 3) / 4), bb(256);
+    e = u8 ? launch_kb<true>(gb, bb, s, it.I, im.p, it.dev, it.ws, it.out, nullptr, nullptr)
+           : launch_kb<false>(gb, bb, s, it.I, im.p, it.dev, it.ws, it.out, nullptr, nullptr);
+    if (e != hipSuccess) break;
+  }
+  profile_mark(1, 0, s);
+  return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
+}
+
+bf_status_t launch_batch(const BatchItem *items, int n, uint32_t *heads, void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // by input type, costliest first (largest tile count x tables x quadruplets)
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto cost = [&](int i) {
+    const BatchItem &it = items[i];
+    return (double)((it.g.W + 63) / 64) * ((it.g.H + 63) / 64) * it.host->n_images *
+           std::max(1, it.host->n_quads + it.host->n_single);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (items[a].host->in_u8 != items[b].host->in_u8) return items[a].host->in_u8 < items[b].host->in_u8;
+    return cost(a) > cost(b);
+  });
+  for (int j0 = 0; j0 < n;) {
+    int j1 = j0;
+    while (j1 < n && j1 - j0 < kMaxBatch && items[order[j1]].host->in_u8 == items[order[j0]].host->in_u8) ++j1;
+    bf_status_t st = launch_batch_chunk(items, order.data() + j0, j1 - j0, heads, s);
+    if (st != BF_OK) return st;
+    j0 = j1;
+  }
+  return BF_OK;
 }
 
 }  // namespace bf

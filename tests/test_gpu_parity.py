@@ -145,6 +145,97 @@ def test_determinism_and_batch_equals_single(torch_dev):
         assert torch.equal(o, s)
 
 
+def _mixed_batch(torch, n=26, seed=5):
+    """n requests with their own plans, sizes and input types: f32 and u8,
+    ragged shapes, a 1x1 image and a plan whose staged region is too wide
+    for LDS (per-pixel lookup kernel)."""
+    bf = _bf()
+    rng = np.random.default_rng(seed)
+    plans, imgs, specs = [], [], []
+    cache = {}
+    for i in range(n):
+        ss = float(rng.choice([2.0, 3.0, 4.0, 8.0]))
+        sr = float(rng.choice([0.05, 0.1, 0.2, 0.3]))
+        nr = int(min(32, max(8, np.ceil(1.6 / sr))))
+        ns = int(rng.choice([4, 6]))
+        r = int(3 * ss)
+        dtype = "u8" if i % 7 == 3 else "f32"
+        H, W = int(rng.integers(40, 330)), int(rng.integers(40, 330))
+        if i == 5:
+            H = W = 1
+        if i == 11:
+            ss, r, ns, H, W = 24.0, 70, 4, 200, 180
+        key = (ss, r, ns, sr, nr, dtype)
+        if key not in cache:
+            cache[key] = bf.Plan(ss, sr, r, nr, ns, dtype=dtype)
+        plans.append(cache[key])
+        specs.append(key)
+        if dtype == "u8":
+            imgs.append(torch.from_numpy(synth.gen_image_u8(H, W, 4, 0.03, 100 + i)).cuda())
+        else:
+            imgs.append(torch.from_numpy(synth.gen_image(H, W, 4, 0.03, 100 + i)).cuda())
+    return plans, imgs, specs
+
+
+def test_mixed_batch_is_bitwise_single(torch_dev):
+    """More requests than one launch takes (two groups), both input types,
+    both lookup kernels: every output equals its single-image call bit for
+    bit, and one of them is checked against the oracle."""
+    import torch
+    bf = _bf()
+    plans, imgs, specs = _mixed_batch(torch)
+    assert any(p.info.radius == 70 for p in plans)
+    singles = [bf.filter(p, I).clone() for p, I in zip(plans, imgs)]
+    outs = bf.filter_batch(plans, imgs)
+    torch.cuda.synchronize()
+    for i, (o, s) in enumerate(zip(outs, singles)):
+        assert torch.equal(o, s), i
+    j = next(i for i, p in enumerate(plans) if p.info.radius == 70)
+    ss, r, ns, sr, nr, _ = specs[j]
+    ref = oracle.expanded_box(imgs[j].cpu().numpy(), oracle.make_plan(ss, r, ns, sr, nr))
+    err = np.abs(outs[j].cpu().numpy() - ref).max()
+    _report("batch member r=70 (per-pixel kernel)", err)
+    assert err <= TIGHT
+
+
+def test_batch_graph_replays(torch_dev):
+    """A batch captured once in a graph and replayed with new inputs, with
+    eager work in between: every replay equals the eager single-image calls
+    on the inputs of that replay."""
+    import torch
+    bf = _bf()
+    plans, imgs, _ = _mixed_batch(torch, n=6, seed=8)
+    static_in = [I.clone() for I in imgs]
+    outs = [torch.empty(I.shape, dtype=torch.float32, device="cuda") for I in imgs]
+    shapes = [tuple(I.shape) for I in imgs]
+    ws = torch.empty(bf.batch_workspace_size(plans, shapes), dtype=torch.uint8, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bf.filter_batch(plans, static_in, outs=outs, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bf.filter_batch(plans, static_in, outs=outs, ws=ws)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for j, I in enumerate(static_in):
+            if I.dtype == torch.uint8:
+                I.copy_(torch.from_numpy(synth.gen_image_u8(I.shape[0], I.shape[1], 4, 0.03, 900 + 10 * rep + j)))
+            else:
+                I.copy_(torch.from_numpy(synth.gen_image(I.shape[0], I.shape[1], 4, 0.03, 900 + 10 * rep + j)))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        eager = [bf.filter(p, I) for p, I in zip(plans, static_in)]  # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        for j in range(len(plans)):
+            assert torch.equal(outs[j], eager[j]), (rep, j)
+        assert torch.isfinite(junk)
+
+
 def test_cfg2_full_image(torch_dev):
     c = CONFIGS["cfg2_1080p"]
     I = synth.config_image("cfg2_1080p")

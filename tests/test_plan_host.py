@@ -88,21 +88,41 @@ def test_taps_reproduce_oracle_correlation(ss, r, ns, sr, nr):
             assert np.abs(c2 - ref[ty:y1, tx:x1]).max() < 1e-10
 
 
-def test_tiling_keeps_tables_in_int32():
-    """Per-image tiling: q keeps every tile table inside int32 ((tile + 2r)^2 2^q
-    <= 2^31 - 1, and q is the largest such shift up to 24); the tile is a
-    multiple of 64, fixed when the plan fixes it, and a pure function of the
-    image size."""
+def test_tiling_keeps_boxes_in_int32():
+    """Every box difference the kernels form stays inside int32: with all taps
+    in symmetric quadruplets q is the largest shift (<= 24) with
+    (2r + 1)^2 (gmax 2^q + 1) <= 2^31 - 1, the same for every image and tile;
+    the tile is a multiple of 64, fixed when the plan fixes it, and a pure
+    function of the image size."""
     for ss, r, ns, sr, nr in CONFIGS:
         for fixed in (0, 128, 256):
             p = bf.Plan(ss, sr, r, nr, ns, tile=fixed, host_only=True)
+            info = p.info
+            assert info.n_single == 0 and 4 * info.n_quads == info.n_taps
+            B = (2 * r + 1) ** 2
+            q0 = info.sat_shift
+            assert B * (2.0 ** q0 + 1) <= 2 ** 31 - 1
+            assert B * (2.0 ** (q0 + 1) + 1) > 2 ** 31 - 1 or q0 == 24
             for H, W in ((1, 1), (256, 256), (1080, 1920), (4096, 4096), (37, 3000)):
                 tile, q, nbytes = p.geometry(H, W)
                 assert tile % 64 == 0 and (fixed == 0 or tile == fixed)
-                E = tile + 2 * r
-                assert E * E * 2.0 ** q <= 2 ** 31 - 1
-                assert E * E * 2.0 ** (q + 1) > 2 ** 31 - 1 or q == 24
+                assert q == q0
                 assert nbytes == p.workspace_size(H, W) and p.geometry(H, W) == (tile, q, nbytes)
+
+
+def test_symmetric_taps_pair_into_quadruplets():
+    """The expansion is symmetric on each axis, so every tap (dy, dx) has
+    partners (1-dy, dx), (dy, 1-dx), (1-dy, 1-dx) with weights -w, -w, w up to
+    rounding of the fit: all taps group into quadruplets."""
+    for ss, r, ns, sr, nr in CONFIGS:
+        p = bf.Plan(ss, sr, r, nr, ns, host_only=True)
+        dy, dx, w = p.taps()
+        d = {(a, b): c for a, b, c in zip(dy.tolist(), dx.tolist(), w.tolist())}
+        for (a, b), c in d.items():
+            assert abs(d[(1 - a, b)] + c) <= 1e-12 * abs(c)
+            assert abs(d[(a, 1 - b)] + c) <= 1e-12 * abs(c)
+            assert abs(d[(1 - a, 1 - b)] - c) <= 1e-12 * abs(c)
+        assert p.info.n_quads * 4 == len(d)
 
 
 @pytest.mark.parametrize("kw", [dict(sigma_s=0.0, sigma_r=0.1), dict(sigma_s=3.0, sigma_r=-1.0),
@@ -140,3 +160,14 @@ def test_filter_rejects_bad_calls_without_touching_the_device():
     assert L.bf_workspace_size(p.handle, 1080, 1920, ctypes.byref(n)) == bf.BF_OK and n.value > 0
     assert L.bf_plan_destroy(None) == bf.BF_OK
     assert bf.status_string(bf.BF_ERR_DEVICE) == "BF_ERR_DEVICE"
+
+
+def test_batch_workspace_is_the_sum_of_aligned_parts():
+    """A batch keeps every image's tables in its own 256-byte aligned region
+    after 256 bytes of work-queue heads."""
+    ps = [bf.Plan(3.0, 0.1, 9, 8, 4, host_only=True), bf.Plan(8.0, 0.2, 24, 8, 6, host_only=True)]
+    shapes = [(300, 200), (1080, 1920), (1, 1)]
+    plans = [ps[0], ps[1], ps[0]]
+    total = bf.batch_workspace_size(plans, shapes)
+    parts = [p.workspace_size(h, w) for p, (h, w) in zip(plans, shapes)]
+    assert total == 256 + sum((b + 255) // 256 * 256 for b in parts)
