@@ -185,6 +185,76 @@ bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, i
 bf_status_t bf_profile_enable(int on);
 bf_status_t bf_profile_read(double ms[2], int launches[2]);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over bf_filter_batch.
+ *
+ * Requests (plan, device image, device output) are queued in arrival order.
+ * Whenever a stream is free, the longest prefix of the queue whose batch
+ * workspace fits in the largest free block of the server's workspace arena
+ * (and has at most max_batch requests) is launched as one batch on that
+ * stream; up to n_streams batches run at once, so requests that arrive while
+ * others are on the GPU are admitted as streams and memory free up and
+ * their work overlaps on the device.  The queue head is never overtaken
+ * (no starvation); a request whose workspace cannot fit the whole arena is
+ * completed with BF_ERR_OUT_OF_MEMORY.  Each result is bitwise the one a
+ * single bf_filter call produces (bf_filter_batch contract).
+ *
+ * The server owns its arena (one device allocation of hbm_budget bytes at
+ * create) and its streams; the caller owns plans, images and outputs and
+ * keeps them alive until the request completes.  Completions are found by
+ * bf_server_poll, which never blocks; `now` is the caller's clock, recorded
+ * as the completion time.  Not thread-safe: one thread drives a server.
+ *
+ * BF_SERVER_DRY_RUN does no device work at all (no arena, no streams, no
+ * launches; plans may be host-only and pointers are not dereferenced): a
+ * batch completes when `now` passes its simulated end, launch time plus its
+ * pixel count / dry_rate.  It exercises the same queue, admission and
+ * arena logic, for tests without a GPU.
+ * ------------------------------------------------------------------------ */
+typedef struct bf_server_s *bf_server_t;
+
+#define BF_SERVER_DRY_RUN 1u
+
+typedef struct {
+  size_t hbm_budget; /* workspace arena bytes; 0 -> 16 GiB */
+  int max_batch;     /* requests per batch; 0 -> 32 */
+  int n_streams;     /* batches in flight at once; 0 -> 2 (at most 8) */
+  unsigned flags;    /* BF_SERVER_DRY_RUN */
+  double dry_rate;   /* dry run: pixels per second of one batch; 0 -> 1e9 */
+} bf_server_opts_t;
+
+typedef struct {
+  unsigned long long tag; /* the caller's request tag */
+  bf_status_t status;     /* BF_OK or the error of its batch */
+  int batch;              /* sequence number of the batch it ran in (-1: none) */
+  int batch_size;         /* requests in that batch */
+  double t_launch;        /* `now` when its batch was launched */
+  double t_done;          /* `now` of the poll that found it complete */
+} bf_completion_t;
+
+typedef struct {
+  long long submitted, completed, batches;
+  int peak_batches_in_flight;
+  int peak_requests_in_flight;
+  size_t peak_arena_bytes; /* high-water mark of arena bytes held by batches */
+  size_t arena_bytes;      /* arena size */
+  long long batch_size_hist[65]; /* batches of size b (b >= 64 counted at 64) */
+} bf_server_stats_t;
+
+bf_status_t bf_server_create(bf_server_t *server, const bf_server_opts_t *opts);
+/* Waits for the batches in flight, then frees the arena and the streams. */
+bf_status_t bf_server_destroy(bf_server_t server);
+/* Queue one request; validated now (plan, sizes, pointers, dtype). */
+bf_status_t bf_server_submit(bf_server_t server, bf_plan_t plan, const void *I, float *out, int H,
+                             int W, unsigned long long tag, double now);
+/* Retire finished batches, launch new ones, and return up to `capacity`
+ * completions (the rest are returned by later polls). */
+bf_status_t bf_server_poll(bf_server_t server, double now, bf_completion_t *done, int capacity,
+                           int *n_done);
+/* Requests queued but not launched, and requests in flight. */
+bf_status_t bf_server_pending(bf_server_t server, int *queued, int *in_flight);
+bf_status_t bf_server_stats(bf_server_t server, bf_server_stats_t *stats);
+
 const char *bf_status_string(bf_status_t s);
 
 /* Library version string. */

@@ -24,6 +24,8 @@ EXPORTED = [
     "bf_filter_parts", "bf_batch_workspace_size", "bf_filter_batch", "bf_plan_query",
     "bf_image_geometry", "bf_plan_range_terms", "bf_plan_spatial_kernel", "bf_plan_taps", "bf_plan_spatial_groups",
     "bf_profile_enable", "bf_profile_read", "bf_status_string", "bf_version",
+    "bf_server_create", "bf_server_destroy", "bf_server_submit", "bf_server_poll", "bf_server_pending",
+    "bf_server_stats",
 ]
 
 
@@ -269,3 +271,82 @@ def filter_batch(plans, images, outs=None, ws=None, stream=None):
                                ws.numel() * ws.element_size(), _stream_handle(stream))
     _check(st, "bf_filter_batch")
     return outs
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+BF_SERVER_DRY_RUN = 1
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_batch", ctypes.c_int), ("n_streams", ctypes.c_int),
+                ("flags", ctypes.c_uint), ("dry_rate", ctypes.c_double)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_ulonglong), ("status", ctypes.c_int), ("batch", ctypes.c_int),
+                ("batch_size", ctypes.c_int), ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong), ("batches", ctypes.c_longlong),
+                ("peak_batches_in_flight", ctypes.c_int), ("peak_requests_in_flight", ctypes.c_int),
+                ("peak_arena_bytes", ctypes.c_size_t), ("arena_bytes", ctypes.c_size_t),
+                ("batch_size_hist", ctypes.c_longlong * 65)]
+
+
+class Server:
+    """Request loop of the library (bf_server_*): queue, HBM-budget admission,
+    continuous batching over several streams."""
+
+    def __init__(self, hbm_budget=0, max_batch=0, n_streams=0, dry_run=False, dry_rate=0.0):
+        o = _ServerOpts(int(hbm_budget), int(max_batch), int(n_streams),
+                        BF_SERVER_DRY_RUN if dry_run else 0, float(dry_rate))
+        h = ctypes.c_void_p()
+        _check(lib().bf_server_create(ctypes.byref(h), ctypes.byref(o)), "bf_server_create")
+        self.handle = h
+        self._buf = (Completion * 256)()
+
+    def submit(self, plan, I, out, tag, now, H=None, W=None):
+        """I, out: torch tensors (or, for a dry run, H and W with any nonzero
+        integers standing in for the pointers)."""
+        if H is None:
+            H, W = _image_args(plan, I)
+            ip, op = I.data_ptr(), out.data_ptr()
+        else:
+            ip, op = I, out
+        st = lib().bf_server_submit(self.handle, plan.handle, ctypes.c_void_p(ip), ctypes.c_void_p(op),
+                                    int(H), int(W), ctypes.c_ulonglong(tag), ctypes.c_double(now))
+        _check(st, "bf_server_submit")
+
+    def poll(self, now):
+        n = ctypes.c_int()
+        out = []
+        while True:
+            _check(lib().bf_server_poll(self.handle, ctypes.c_double(now), self._buf, len(self._buf),
+                                        ctypes.byref(n)), "bf_server_poll")
+            out.extend(Completion.from_buffer_copy(self._buf[i]) for i in range(n.value))
+            if n.value < len(self._buf):
+                return out
+
+    def pending(self):
+        q, f = ctypes.c_int(), ctypes.c_int()
+        _check(lib().bf_server_pending(self.handle, ctypes.byref(q), ctypes.byref(f)), "bf_server_pending")
+        return q.value, f.value
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().bf_server_stats(self.handle, ctypes.byref(s)), "bf_server_stats")
+        return s
+
+    def close(self):
+        if self.handle:
+            lib().bf_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

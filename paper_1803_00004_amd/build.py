@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbf.so")
-SOURCES = ["plan.cpp", "api.cpp", "profile.cpp", "kernels.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "profile.cpp", "server.cpp", "kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

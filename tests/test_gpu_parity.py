@@ -289,3 +289,35 @@ def test_argument_errors_on_device(torch_dev):
     assert L.bf_filter_ws(p.handle, ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                           64, 64, ctypes.c_void_p(ws.data_ptr()), need, s) == bf.BF_OK
     torch.cuda.synchronize()
+
+
+def test_served_results_equal_alone(torch_dev):
+    """A short served stream (Poisson arrivals, mixed sizes and sigmas)
+    through the native request loop: every request completes, and each
+    result is bitwise the single-image result, whatever it was batched and
+    overlapped with."""
+    import torch
+    bf = _bf()
+    from paper_1803_00004_amd import serve
+    reqs = synth.gen_stream(n=40, rate_hz=20000.0, seed=14, hw_lo=48, hw_hi=400)
+    plans = serve.make_plans(reqs)
+    imgs = [torch.from_numpy(serve._gen_one(r)).cuda() for r in reqs]
+    outs = [torch.full(I.shape, -1.0, device="cuda") for I in imgs]
+    srv = bf.Server(hbm_budget=2 << 30, max_batch=6, n_streams=2)
+    done, makespan = serve.run_open_loop(srv, reqs, plans, imgs, outs)
+    st = srv.stats()
+    srv.close()
+    assert sorted(done) == list(range(len(reqs)))
+    assert all(c.status == bf.BF_OK for c in done.values())
+    assert st.batches < len(reqs)
+    alone = [torch.empty_like(o) for o in outs]
+    serve.run_plain(reqs, plans, imgs, alone)
+    for i in range(len(reqs)):
+        assert torch.equal(outs[i], alone[i]), i
+    lat = serve.latency_summary(reqs, done)
+    print("[served] 40 requests: batches %d, peak in flight %d batches / %d requests, p50 %.2f ms, p99 %.2f ms"
+          % (st.batches, st.peak_batches_in_flight, st.peak_requests_in_flight, lat["p50_ms"], lat["p99_ms"]))
+    r0 = reqs[3]
+    ref = oracle.expanded_box(imgs[3].cpu().numpy(), oracle.make_plan(r0["sigma_s"], r0["radius"], r0["n_spatial"],
+                                                                      r0["sigma_r"], r0["n_range"]))
+    assert np.abs(outs[3].cpu().numpy() - ref).max() <= TIGHT
