@@ -191,6 +191,7 @@ def main():
     ap.add_argument("--workload", default="cfg2_1080p",
                     choices=["cfg1_256", "cfg2_1080p", "cfg3_4096", "cfg4_served", "cfg5_4096_u8"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (no error check)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (heuristic tiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run one device copy of MIB MiB (a reference kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -224,8 +225,14 @@ def main():
     dev = torch.device("cuda:0")
     I = torch.from_numpy(I_host).to(dev)
     out = torch.empty((H, W), dtype=torch.float32, device=dev)
-    ws = bf.workspace(plan, H, W, dev)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tuned = plan.autotune(H, W, reps=5, stream=stream)
+        log("[bench] autotuner: table tile %d (%.0f ms)" % (tuned, (time.perf_counter() - t0) * 1e3))
+    tile, q, ws_bytes = plan.geometry(H, W)
+    ws = bf.workspace(plan, H, W, dev)
 
     for _ in range(args.warmup):
         bf.filter(plan, I, out=out, ws=ws, stream=stream)
@@ -258,31 +265,16 @@ def main():
     log("[bench] %.4f ms/step  %.1f Mpix/s  kernels: tables %.4f ms, lookup %.4f ms"
         % (ms_per_step, mpix, k_avg[0], k_avg[1]))
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel, from algorithmic work per launch
     px = H * W
     in_b = 1 if c["dtype"] == "u8" else 4
     n_img = info.n_images
     ka_bytes = px * (4 * n_img + in_b)             # write every table once, read I
     kb_bytes = px * (4 * n_img + in_b + 4)         # read every table once, read I, write out
     kb_flops = px * 2.0 * n_img * info.n_taps      # one FP64 FMA per tap per table
-    names = ["ka_sat", "kb_lookup"]
-    dom = int(np.argmax(k_avg))
-    if dom == 0:
-        achieved = ka_bytes / (k_avg[0] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS}
-    else:
-        gbs = kb_bytes / (k_avg[1] * 1e-3) / 1e9
-        tfl = kb_flops / (k_avg[1] * 1e-3) / 1e12
-        if gbs / HBM_PEAK_GBS >= tfl / FP64_PEAK_TFLOPS:
-            roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": gbs / HBM_PEAK_GBS}
-        else:
-            roof = {"bound": "alu", "achieved": tfl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": tfl / FP64_PEAK_TFLOPS}
-    roof["kernel"] = names[dom]
-    roof["kernel_ms"] = k_avg[dom]
-    roof["traffic"] = recorded_traffic(args.workload, names[dom])
+    kb_name = "kb_tile" if info.lookup_kernel == 1 else "kb_lookup"
+    roof, dom = kb_roofline(k_avg, [1, 1], ka_bytes, kb_bytes, kb_flops, kb_name)
+    roof["traffic"] = recorded_traffic(args.workload, roof["kernel"])
 
     result = {
         "metric": METRIC, "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1,
@@ -292,9 +284,10 @@ def main():
         "config": {"workload": "%s: %dx%d %s, Gaussian sigma_s=%g r=%d, sigma_r=%g, N_r=%d, N_s=%d"
                    % (args.workload, W, H, c["dtype"], c["sigma_s"], c["radius"], c["sigma_r"],
                       c["n_range"], c["n_spatial"]),
-                   "H": H, "W": W, "tile": info.tile, "n_images": n_img, "n_taps": info.n_taps},
+                   "H": H, "W": W, "table_tile": tile, "autotuned": tuned is not None, "sat_shift": q,
+                   "n_images": n_img, "n_taps": info.n_taps, "workspace_bytes": ws_bytes},
         "plan_ms": round(plan_ms, 2),
-        "kernel_ms": {"ka_sat": round(k_avg[0], 5), "kb_lookup": round(k_avg[1], 5)},
+        "kernel_ms": {"ka_sat": round(k_avg[0], 5), kb_name: round(k_avg[1], 5)},
         "roofline": roof,
     }
 

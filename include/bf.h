@@ -146,6 +146,7 @@ typedef struct {
   double den_floor;   /* out = I where den <= den_floor (1e-7 sum |K~_s|) */
   int n_quads;        /* taps grouped in symmetric quadruplets (one box sum each) */
   int n_single;       /* taps outside any quadruplet */
+  int lookup_kernel;  /* 1: LDS tile lookup kernel, 0: per-pixel lookup kernel */
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);
@@ -175,6 +176,24 @@ bf_status_t bf_plan_taps(bf_plan_t plan, int *dy, int *dx, double *w, int capaci
 
 /* Selected Haar level groups as (level_x, level_y) pairs, level -1 = phi. */
 bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, int capacity);
+
+/* Autotuner.  Times the candidate launch shapes for H x W images under this
+ * plan -- table tiles of 64, 128, 256 and 512 (tile + 2r + 1 <= 1024), each
+ * with the lookup kernel double- and single-buffered where two staged
+ * regions fit -- on a temporary mid-grey image (reps launches each, at least
+ * 3) and keeps the fastest, process-wide, for the plan's shape class (the
+ * radius, term and quadruplet counts, input type) and images in the same
+ * 256-pixel size bucket of H and W.  From then on every call path (bf_filter,
+ * bf_filter_ws, bf_filter_batch, bf_workspace_size, the request loop) uses
+ * it, so the workspace size of those images may change: size workspaces
+ * after tuning.  Results do not change: only plans whose taps all belong to
+ * quadruplets are tuned, and their outputs do not depend on the tiling.
+ * Other plans (lone taps, or a tile fixed in the options) are left as they
+ * are.  Allocates and frees device memory and synchronises `stream`; not for
+ * use under graph capture.  *tile (may be NULL) receives the chosen tile. */
+bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, int *tile);
+/* Forget every tuned shape. */
+bf_status_t bf_autotune_clear(void);
 
 /* Per-kernel timing for measurement.  While enabled, every filter call
  * records HIP events around each of its kernels on the call's stream (all

@@ -25,7 +25,7 @@ EXPORTED = [
     "bf_image_geometry", "bf_plan_range_terms", "bf_plan_spatial_kernel", "bf_plan_taps", "bf_plan_spatial_groups",
     "bf_profile_enable", "bf_profile_read", "bf_status_string", "bf_version",
     "bf_server_create", "bf_server_destroy", "bf_server_submit", "bf_server_poll", "bf_server_pending",
-    "bf_server_stats",
+    "bf_server_stats", "bf_autotune", "bf_autotune_clear",
 ]
 
 
@@ -49,7 +49,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_taps", ctypes.c_int), ("n_tap_rows", ctypes.c_int), ("n_tap_cols", ctypes.c_int),
                 ("n_images", ctypes.c_int), ("tile", ctypes.c_int), ("sat_shift", ctypes.c_int),
                 ("T_s", ctypes.c_double), ("T_r", ctypes.c_double), ("T", ctypes.c_double),
-                ("den_floor", ctypes.c_double), ("n_quads", ctypes.c_int), ("n_single", ctypes.c_int)]
+                ("den_floor", ctypes.c_double), ("n_quads", ctypes.c_int), ("n_single", ctypes.c_int),
+                ("lookup_kernel", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -194,6 +195,14 @@ class Plan:
         _check(lib().bf_image_geometry(self._h, int(H), int(W), ctypes.byref(t), ctypes.byref(q),
                                        ctypes.byref(b)), "bf_image_geometry")
         return t.value, q.value, b.value
+
+    def autotune(self, H, W, reps=5, stream=None):
+        """Time the candidate tilings for H x W images and keep the fastest
+        (bf_autotune); returns the chosen table tile."""
+        t = ctypes.c_int()
+        _check(lib().bf_autotune(self.handle, int(H), int(W), int(reps), _stream_handle(stream), ctypes.byref(t)),
+               "bf_autotune")
+        return t.value
 
     def workspace_size(self, H, W):
         b = ctypes.c_size_t()

@@ -6,6 +6,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <new>
 #include <vector>
 
@@ -21,11 +24,46 @@ bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
   return a0 < b0 + nb && b0 < a0 + na;
 }
 
-bf::Geometry geometry_of(const bf_plan_s *p, int H, int W) {
+// Launch shapes chosen by bf_autotune, per image-size class (256-pixel
+// buckets of H and W) and plan shape.  Only plans whose results do not depend
+// on the tiling are tuned (every tap in a quadruplet: q fixed by the box).
+struct TuneKey {
+  int hb, wb, radius, n_terms, n_images, n_quads, u8;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(hb, wb, radius, n_terms, n_images, n_quads, u8) <
+           std::tie(o.hb, o.wb, o.radius, o.n_terms, o.n_images, o.n_quads, o.u8);
+  }
+};
+struct TuneVal {
+  int tile, kb_single;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tuned;
+
+TuneKey tune_key(const bf_plan_s *p, int H, int W) {
+  const bf::DevTables &h = p->host_tables;
+  return TuneKey{(H + 255) / 256, (W + 255) / 256, p->fit.radius, h.n_terms, h.n_images, h.n_quads, h.in_u8};
+}
+
+bool tunable(const bf_plan_s *p) { return p->tile == 0 && p->host_tables.n_single == 0; }
+
+bf::Geometry geometry_with(const bf_plan_s *p, int H, int W, int tile_override, int kb_single) {
   int tile = 0, q = 0;
   const int box_edge = p->host_tables.n_single == 0 ? 2 * p->fit.radius + 1 : 0;
-  bf::choose_tiling(H, W, p->fit.radius, p->host_tables.n_terms, p->tile, p->gmax, box_edge, &tile, &q);
-  return bf::make_geometry(H, W, tile, p->fit.radius, p->host_tables.n_images, q);
+  bf::choose_tiling(H, W, p->fit.radius, p->host_tables.n_terms, tile_override ? tile_override : p->tile,
+                    p->gmax, box_edge, &tile, &q);
+  bf::Geometry g = bf::make_geometry(H, W, tile, p->fit.radius, p->host_tables.n_images, q);
+  g.kb_single = kb_single;
+  return g;
+}
+
+bf::Geometry geometry_of(const bf_plan_s *p, int H, int W) {
+  if (tunable(p)) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(p, H, W));
+    if (it != g_tuned.end()) return geometry_with(p, H, W, it->second.tile, it->second.kb_single);
+  }
+  return geometry_with(p, H, W, 0, 0);
 }
 
 bf_status_t check_image(const bf_plan_s *p, const void *I, const float *out, int H, int W) {
@@ -290,6 +328,91 @@ bf_status_t bf_filter_batch(const bf_plan_t *plans, int n, const void *const *I,
   return bf::launch_batch(items.data(), n, static_cast<uint32_t *>(ws), stream);
 }
 
+bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, int *tile_out) {
+  if (!plan || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
+  if (plan->flags & BF_FLAG_HOST_ONLY) return BF_ERR_INVALID_ARG;
+  if (!tunable(plan)) {
+    if (tile_out) *tile_out = geometry_of(plan, H, W).tile;
+    return BF_OK;
+  }
+  reps = std::max(reps, 3);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bf::DevTables &h = plan->host_tables;
+  const int r = plan->fit.radius;
+  struct Cand {
+    int tile, single;
+  };
+  std::vector<Cand> cands;
+  const bool db_fits = h.lds_pitch == 128;
+  for (int t : {64, 128, 256, 512}) {
+    if (t + 2 * r + 1 > 1024) continue;
+    if ((t > 64 && (t / 2) >= std::max(H, W))) continue;  // one tile already covers the image
+    cands.push_back({t, 0});
+    if (db_fits) cands.push_back({t, 1});
+  }
+  if (cands.empty()) cands.push_back({64, 0});
+  size_t ws_bytes = 0;
+  for (const Cand &c : cands) ws_bytes = std::max(ws_bytes, geometry_with(plan, H, W, c.tile, c.single).bytes);
+  const size_t in_bytes = (size_t)H * W * (plan->in_dtype == BF_IN_U8 ? 1 : 4);
+  void *I = nullptr, *out = nullptr, *ws = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bf_status_t st = BF_OK;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (I) (void)hipFree(I);
+    if (out) (void)hipFree(out);
+    if (ws) (void)hipFree(ws);
+  };
+  if (hipMalloc(&I, in_bytes) != hipSuccess || hipMalloc(&out, (size_t)H * W * 4) != hipSuccess ||
+      hipMalloc(&ws, ws_bytes) != hipSuccess) {
+    cleanup();
+    return BF_ERR_OUT_OF_MEMORY;
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipMemsetAsync(I, plan->in_dtype == BF_IN_U8 ? 0x80 : 0x3E, in_bytes, s) != hipSuccess) {
+    cleanup();
+    return BF_ERR_DEVICE;
+  }
+  float best_ms = 0;
+  Cand best = cands[0];
+  for (const Cand &c : cands) {
+    const bf::Geometry g = geometry_with(plan, H, W, c.tile, c.single);
+    st = bf::launch_filter(plan->dev_tables, h, g, I, static_cast<float *>(out), nullptr, nullptr,
+                           static_cast<int32_t *>(ws), s);
+    if (st != BF_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) st = BF_ERR_DEVICE;
+    for (int i = 0; i < reps && st == BF_OK; ++i)
+      st = bf::launch_filter(plan->dev_tables, h, g, I, static_cast<float *>(out), nullptr, nullptr,
+                             static_cast<int32_t *>(ws), s);
+    float ms = 0;
+    if (st != BF_OK || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      if (st == BF_OK) st = BF_ERR_DEVICE;
+      break;
+    }
+    if (&c == &cands[0] || ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  if (st == BF_OK && hipStreamSynchronize(s) != hipSuccess) st = BF_ERR_DEVICE;
+  cleanup();
+  if (st != BF_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[tune_key(plan, H, W)] = TuneVal{best.tile, best.single};
+  }
+  if (tile_out) *tile_out = best.tile;
+  return BF_OK;
+}
+
+bf_status_t bf_autotune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
+  return BF_OK;
+}
+
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   if (!plan || !info) return BF_ERR_INVALID_ARG;
   const bf::Fit &f = plan->fit;
@@ -302,6 +425,7 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   info->n_images = plan->host_tables.n_images;
   info->tile = plan->tile;
   info->n_quads = plan->host_tables.n_quads;
+  info->lookup_kernel = bf::lookup_kernel_kind(plan->host_tables);
   info->n_single = plan->host_tables.n_single;
   if (plan->host_tables.n_single == 0) {  // q depends on r and gmax only
     int tile = 0, q = 0;

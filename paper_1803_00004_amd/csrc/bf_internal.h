@@ -84,6 +84,7 @@ struct Geometry {
   int E_max, pitch;                 // max table edge (tile + 2r + 1) and padded row pitch
   size_t table_elems;               // E_max * pitch per table
   size_t bytes;                     // whole workspace
+  int kb_single = 0;                // 1: single-buffered lookup kernel even where two regions fit
 };
 
 Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat_shift);
@@ -127,6 +128,10 @@ struct BatchItem {
 // kMaxBatch images of one input type.  `heads` is kBatchHeadBytes of device
 // memory for the K-B work queues.
 bf_status_t launch_batch(const BatchItem *items, int n, uint32_t *heads, void *stream);
+
+// Which lookup kernel a plan's images use: 1 the LDS tile kernel, 0 the
+// per-pixel kernel.
+int lookup_kernel_kind(const DevTables &h);
 
 // Optional per-kernel event recording (bf_profile_enable); kernel 0 / 1.
 void profile_mark(int kernel, int begin, void *stream);

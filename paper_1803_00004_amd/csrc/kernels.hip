@@ -691,12 +691,12 @@ static hipError_t launch_kb_tile_nq(int nq, dim3 grid, size_t lds, hipStream_t s
 }
 
 template <bool U8>
-static hipError_t launch_kb_tile_any(const DevTables &h, dim3 grid, hipStream_t s, const void *I,
-                                     ImageParams p, const DevTables *tab, const int32_t *ws,
-                                     float *out, float *num, float *den) {
+static hipError_t launch_kb_tile_any(const DevTables &h, bool single, dim3 grid, hipStream_t s,
+                                     const void *I, ImageParams p, const DevTables *tab,
+                                     const int32_t *ws, float *out, float *num, float *den) {
   const size_t lds = kb_region_bytes(h);
   const int nq = h.n_quads;
-  if (kb_double_buffered(h))
+  if (!single && kb_double_buffered(h))
     return launch_kb_tile_nq<128, true, U8>(nq, grid, 2 * lds, s, I, p, tab, ws, out, num, den);
   switch (h.lds_pitch) {
     case 128: return launch_kb_tile_nq<128, false, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
@@ -769,6 +769,8 @@ static bool kb_tile_eligible(const DevTables &h) {
   return h.lds_pitch > 0 && kb_region_bytes(h) <= 160 * 1024 && h.n_quads <= 12;
 }
 
+int lookup_kernel_kind(const DevTables &h) { return kb_tile_eligible(h) ? 1 : 0; }
+
 bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geometry &g,
                           const void *I, float *out, float *num, float *den, int32_t *ws,
                           void *stream) {
@@ -788,8 +790,9 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
   if (kb_tile_eligible(host)) {
     const int n_tiles = ((g.W + 63) / 64) * ((g.H + 63) / 64);
     dim3 gt(8 * ((n_tiles + 7) / 8));
-    e = host.in_u8 ? launch_kb_tile_any<true>(host, gt, s, I, p, dev, ws, out, num, den)
-                   : launch_kb_tile_any<false>(host, gt, s, I, p, dev, ws, out, num, den);
+    const bool single = g.kb_single != 0;
+    e = host.in_u8 ? launch_kb_tile_any<true>(host, single, gt, s, I, p, dev, ws, out, num, den)
+                   : launch_kb_tile_any<false>(host, single, gt, s, I, p, dev, ws, out, num, den);
   } else {
     dim3 gb((g.W + 63) / 64, (g.H + 3) / 4), bb(256);
     e = host.in_u8 ? launch_kb<true>(gb, bb, s, I, p, dev, ws, out, num, den)
@@ -887,7 +890,7 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
     pitch = std::max(pitch, h.lds_pitch);
     nq = std::max(nq, h.n_quads);
     rh = std::max(rh, 64 + h.tap_dy_max - h.tap_dy_min);
-    db = db && kb_double_buffered(h);
+    db = db && kb_double_buffered(h) && !items[idx[j]].g.kb_single;
     tiles += ka.img[j].n_tiles;
   }
   profile_mark(1, 1, s);

@@ -321,3 +321,29 @@ def test_served_results_equal_alone(torch_dev):
     ref = oracle.expanded_box(imgs[3].cpu().numpy(), oracle.make_plan(r0["sigma_s"], r0["radius"], r0["n_spatial"],
                                                                       r0["sigma_r"], r0["n_range"]))
     assert np.abs(outs[3].cpu().numpy() - ref).max() <= TIGHT
+
+
+def test_tiling_and_autotuning_do_not_change_results(torch_dev):
+    """With every tap in a quadruplet the kernels only form exact int32 box
+    sums, so the table tile, the lookup kernel's buffering and the
+    autotuner's choice leave every output bit unchanged."""
+    import torch
+    bf = _bf()
+    I = torch.from_numpy(synth.gen_image(333, 517, 6, 0.03, 77)).cuda()
+    ref = None
+    for tile in (64, 128, 256, 512):
+        p = bf.Plan(8.0, 0.1, 24, 16, 6, tile=tile)
+        o = bf.filter(p, I)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = o.clone()
+        assert torch.equal(o, ref), tile
+    p = bf.Plan(8.0, 0.1, 24, 16, 6)
+    before = bf.filter(p, I).clone()
+    t = p.autotune(333, 517, reps=3)
+    after = bf.filter(p, I)
+    torch.cuda.synchronize()
+    print("[autotune] 333x517 r=24: tile %d" % t)
+    assert t in (64, 128, 256, 512)
+    assert torch.equal(before, ref) and torch.equal(after, ref)
+    bf.lib().bf_autotune_clear()

@@ -158,6 +158,7 @@ def test_filter_rejects_bad_calls_without_touching_the_device():
     assert L.bf_workspace_size(p.handle, 40000, 5, ctypes.byref(ctypes.c_size_t())) == bf.BF_ERR_INVALID_ARG
     n = ctypes.c_size_t()
     assert L.bf_workspace_size(p.handle, 1080, 1920, ctypes.byref(n)) == bf.BF_OK and n.value > 0
+    assert L.bf_autotune(p.handle, 64, 64, 3, None, None) == bf.BF_ERR_INVALID_ARG  # host-only plan
     assert L.bf_plan_destroy(None) == bf.BF_OK
     assert bf.status_string(bf.BF_ERR_DEVICE) == "BF_ERR_DEVICE"
 
