@@ -6,8 +6,9 @@
 //   summed-area table of each term image over the tile plus an r-pixel halo
 //   (recurrences of Eq. sum_sat_recurrence_2D: prefix along the row, then
 //   accumulation down the columns).  Values are stored as round(v * 2^q) in
-//   int32, so every prefix sum and every box difference is exact; q is chosen
-//   per plan so that no tile table can overflow.
+//   int32 (the k = 0 image of 8-bit input as the byte itself) and summed
+//   with wrapping 32-bit adds, so every box difference is exact; q is chosen
+//   so that no box of the window can overflow.
 // K-B (kb_lookup): per output pixel, read the table at the taps of the
 //   spatial expansion (four-reference box sums of Eq. sum_sat_sum_region_2D,
 //   merged at shared corners), accumulate the numerator and denominator of
@@ -165,7 +166,8 @@ __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageP
         const float px = cur[g][c];
         const float xs = (U8 ? px * (1.0f / 255.0f) : px) * scale;  // I * 2^q
         if (k0) {
-          v[0][c] = (uint32_t)__float2int_rn(xs);
+          // 8-bit input: the k = 0 image is the byte itself, summed exactly
+          v[0][c] = U8 ? (uint32_t)px : (uint32_t)__float2int_rn(xs);
           v[1][c] = v[2][c] = v[3][c] = 0;
         } else {
           const float fr = phase_rev(f_hi, f_lo, px);
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
         const int X = min(max(x + tab->tap_dx[i], 0), p.W) - ox;
         d0 = __builtin_fma(tab->tap_w[i], (double)(Y * X), d0);
       }
-      num = __builtin_fma(a * inv, s[0], num);
+      num = __builtin_fma(a * (U8 ? 1.0 / 255.0 : inv), s[0], num);
       den = __builtin_fma(a, d0, den);
       continue;
     }
@@ -459,6 +461,15 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
         s[i] = __builtin_fma(qw[q], (double)box, s[i]);
       }
     }
+    // software pipeline of the quadruplet loop: the reads of two quadruplets
+    // first, then the arithmetic of quadruplet q beside the reads of q + 2
+    __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+#pragma unroll
+    for (int q = 0; q + 2 < NQ; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x002, 5 * PX, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x002, 10 * PX, 0);
     for (int q = 0; q < tab->n_single; ++q) {
       const uint32_t a =
           lb + (uint32_t)((tab->single_dy[q] - dy0) * RS + tab->single_dx[q] - dx0) * 4u + bo;
@@ -466,7 +477,8 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
 #pragma unroll
       for (int i = 0; i < PX; ++i) s[i] = __builtin_fma(w, (double)lds_ld(lds, a + i * PSTEP), s[i]);
     }
-    const double ai = tab->a[t] * inv;
+    // the k = 0 table of 8-bit input holds bytes: scale 1/255 instead of 2^-q
+    const double ai = tab->a[t] * (U8 && part == 4 ? 1.0 / 255.0 : inv);
 #pragma unroll
     for (int i = 0; i < PX; ++i) {
       if (part == 4) {
@@ -580,14 +592,14 @@ struct BatchImage {
 
 struct BatchArgs {
   int n;
-  uint32_t *heads;  // 8 queue heads
+  uint32_t *heads;  // 8 queue heads per lookup launch (two launches: 16)
   int ka_start[kMaxBatch + 1];
   BatchImage img[kMaxBatch];
 };
 
 template <int G, bool U8>
 __global__ __launch_bounds__(256) void ka_batch(BatchArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x < 8) a.heads[threadIdx.x] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < 16) a.heads[threadIdx.x] = 0u;  // two classes x 8 queues
   const int b = blockIdx.x;
   int i = 0;
   while (i + 1 < a.n && b >= a.ka_start[i + 1]) ++i;
@@ -876,32 +888,36 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
   profile_mark(0, 0, s);
   if (e != hipSuccess) return BF_ERR_DEVICE;
 
-  // K-B: images the LDS tile kernel takes go in one persistent launch at the
-  // widest pitch and largest quadruplet count among them; the others run
-  // the per-pixel kernel one by one.
-  BatchArgs kb{};
-  kb.heads = heads;
-  int pitch = 0, nq = 0, tiles = 0, rh = 0;
-  bool db = true;
-  for (int j = 0; j < n; ++j) {
-    const DevTables &h = *items[idx[j]].host;
-    if (!kb_tile_eligible(h)) continue;
-    kb.img[kb.n++] = ka.img[j];
-    pitch = std::max(pitch, h.lds_pitch);
-    nq = std::max(nq, h.n_quads);
-    rh = std::max(rh, 64 + h.tap_dy_max - h.tap_dy_min);
-    db = db && kb_double_buffered(h) && !items[idx[j]].g.kb_single;
-    tiles += ka.img[j].n_tiles;
-  }
+  // K-B: images the LDS tile kernel takes run in persistent launches, one
+  // per buffering class -- double-buffered at pitch 128, and single-buffered
+  // at the widest pitch of the rest -- each at the largest quadruplet count
+  // of its class, with its own 8 queue heads; the others run the per-pixel
+  // kernel one by one.
   profile_mark(1, 1, s);
-  if (kb.n > 0) {
-    db = db && pitch == 128;
-    const size_t lds = (size_t)rh * pitch * sizeof(int32_t) * (db ? 2 : 1);
-    int dev = 0, n_cu = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-      int v = 0;
-      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+  int dev = 0, n_cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+  }
+  for (int cls = 0; cls < 2; ++cls) {
+    BatchArgs kb{};
+    kb.heads = heads + 8 * cls;
+    int pitch = 0, nq = 0, tiles = 0, rh = 0;
+    for (int j = 0; j < n; ++j) {
+      const BatchItem &it = items[idx[j]];
+      const DevTables &h = *it.host;
+      if (!kb_tile_eligible(h)) continue;
+      const bool db = kb_double_buffered(h) && !it.g.kb_single;
+      if (db != (cls == 0)) continue;
+      kb.img[kb.n++] = ka.img[j];
+      pitch = std::max(pitch, h.lds_pitch);
+      nq = std::max(nq, h.n_quads);
+      rh = std::max(rh, 64 + h.tap_dy_max - h.tap_dy_min);
+      tiles += ka.img[j].n_tiles;
     }
+    if (kb.n == 0) continue;
+    const bool db = cls == 0;
+    const size_t lds = (size_t)rh * pitch * sizeof(int32_t) * (db ? 2 : 1);
     const int grid = std::min(8 * ((tiles + 7) / 8), 8 * ((n_cu + 7) / 8));
     e = u8 ? launch_kb_batch<true>(pitch, db, nq, grid, lds, s, kb)
            : launch_kb_batch<false>(pitch, db, nq, grid, lds, s, kb);
