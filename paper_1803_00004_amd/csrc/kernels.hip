@@ -110,6 +110,22 @@ __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageP
   int32_t *base = ws + ((long long)tile_id * p.n_images + tab->slot[term]) * p.table_elems;
   const long long te = p.table_elems;
 
+  // 8-bit input takes 256 values only: each wave tabulates its term's four
+  // quantised values per byte value in LDS, with the very expressions of the
+  // per-pixel path below (same integers), and looks them up per pixel.
+  __shared__ int4 lut8[4][256];
+  if (U8 && !k0) {
+    for (int b = lane; b < 256; b += 64) {
+      const float px = (float)b;
+      const float xs = px * (1.0f / 255.0f) * scale;
+      const float fr = phase_rev(f_hi, f_lo, px);
+      const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
+      lut8[wave][b] = make_int4(__float2int_rn(C * xs), __float2int_rn(S * xs), __float2int_rn(C * scale),
+                                __float2int_rn(S * scale));
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's table is in LDS before it reads it
+  }
+
   // raw pixel values (u8 as integer-valued float) of the rows i .. i + kPF - 1
   float pf[kPF][G][4];
   auto load_row = [&](int i, float (&dst)[G][4]) {
@@ -169,6 +185,12 @@ __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageP
           // 8-bit input: the k = 0 image is the byte itself, summed exactly
           v[0][c] = U8 ? (uint32_t)px : (uint32_t)__float2int_rn(xs);
           v[1][c] = v[2][c] = v[3][c] = 0;
+        } else if (U8) {
+          const int4 e = lut8[wave][(int)px];
+          v[0][c] = (uint32_t)e.x;
+          v[1][c] = (uint32_t)e.y;
+          v[2][c] = (uint32_t)e.z;
+          v[3][c] = (uint32_t)e.w;
         } else {
           const float fr = phase_rev(f_hi, f_lo, px);
           const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
