@@ -102,13 +102,16 @@ bf_status_t bf_workspace_size(bf_plan_t plan, int H, int W, size_t *bytes);
 
 /* Filter one image: out[H*W] (float32, same units as float input, [0, 1] for
  * uint8 input) from I[H*W] (type fixed by the plan).  I and out are device
- * pointers and must not overlap.  Uses a workspace owned by the plan, grown on
- * demand (hipMalloc on first use at a larger size). */
+ * pointers and must not overlap.  Uses one workspace owned by the plan, grown
+ * on demand: the first call at a larger size waits for the device to finish
+ * what it has queued, frees the old workspace and allocates a new one (not
+ * under graph capture; use bf_filter_ws there).  Calls on one plan share that
+ * workspace, so they must be ordered on one stream (or by the caller). */
 bf_status_t bf_filter(bf_plan_t plan, const void *I, float *out, int H, int W, void *stream);
 
 /* As bf_filter with a caller-owned device workspace of ws_bytes >=
- * bf_workspace_size(plan, H, W).  Allocates nothing.  Calls that share a
- * workspace must be ordered on one stream. */
+ * bf_workspace_size(plan, H, W), which must not overlap I or out.  Allocates
+ * nothing.  Calls that share a workspace must be ordered on one stream. */
 bf_status_t bf_filter_ws(bf_plan_t plan, const void *I, float *out, int H, int W, void *ws,
                          size_t ws_bytes, void *stream);
 
@@ -123,7 +126,8 @@ bf_status_t bf_batch_workspace_size(const bf_plan_t *plans, int n, const int *H,
 
 /* Filter n images of possibly different sizes and plans.  plans, I, out, H, W
  * are HOST arrays of n entries (I[i], out[i] are device pointers); ws is a
- * device workspace of >= bf_batch_workspace_size bytes.  If any entry is
+ * device workspace of >= bf_batch_workspace_size bytes.  No output may
+ * overlap another output, any input or the workspace.  If any entry is
  * invalid the whole batch is rejected before anything is enqueued.  Output i
  * is bitwise identical to bf_filter_ws(plans[i], I[i], out[i], H[i], W[i]). */
 bf_status_t bf_filter_batch(const bf_plan_t *plans, int n, const void *const *I, float *const *out,
@@ -263,7 +267,9 @@ typedef struct {
 bf_status_t bf_server_create(bf_server_t *server, const bf_server_opts_t *opts);
 /* Waits for the batches in flight, then frees the arena and the streams. */
 bf_status_t bf_server_destroy(bf_server_t server);
-/* Queue one request; validated now (plan, sizes, pointers, dtype). */
+/* Queue one request; validated now (plan, sizes, pointers, its input and
+ * output not overlapping).  Requests whose buffers overlap each other are
+ * completed with BF_ERR_INVALID_ARG together with their batch. */
 bf_status_t bf_server_submit(bf_server_t server, bf_plan_t plan, const void *I, float *out, int H,
                              int W, unsigned long long tag, double now);
 /* Retire finished batches, launch new ones, and return up to `capacity`

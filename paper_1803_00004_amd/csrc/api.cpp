@@ -256,6 +256,9 @@ bf_status_t bf_filter_parts(bf_plan_t plan, const void *I, float *out, float *nu
   if (st != BF_OK) return st;
   const bf::Geometry g = geometry_of(plan, H, W);
   if (!ws || ws_bytes < g.bytes) return BF_ERR_INVALID_ARG;
+  const size_t px = (size_t)H * W, in_bytes = px * (plan->in_dtype == BF_IN_U8 ? 1 : 4);
+  if (ranges_overlap(ws, g.bytes, I, in_bytes) || ranges_overlap(ws, g.bytes, out, px * 4))
+    return BF_ERR_INVALID_ARG;
   return bf::launch_filter(plan->dev_tables, plan->host_tables, g, I, out, num, den,
                            static_cast<int32_t *>(ws), stream);
 }
@@ -270,9 +273,9 @@ bf_status_t bf_filter(bf_plan_t plan, const void *I, float *out, int H, int W, v
   if (st != BF_OK) return st;
   const bf::Geometry g = geometry_of(plan, H, W);
   if (plan->own_ws_bytes < g.bytes) {
-    // the old workspace may still be read by queued work on `stream`
+    // the old workspace may still be read by queued work, on any stream
     if (plan->own_ws) {
-      if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return BF_ERR_DEVICE;
+      if (hipDeviceSynchronize() != hipSuccess) return BF_ERR_DEVICE;
       (void)hipFree(plan->own_ws);
       plan->own_ws = nullptr;
       plan->own_ws_bytes = 0;
@@ -306,6 +309,7 @@ bf_status_t bf_filter_batch(const bf_plan_t *plans, int n, const void *const *I,
                             const int *H, const int *W, void *ws, size_t ws_bytes, void *stream) {
   if (!plans || !I || !out || !H || !W || n < 0) return BF_ERR_INVALID_ARG;
   if (n == 0) return BF_OK;
+  if (!ws) return BF_ERR_INVALID_ARG;
   std::vector<bf::BatchItem> items(n);
   size_t off = bf::kBatchHeadBytes;
   for (int i = 0; i < n; ++i) {
@@ -320,11 +324,21 @@ bf_status_t bf_filter_batch(const bf_plan_t *plans, int n, const void *const *I,
     it.ws = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + off);
     off += align256(it.g.bytes);
   }
-  if (!ws || ws_bytes < off) return BF_ERR_INVALID_ARG;
-  for (int i = 0; i < n; ++i)  // outputs must not overlap each other
-    for (int j = i + 1; j < n; ++j)
-      if (ranges_overlap(out[i], (size_t)H[i] * W[i] * 4, out[j], (size_t)H[j] * W[j] * 4))
-        return BF_ERR_INVALID_ARG;
+  if (ws_bytes < off) return BF_ERR_INVALID_ARG;
+  // no output may overlap another output, any input or the workspace (the
+  // lookup launch reads every input while it writes every output)
+  auto in_bytes = [&](int i) {
+    return (size_t)H[i] * W[i] * (plans[i]->in_dtype == BF_IN_U8 ? 1 : 4);
+  };
+  for (int i = 0; i < n; ++i) {
+    const size_t oi = (size_t)H[i] * W[i] * 4;
+    if (ranges_overlap(out[i], oi, ws, off) || ranges_overlap(I[i], in_bytes(i), ws, off))
+      return BF_ERR_INVALID_ARG;
+    for (int j = 0; j < n; ++j) {
+      if (j > i && ranges_overlap(out[i], oi, out[j], (size_t)H[j] * W[j] * 4)) return BF_ERR_INVALID_ARG;
+      if (j != i && ranges_overlap(out[i], oi, I[j], in_bytes(j))) return BF_ERR_INVALID_ARG;
+    }
+  }
   return bf::launch_batch(items.data(), n, static_cast<uint32_t *>(ws), stream);
 }
 

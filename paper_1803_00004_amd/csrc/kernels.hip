@@ -1,18 +1,21 @@
 // gfx950 kernels of the N-term bilateral filter.
 //
-// K-A (ka_sat): for one output tile and one range term k, modulate the image
-//   (C = cos(omega_k I), S = sin(omega_k I); term values C*I, S*I, C, S, or I
-//   alone for k = 0 -- the shift identity of Eq. 1D_N_terms) and build the
-//   summed-area table of each term image over the tile plus an r-pixel halo
-//   (recurrences of Eq. sum_sat_recurrence_2D: prefix along the row, then
-//   accumulation down the columns).  Values are stored as round(v * 2^q) in
-//   int32 (the k = 0 image of 8-bit input as the byte itself) and summed
-//   with wrapping 32-bit adds, so every box difference is exact; q is chosen
-//   so that no box of the window can overflow.
-// K-B (kb_lookup): per output pixel, read the table at the taps of the
-//   spatial expansion (four-reference box sums of Eq. sum_sat_sum_region_2D,
-//   merged at shared corners), accumulate the numerator and denominator of
-//   Eq. BF over the range terms and normalise.
+// K-A (ka_sat / ka_body): for one table tile and one range term k, modulate
+//   the image (C = cos(omega_k I), S = sin(omega_k I); term values C*I, S*I,
+//   C, S, or I alone for k = 0 -- the shift identity of Eq. 1D_N_terms) and
+//   build the summed-area table of each term image over the tile plus an
+//   r-pixel halo (recurrences of Eq. sum_sat_recurrence_2D: prefix along the
+//   row, then accumulation down the columns).  Values are stored as
+//   round(v * 2^q) in int32 (the k = 0 image of 8-bit input as the byte
+//   itself) and summed with wrapping 32-bit adds, so every box difference is
+//   exact; q is chosen so that no box of the window can overflow.
+// K-B (kb_tile / kb_body, LDS tile form; kb_lookup, per-pixel form): per
+//   output pixel, the box sums of the spatial expansion's tap quadruplets
+//   (four-reference box sums of Eq. sum_sat_sum_region_2D), accumulated into
+//   the numerator and denominator of Eq. BF over the range terms, and the
+//   normalisation.
+// Batches (ka_batch, kb_batch) run the same per-image bodies over many
+//   images in one launch per kernel.
 //
 // Layout in HBM: one workspace of int32 tables, [tile][image][row][pitch],
 // each table (tile + 2r + 1) x pitch with pitch a multiple of 64 elements.

@@ -292,7 +292,14 @@ bf_status_t bf_server_submit(bf_server_t s, bf_plan_t plan, const void *I, float
   size_t ws = 0;
   bf_status_t st = bf_workspace_size(plan, H, W, &ws);
   if (st != BF_OK) return st;
-  if (!s->dry && (plan->flags & BF_FLAG_HOST_ONLY)) return BF_ERR_INVALID_ARG;
+  if (!s->dry) {
+    if (plan->flags & BF_FLAG_HOST_ONLY) return BF_ERR_INVALID_ARG;
+    // the request's own input and output must not overlap (requests that
+    // overlap each other are rejected with their whole batch)
+    const uintptr_t i0 = (uintptr_t)I, o0 = (uintptr_t)out;
+    const size_t px = (size_t)H * W, ib = px * (plan->in_dtype == BF_IN_U8 ? 1 : 4);
+    if (i0 < o0 + px * 4 && o0 < i0 + ib) return BF_ERR_INVALID_ARG;
+  }
   Request r;
   r.tag = tag;
   r.plan = plan;

@@ -288,6 +288,30 @@ def test_argument_errors_on_device(torch_dev):
                        64, 64, s) == bf.BF_ERR_INVALID_ARG
     assert L.bf_filter_ws(p.handle, ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                           64, 64, ctypes.c_void_p(ws.data_ptr()), need, s) == bf.BF_OK
+    # a workspace overlapping the output is rejected
+    big = torch.empty(need + 64 * 64 * 4, dtype=torch.uint8, device="cuda")
+    assert L.bf_filter_ws(p.handle, ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(big.data_ptr()),
+                          64, 64, ctypes.c_void_p(big.data_ptr() + 256), need, s) == bf.BF_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    # batch: an output over another request's input, or over the workspace, is rejected
+    I2 = torch.rand(64, 64, device="cuda")
+    outs = [torch.empty_like(I), torch.empty_like(I)]
+    shapes = [(64, 64), (64, 64)]
+    bws = torch.empty(bf.batch_workspace_size([p, p], shapes), dtype=torch.uint8, device="cuda")
+    hp = (ctypes.c_void_p * 2)(p.handle.value, p.handle.value)
+    hs = (ctypes.c_int * 2)(64, 64)
+
+    def batch(ip, op, wsp):
+        return L.bf_filter_batch(hp, 2, (ctypes.c_void_p * 2)(*ip), (ctypes.c_void_p * 2)(*op), hs, hs,
+                                 ctypes.c_void_p(wsp), bws.numel(), s)
+    assert batch([I.data_ptr(), I2.data_ptr()], [outs[0].data_ptr(), I2.data_ptr()],
+                 bws.data_ptr()) == bf.BF_ERR_INVALID_ARG
+    assert batch([I.data_ptr(), I2.data_ptr()], [outs[0].data_ptr(), I.data_ptr()],
+                 bws.data_ptr()) == bf.BF_ERR_INVALID_ARG
+    assert batch([I.data_ptr(), I2.data_ptr()], [outs[0].data_ptr(), bws.data_ptr() + 1024],
+                 bws.data_ptr()) == bf.BF_ERR_INVALID_ARG
+    assert batch([I.data_ptr(), I2.data_ptr()], [outs[0].data_ptr(), outs[1].data_ptr()],
+                 bws.data_ptr()) == bf.BF_OK
     torch.cuda.synchronize()
 
 
