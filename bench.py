@@ -183,7 +183,40 @@ def served(args):
     print(json.dumps(result), flush=True)
 
 
+def oracle_one_core(workload, n):
+    """Child-process mode (OMP_NUM_THREADS=1): time oracle T2 on n sampled
+    pixels of the workload's image and print one JSON line."""
+    import oracle
+    import synth
+    from synth.images import CONFIGS
+    c = CONFIGS[workload]
+    I_host = synth.config_image(workload)
+    op = oracle.make_plan(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"])
+    rng = np.random.default_rng(13)
+    ys = rng.integers(0, c["H"], n).astype(np.int32)
+    xs = rng.integers(0, c["W"], n).astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.expanded_brute(I_host, op, ys, xs)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"mpix_s": n / dt / 1e6, "seconds": dt, "pixels": n}))
+
+
+def one_core_baseline(workload, n):
+    """The oracle on one host core, timed in a child process started before
+    this process touches the GPU."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-one-core", workload, str(n)],
+                       env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        log("[bench] one-core oracle failed: %s" % r.stderr[-500:])
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def main():
+    if len(sys.argv) == 4 and sys.argv[1] == "--oracle-one-core":
+        return oracle_one_core(sys.argv[2], int(sys.argv[3]))
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -214,6 +247,12 @@ def main():
     H, W = c["H"], c["W"]
     log("[bench] generating %s %dx%d" % (args.workload, H, W))
     I_host = synth.config_image(args.workload)
+
+    one_core = None
+    if not args.no_cpu:
+        n1 = 1024 if c["H"] * c["W"] > 4 * 1024 * 1024 else 4096  # a few seconds of one core
+        log("[bench] oracle T2 on %d sampled pixels, one core (child process)" % n1)
+        one_core = one_core_baseline(args.workload, n1)
 
     t0 = time.perf_counter()
     plan = bf.Plan(c["sigma_s"], c["sigma_r"], c["radius"], c["n_range"], c["n_spatial"],
@@ -275,6 +314,10 @@ def main():
     kb_name = "kb_tile" if info.lookup_kernel == 1 else "kb_lookup"
     roof, dom = kb_roofline(k_avg, [1, 1], ka_bytes, kb_bytes, kb_flops, kb_name)
     roof["traffic"] = recorded_traffic(args.workload, roof["kernel"])
+    # the whole path against HBM: every table written once and read once, I
+    # read twice, out written once (8 n_img + 2 in_b + 4 bytes per pixel)
+    path_bytes = px * (8 * n_img + 2 * in_b + 4)
+    path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
 
     result = {
         "metric": METRIC, "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1,
@@ -289,6 +332,8 @@ def main():
         "plan_ms": round(plan_ms, 2),
         "kernel_ms": {"ka_sat": round(k_avg[0], 5), kb_name: round(k_avg[1], 5)},
         "roofline": roof,
+        "path_hbm": {"algorithmic_bytes_per_px": 8 * n_img + 2 * in_b + 4, "achieved_gbs": round(path_gbs, 1),
+                     "frac_of_peak": round(path_gbs / HBM_PEAK_GBS, 4)},
     }
 
     if not args.no_cpu:
@@ -322,6 +367,11 @@ def main():
         result["max_abs_err_vs_true_bf_4096px"] = float(np.abs(out_host[ys, xs] - t1).max())
         result["cpu_baseline"] = {"value": round(cpu_mpix, 4), "unit": "Mpix/s", "cores": threads,
                                   "kind": "oracle", "sample": sample, "seconds": round(cpu_s, 2)}
+        if one_core:
+            result["cpu_baseline"]["one_core"] = {
+                "value": round(one_core["mpix_s"], 5), "unit": "Mpix/s", "cores": 1,
+                "sample": "%d random pixels, oracle T2 (FP64 direct sum)" % one_core["pixels"],
+                "seconds": round(one_core["seconds"], 2)}
         log("[bench] max-abs err vs oracle %.3e; oracle %.3f Mpix/s" % (err, cpu_mpix))
     print(json.dumps(result), flush=True)
 
