@@ -183,8 +183,9 @@ bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, i
 
 /* Autotuner.  Times the candidate launch shapes for H x W images under this
  * plan -- table tiles of 64, 128, 256 and 512 (tile + 2r + 1 <= 1024), each
- * with the lookup kernel double- and single-buffered where two staged
- * regions fit -- on a temporary mid-grey image (reps launches each, at least
+ * with one range term or one table per table-kernel wave, and with the
+ * lookup kernel double- and single-buffered where two staged regions fit --
+ * on a temporary mid-grey image (reps launches each, at least
  * 3) and keeps the fastest, process-wide, for the plan's shape class (the
  * radius, term and quadruplet counts, input type) and images in the same
  * 256-pixel size bucket of H and W.  From then on every call path (bf_filter,
@@ -196,6 +197,12 @@ bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, i
  * are.  Allocates and frees device memory and synchronises `stream`; not for
  * use under graph capture.  *tile (may be NULL) receives the chosen tile. */
 bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, int *tile);
+/* Set the launch shape for this plan's shape class and H x W's size bucket
+ * by hand, as bf_autotune would: table tile (a multiple of 64 with
+ * tile + 2r + 1 <= 1024), kb_single (1: single-buffered lookup kernel),
+ * ka_one (1: one table per table-kernel wave).  BF_ERR_UNSUPPORTED for plans
+ * that are not tuned (lone taps or a fixed tile). */
+bf_status_t bf_tuning_set(bf_plan_t plan, int H, int W, int tile, int kb_single, int ka_one);
 /* Forget every tuned shape. */
 bf_status_t bf_autotune_clear(void);
 

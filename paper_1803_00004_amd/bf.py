@@ -25,7 +25,7 @@ EXPORTED = [
     "bf_image_geometry", "bf_plan_range_terms", "bf_plan_spatial_kernel", "bf_plan_taps", "bf_plan_spatial_groups",
     "bf_profile_enable", "bf_profile_read", "bf_status_string", "bf_version",
     "bf_server_create", "bf_server_destroy", "bf_server_submit", "bf_server_poll", "bf_server_pending",
-    "bf_server_stats", "bf_autotune", "bf_autotune_clear",
+    "bf_server_stats", "bf_autotune", "bf_tuning_set", "bf_autotune_clear",
 ]
 
 
@@ -203,6 +203,12 @@ class Plan:
         _check(lib().bf_autotune(self.handle, int(H), int(W), int(reps), _stream_handle(stream), ctypes.byref(t)),
                "bf_autotune")
         return t.value
+
+    def set_tuning(self, H, W, tile, kb_single=0, ka_one=0):
+        """Pin the launch shape for this plan's shape class and size bucket
+        (bf_tuning_set)."""
+        _check(lib().bf_tuning_set(self.handle, int(H), int(W), int(tile), int(kb_single), int(ka_one)),
+               "bf_tuning_set")
 
     def workspace_size(self, H, W):
         b = ctypes.c_size_t()

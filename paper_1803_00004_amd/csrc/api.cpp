@@ -35,7 +35,7 @@ struct TuneKey {
   }
 };
 struct TuneVal {
-  int tile, kb_single;
+  int tile, kb_single, ka_one;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tuned;
@@ -47,13 +47,15 @@ TuneKey tune_key(const bf_plan_s *p, int H, int W) {
 
 bool tunable(const bf_plan_s *p) { return p->tile == 0 && p->host_tables.n_single == 0; }
 
-bf::Geometry geometry_with(const bf_plan_s *p, int H, int W, int tile_override, int kb_single) {
+bf::Geometry geometry_with(const bf_plan_s *p, int H, int W, int tile_override, int kb_single,
+                           int ka_one) {
   int tile = 0, q = 0;
   const int box_edge = p->host_tables.n_single == 0 ? 2 * p->fit.radius + 1 : 0;
   bf::choose_tiling(H, W, p->fit.radius, p->host_tables.n_terms, tile_override ? tile_override : p->tile,
                     p->gmax, box_edge, &tile, &q);
   bf::Geometry g = bf::make_geometry(H, W, tile, p->fit.radius, p->host_tables.n_images, q);
   g.kb_single = kb_single;
+  g.ka_one = ka_one;
   return g;
 }
 
@@ -61,9 +63,10 @@ bf::Geometry geometry_of(const bf_plan_s *p, int H, int W) {
   if (tunable(p)) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(tune_key(p, H, W));
-    if (it != g_tuned.end()) return geometry_with(p, H, W, it->second.tile, it->second.kb_single);
+    if (it != g_tuned.end())
+      return geometry_with(p, H, W, it->second.tile, it->second.kb_single, it->second.ka_one);
   }
-  return geometry_with(p, H, W, 0, 0);
+  return geometry_with(p, H, W, 0, 0, 0);
 }
 
 bf_status_t check_image(const bf_plan_s *p, const void *I, const float *out, int H, int W) {
@@ -354,19 +357,22 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
   const bf::DevTables &h = plan->host_tables;
   const int r = plan->fit.radius;
   struct Cand {
-    int tile, single;
+    int tile, single, one;
   };
   std::vector<Cand> cands;
   const bool db_fits = h.lds_pitch == 128;
   for (int t : {64, 128, 256, 512}) {
     if (t + 2 * r + 1 > 1024) continue;
     if ((t > 64 && (t / 2) >= std::max(H, W))) continue;  // one tile already covers the image
-    cands.push_back({t, 0});
-    if (db_fits) cands.push_back({t, 1});
+    for (int one = 0; one < 2; ++one) {
+      cands.push_back({t, 0, one});
+      if (db_fits) cands.push_back({t, 1, one});
+    }
   }
-  if (cands.empty()) cands.push_back({64, 0});
+  if (cands.empty()) cands.push_back({64, 0, 0});
   size_t ws_bytes = 0;
-  for (const Cand &c : cands) ws_bytes = std::max(ws_bytes, geometry_with(plan, H, W, c.tile, c.single).bytes);
+  for (const Cand &c : cands)
+    ws_bytes = std::max(ws_bytes, geometry_with(plan, H, W, c.tile, c.single, c.one).bytes);
   const size_t in_bytes = (size_t)H * W * (plan->in_dtype == BF_IN_U8 ? 1 : 4);
   void *I = nullptr, *out = nullptr, *ws = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -391,7 +397,7 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
   float best_ms = 0;
   Cand best = cands[0];
   for (const Cand &c : cands) {
-    const bf::Geometry g = geometry_with(plan, H, W, c.tile, c.single);
+    const bf::Geometry g = geometry_with(plan, H, W, c.tile, c.single, c.one);
     st = bf::launch_filter(plan->dev_tables, h, g, I, static_cast<float *>(out), nullptr, nullptr,
                            static_cast<int32_t *>(ws), s);
     if (st != BF_OK) break;
@@ -415,9 +421,19 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
   if (st != BF_OK) return st;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[tune_key(plan, H, W)] = TuneVal{best.tile, best.single};
+    g_tuned[tune_key(plan, H, W)] = TuneVal{best.tile, best.single, best.one};
   }
   if (tile_out) *tile_out = best.tile;
+  return BF_OK;
+}
+
+bf_status_t bf_tuning_set(bf_plan_t plan, int H, int W, int tile, int kb_single, int ka_one) {
+  if (!plan || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
+  if (tile < 64 || tile % 64 || tile + 2 * plan->fit.radius + 1 > 1024 || (kb_single | ka_one) & ~1)
+    return BF_ERR_INVALID_ARG;
+  if (!tunable(plan)) return BF_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[tune_key(plan, H, W)] = TuneVal{tile, kb_single, ka_one};
   return BF_OK;
 }
 

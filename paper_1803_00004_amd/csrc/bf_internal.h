@@ -85,6 +85,7 @@ struct Geometry {
   size_t table_elems;               // E_max * pitch per table
   size_t bytes;                     // whole workspace
   int kb_single = 0;                // 1: single-buffered lookup kernel even where two regions fit
+  int ka_one = 0;                   // 1: one table per table-kernel wave (else one range term)
 };
 
 Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat_shift);

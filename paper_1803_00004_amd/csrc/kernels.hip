@@ -92,14 +92,20 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
 // ---------------------------------------------------------------------------
 constexpr int kPF = 4;
 
-template <int G, bool U8>
+// ONE = false: a wave builds the 1 or 4 tables of one range term (one sin/cos
+// per pixel for all four); ONE = true: a wave builds one table (4x the waves
+// for the same tile, so larger tiles keep the chip busy).  Both store the
+// same integers.
+template <int G, bool U8, bool ONE>
 __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageParams &p,
                                         const DevTables *__restrict__ tab, int32_t *__restrict__ ws,
-                                        int tile_id, int term_group) {
+                                        int tile_id, int unit_group) {
   // the wave index is uniform; saying so keeps per-term loads scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int term = term_group * 4 + wave;
-  if (term >= p.n_terms) return;
+  const int unit = unit_group * 4 + wave;
+  if (unit >= (ONE ? p.n_images : p.n_terms)) return;
+  const int term = ONE ? tab->slot_term[unit] : unit;
+  const int part = ONE ? tab->slot_part[unit] : 0;  // ONE: the table's part (4: k = 0)
   const int ty = tile_id / p.tiles_x, tx = tile_id - ty * p.tiles_x;
   const int y0 = ty * p.tile, x0 = tx * p.tile;
   const int y1 = min(p.H, y0 + p.tile), x1 = min(p.W, x0 + p.tile);
@@ -107,10 +113,10 @@ __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageP
   const int Eh = min(y1 + p.radius, p.H) - oy + 1;
   const int Ew = min(x1 + p.radius, p.W) - ox + 1;
   const bool k0 = tab->k_is_zero[term] != 0;
-  const int nimg = k0 ? 1 : 4;
+  const int nimg = (k0 || ONE) ? 1 : 4;
   const float f_hi = tab->f_hi[term], f_lo = tab->f_lo[term];
   const float scale = p.sat_scale;
-  int32_t *base = ws + ((long long)tile_id * p.n_images + tab->slot[term]) * p.table_elems;
+  int32_t *base = ws + ((long long)tile_id * p.n_images + (ONE ? unit : tab->slot[term])) * p.table_elems;
   const long long te = p.table_elems;
 
   // 8-bit input takes 256 values only: each wave tabulates its term's four
@@ -190,10 +196,19 @@ __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageP
           v[1][c] = v[2][c] = v[3][c] = 0;
         } else if (U8) {
           const int4 e = lut8[wave][(int)px];
-          v[0][c] = (uint32_t)e.x;
-          v[1][c] = (uint32_t)e.y;
-          v[2][c] = (uint32_t)e.z;
-          v[3][c] = (uint32_t)e.w;
+          if (ONE) {
+            v[0][c] = (uint32_t)(part == 0 ? e.x : part == 1 ? e.y : part == 2 ? e.z : e.w);
+          } else {
+            v[0][c] = (uint32_t)e.x;
+            v[1][c] = (uint32_t)e.y;
+            v[2][c] = (uint32_t)e.z;
+            v[3][c] = (uint32_t)e.w;
+          }
+        } else if (ONE) {
+          // the one table's value, by the same expressions as below
+          const float fr = phase_rev(f_hi, f_lo, px);
+          const float t = (part & 1) ? __builtin_amdgcn_sinf(fr) : __builtin_amdgcn_cosf(fr);
+          v[0][c] = (uint32_t)__float2int_rn(t * (part < 2 ? xs : scale));
         } else {
           const float fr = phase_rev(f_hi, f_lo, px);
           const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
@@ -223,11 +238,11 @@ __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageP
   }
 }
 
-template <int G, bool U8>
+template <int G, bool U8, bool ONE>
 __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageParams p,
                                              const DevTables *__restrict__ tab,
                                              int32_t *__restrict__ ws) {
-  ka_body<G, U8>(I, p, tab, ws, blockIdx.x, blockIdx.y);
+  ka_body<G, U8, ONE>(I, p, tab, ws, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -622,7 +637,7 @@ struct BatchArgs {
   BatchImage img[kMaxBatch];
 };
 
-template <int G, bool U8>
+template <int G, bool U8, bool ONE>
 __global__ __launch_bounds__(256) void ka_batch(BatchArgs a) {
   if (blockIdx.x == 0 && threadIdx.x < 16) a.heads[threadIdx.x] = 0u;  // two classes x 8 queues
   const int b = blockIdx.x;
@@ -631,7 +646,7 @@ __global__ __launch_bounds__(256) void ka_batch(BatchArgs a) {
   const BatchImage &im = a.img[i];
   const int lb = b - a.ka_start[i];
   const int tiles = im.p.tiles_x * ((im.p.H + im.p.tile - 1) / im.p.tile);
-  ka_body<G, U8>(im.I, im.p, im.tab, const_cast<int32_t *>(im.ws), lb % tiles, lb / tiles);
+  ka_body<G, U8, ONE>(im.I, im.p, im.tab, const_cast<int32_t *>(im.ws), lb % tiles, lb / tiles);
 }
 
 template <int PITCH, int NQ, bool DB, bool U8>
@@ -666,20 +681,27 @@ __global__ __launch_bounds__(1024) void kb_batch(BatchArgs a) {
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-template <bool U8>
-static hipError_t launch_ka(int G, dim3 grid, dim3 block, hipStream_t s, const void *I,
-                            ImageParams p, const DevTables *tab, int32_t *ws) {
+template <bool U8, bool ONE>
+static hipError_t launch_ka1(int G, dim3 grid, dim3 block, hipStream_t s, const void *I,
+                             ImageParams p, const DevTables *tab, int32_t *ws) {
   switch (G) {
-    case 1: hipLaunchKernelGGL((ka_sat<1, U8>), grid, block, 0, s, I, p, tab, ws); break;
-    case 2: hipLaunchKernelGGL((ka_sat<2, U8>), grid, block, 0, s, I, p, tab, ws); break;
-    case 3: hipLaunchKernelGGL((ka_sat<3, U8>), grid, block, 0, s, I, p, tab, ws); break;
-    case 4: hipLaunchKernelGGL((ka_sat<4, U8>), grid, block, 0, s, I, p, tab, ws); break;
-    case 5: hipLaunchKernelGGL((ka_sat<5, U8>), grid, block, 0, s, I, p, tab, ws); break;
-    case 6: hipLaunchKernelGGL((ka_sat<6, U8>), grid, block, 0, s, I, p, tab, ws); break;
-    case 7: hipLaunchKernelGGL((ka_sat<7, U8>), grid, block, 0, s, I, p, tab, ws); break;
-    default: hipLaunchKernelGGL((ka_sat<8, U8>), grid, block, 0, s, I, p, tab, ws); break;
+    case 1: hipLaunchKernelGGL((ka_sat<1, U8, ONE>), grid, block, 0, s, I, p, tab, ws); break;
+    case 2: hipLaunchKernelGGL((ka_sat<2, U8, ONE>), grid, block, 0, s, I, p, tab, ws); break;
+    case 3: hipLaunchKernelGGL((ka_sat<3, U8, ONE>), grid, block, 0, s, I, p, tab, ws); break;
+    case 4: hipLaunchKernelGGL((ka_sat<4, U8, ONE>), grid, block, 0, s, I, p, tab, ws); break;
+    case 5: hipLaunchKernelGGL((ka_sat<5, U8, ONE>), grid, block, 0, s, I, p, tab, ws); break;
+    case 6: hipLaunchKernelGGL((ka_sat<6, U8, ONE>), grid, block, 0, s, I, p, tab, ws); break;
+    case 7: hipLaunchKernelGGL((ka_sat<7, U8, ONE>), grid, block, 0, s, I, p, tab, ws); break;
+    default: hipLaunchKernelGGL((ka_sat<8, U8, ONE>), grid, block, 0, s, I, p, tab, ws); break;
   }
   return hipGetLastError();
+}
+
+template <bool U8>
+static hipError_t launch_ka(int G, bool one, dim3 grid, dim3 block, hipStream_t s, const void *I,
+                            ImageParams p, const DevTables *tab, int32_t *ws) {
+  return one ? launch_ka1<U8, true>(G, grid, block, s, I, p, tab, ws)
+             : launch_ka1<U8, false>(G, grid, block, s, I, p, tab, ws);
 }
 
 template <bool U8>
@@ -815,10 +837,11 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
   const ImageParams p = image_params(host, g);
   const int G = ka_chunks(g);
   if (G > kMaxChunks) return BF_ERR_UNSUPPORTED;
-  dim3 ga(g.tiles_y * g.tiles_x, (host.n_terms + 3) / 4), ba(256);
+  const bool one = g.ka_one != 0;
+  dim3 ga(g.tiles_y * g.tiles_x, ((one ? host.n_images : host.n_terms) + 3) / 4), ba(256);
   profile_mark(0, 1, stream);
-  hipError_t e = host.in_u8 ? launch_ka<true>(G, ga, ba, s, I, p, dev, ws)
-                            : launch_ka<false>(G, ga, ba, s, I, p, dev, ws);
+  hipError_t e = host.in_u8 ? launch_ka<true>(G, one, ga, ba, s, I, p, dev, ws)
+                            : launch_ka<false>(G, one, ga, ba, s, I, p, dev, ws);
   profile_mark(0, 0, stream);
   if (e != hipSuccess) return BF_ERR_DEVICE;
   // LDS tile kernel when the staged region fits and the quadruplets' corner
@@ -839,20 +862,25 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
 }
 
-template <bool U8>
-static hipError_t launch_ka_batch(int G, int blocks, hipStream_t s, const BatchArgs &a) {
+template <bool U8, bool ONE>
+static hipError_t launch_ka_batch1(int G, int blocks, hipStream_t s, const BatchArgs &a) {
   dim3 grid(blocks), block(256);
   switch (G) {
-    case 1: hipLaunchKernelGGL((ka_batch<1, U8>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((ka_batch<2, U8>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((ka_batch<3, U8>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((ka_batch<4, U8>), grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((ka_batch<5, U8>), grid, block, 0, s, a); break;
-    case 6: hipLaunchKernelGGL((ka_batch<6, U8>), grid, block, 0, s, a); break;
-    case 7: hipLaunchKernelGGL((ka_batch<7, U8>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((ka_batch<8, U8>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((ka_batch<1, U8, ONE>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((ka_batch<2, U8, ONE>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((ka_batch<3, U8, ONE>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((ka_batch<4, U8, ONE>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((ka_batch<5, U8, ONE>), grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((ka_batch<6, U8, ONE>), grid, block, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((ka_batch<7, U8, ONE>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((ka_batch<8, U8, ONE>), grid, block, 0, s, a); break;
   }
   return hipGetLastError();
+}
+
+template <bool U8>
+static hipError_t launch_ka_batch(int G, bool one, int blocks, hipStream_t s, const BatchArgs &a) {
+  return one ? launch_ka_batch1<U8, true>(G, blocks, s, a) : launch_ka_batch1<U8, false>(G, blocks, s, a);
 }
 
 template <int PITCH, int NQ, bool DB, bool U8>
@@ -890,6 +918,9 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
   BatchArgs ka{};
   ka.n = n;
   ka.heads = heads;
+  // one table per K-A wave when every image of the group was tuned that way
+  bool one = true;
+  for (int j = 0; j < n; ++j) one = one && items[idx[j]].g.ka_one != 0;
   int G = 1, blocks = 0;
   for (int j = 0; j < n; ++j) {
     const BatchItem &it = items[idx[j]];
@@ -899,7 +930,7 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
     im.ws = it.ws;
     im.tab = it.dev;
     im.p = image_params(*it.host, it.g);
-    im.ka_blocks = it.g.tiles_y * it.g.tiles_x * ((it.host->n_terms + 3) / 4);
+    im.ka_blocks = it.g.tiles_y * it.g.tiles_x * (((one ? it.host->n_images : it.host->n_terms) + 3) / 4);
     im.n_tiles = ((it.g.W + 63) / 64) * ((it.g.H + 63) / 64);
     im.per_xcd = (im.n_tiles + 7) / 8;
     ka.ka_start[j] = blocks;
@@ -909,7 +940,7 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
   ka.ka_start[n] = blocks;
   if (G > kMaxChunks) return BF_ERR_UNSUPPORTED;
   profile_mark(0, 1, s);
-  hipError_t e = u8 ? launch_ka_batch<true>(G, blocks, s, ka) : launch_ka_batch<false>(G, blocks, s, ka);
+  hipError_t e = u8 ? launch_ka_batch<true>(G, one, blocks, s, ka) : launch_ka_batch<false>(G, one, blocks, s, ka);
   profile_mark(0, 0, s);
   if (e != hipSuccess) return BF_ERR_DEVICE;
 

@@ -364,6 +364,21 @@ def test_tiling_and_autotuning_do_not_change_results(torch_dev):
         assert torch.equal(o, ref), tile
     p = bf.Plan(8.0, 0.1, 24, 16, 6)
     before = bf.filter(p, I).clone()
+    # every launch shape the tuner may pick, pinned by hand
+    for tile in (64, 128, 256, 512):
+        for kb_single in (0, 1):
+            for ka_one in (0, 1):
+                p.set_tuning(333, 517, tile, kb_single, ka_one)
+                o = bf.filter(p, I)
+                torch.cuda.synchronize()
+                assert torch.equal(o, ref), (tile, kb_single, ka_one)
+    # and in a batch (one table-kernel launch for both images)
+    I2 = torch.from_numpy(synth.gen_image(333, 517, 6, 0.03, 78)).cuda()
+    p.set_tuning(333, 517, 256, 1, 1)
+    outs = bf.filter_batch([p, p], [I, I2])
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], ref)
+    bf.lib().bf_autotune_clear()
     t = p.autotune(333, 517, reps=3)
     after = bf.filter(p, I)
     torch.cuda.synchronize()
