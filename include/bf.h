@@ -206,6 +206,30 @@ bf_status_t bf_tuning_set(bf_plan_t plan, int H, int W, int tile, int kb_single,
 /* Forget every tuned shape. */
 bf_status_t bf_autotune_clear(void);
 
+/* ------------------------------------------------------------------------
+ * Pre-computed tables (Case 1 of Sec. V-C).  The term tables of an image
+ * depend on the image, the range terms k and T only (not on the spatial
+ * kernel or on sigma_r while T = max(T_r, span) stays the same), so tables
+ * built once under `tables_plan` serve later filters of the same image under
+ * any `plan` that is compatible: same input type, radius <= tables_plan's,
+ * no lone taps, and range terms equal to the first terms of tables_plan's
+ * (same k, same T).  Only the lookup kernel runs.  The result equals
+ * bf_filter(plan) up to the fixed-point shift, which here is tables_plan's
+ * (within 1e-6 of it; not bitwise).
+ * ------------------------------------------------------------------------ */
+/* Workspace bytes of the tables of an H x W image under tables_plan. */
+bf_status_t bf_precompute_size(bf_plan_t tables_plan, int H, int W, size_t *bytes);
+/* Build the tables (table kernel only) into ws (>= bf_precompute_size). */
+bf_status_t bf_precompute(bf_plan_t tables_plan, const void *I, int H, int W, void *ws, size_t ws_bytes,
+                          void *stream);
+/* BF_OK if tables built under tables_plan serve plan; else BF_ERR_INVALID_ARG
+ * (or BF_ERR_UNSUPPORTED for a plan with lone taps). Host only. */
+bf_status_t bf_precomputed_compatible(bf_plan_t tables_plan, bf_plan_t plan);
+/* Filter I (the image the tables were built from) under plan, reading the
+ * tables in ws; lookup kernel only. */
+bf_status_t bf_filter_precomputed(bf_plan_t tables_plan, bf_plan_t plan, const void *I, float *out, int H,
+                                  int W, const void *ws, size_t ws_bytes, void *stream);
+
 /* Per-kernel timing for measurement.  While enabled, every filter call
  * records HIP events around each of its kernels on the call's stream (all
  * work still runs); bf_profile_read waits for the recorded events, returns

@@ -26,6 +26,7 @@ EXPORTED = [
     "bf_profile_enable", "bf_profile_read", "bf_status_string", "bf_version",
     "bf_server_create", "bf_server_destroy", "bf_server_submit", "bf_server_poll", "bf_server_pending",
     "bf_server_stats", "bf_autotune", "bf_tuning_set", "bf_autotune_clear",
+    "bf_precompute_size", "bf_precompute", "bf_precomputed_compatible", "bf_filter_precomputed",
 ]
 
 
@@ -365,3 +366,38 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Pre-computed tables (re-filtering one image under several plans)
+# ---------------------------------------------------------------------------
+def precompute(tables_plan, I, ws=None, stream=None):
+    """Build the term tables of I under tables_plan (table kernel only);
+    returns the workspace tensor holding them."""
+    import torch
+    H, W = _image_args(tables_plan, I)
+    n = ctypes.c_size_t()
+    _check(lib().bf_precompute_size(tables_plan.handle, H, W, ctypes.byref(n)), "bf_precompute_size")
+    if ws is None:
+        ws = torch.empty(max(1, n.value), dtype=torch.uint8, device=I.device)
+    _check(lib().bf_precompute(tables_plan.handle, ctypes.c_void_p(I.data_ptr()), H, W,
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                               _stream_handle(stream)), "bf_precompute")
+    return ws
+
+
+def precomputed_compatible(tables_plan, plan):
+    return lib().bf_precomputed_compatible(tables_plan.handle, plan.handle)
+
+
+def filter_precomputed(tables_plan, plan, I, ws, out=None, stream=None):
+    """Filter I under plan from tables built by precompute(tables_plan, I)."""
+    import torch
+    H, W = _image_args(plan, I)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=I.device)
+    _check(lib().bf_filter_precomputed(tables_plan.handle, plan.handle, ctypes.c_void_p(I.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), H, W, ctypes.c_void_p(ws.data_ptr()),
+                                       ws.numel() * ws.element_size(), _stream_handle(stream)),
+           "bf_filter_precomputed")
+    return out

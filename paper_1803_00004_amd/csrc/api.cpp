@@ -443,6 +443,59 @@ bf_status_t bf_autotune_clear(void) {
   return BF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Pre-computed tables (Case 1 of Sec. V-C): the term tables of an image built
+// once under one plan serve later plans whose terms they contain.
+// ---------------------------------------------------------------------------
+namespace {
+// Tables are laid out by the untuned heuristic tiling of the plan that
+// builds them, so a later call finds them where they were written.
+bf::Geometry precompute_geometry(const bf_plan_s *p, int H, int W) { return geometry_with(p, H, W, 0, 0, 0); }
+}  // namespace
+
+bf_status_t bf_precompute_size(bf_plan_t tables_plan, int H, int W, size_t *bytes) {
+  if (!tables_plan || !bytes || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
+  *bytes = precompute_geometry(tables_plan, H, W).bytes;
+  return BF_OK;
+}
+
+bf_status_t bf_precompute(bf_plan_t tables_plan, const void *I, int H, int W, void *ws, size_t ws_bytes,
+                          void *stream) {
+  if (!tables_plan || !I || !ws || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
+  if (tables_plan->flags & BF_FLAG_HOST_ONLY) return BF_ERR_INVALID_ARG;
+  const bf::Geometry g = precompute_geometry(tables_plan, H, W);
+  const size_t in_bytes = (size_t)H * W * (tables_plan->in_dtype == BF_IN_U8 ? 1 : 4);
+  if (ws_bytes < g.bytes || ranges_overlap(ws, g.bytes, I, in_bytes)) return BF_ERR_INVALID_ARG;
+  return bf::launch_tables(tables_plan->dev_tables, tables_plan->host_tables, g, I,
+                           static_cast<int32_t *>(ws), stream);
+}
+
+bf_status_t bf_precomputed_compatible(bf_plan_t tables_plan, bf_plan_t plan) {
+  if (!tables_plan || !plan) return BF_ERR_INVALID_ARG;
+  const bf::DevTables &a = tables_plan->host_tables, &b = plan->host_tables;
+  if (tables_plan->in_dtype != plan->in_dtype) return BF_ERR_INVALID_ARG;
+  if (plan->fit.radius > tables_plan->fit.radius) return BF_ERR_INVALID_ARG;  // halo too small
+  if (b.n_single != 0) return BF_ERR_UNSUPPORTED;  // lone taps read raw (possibly wrapped) entries
+  if (b.n_terms > a.n_terms) return BF_ERR_INVALID_ARG;
+  for (int i = 0; i < b.n_terms; ++i)  // the same terms, in the same table slots
+    if (plan->fit.k[i] != tables_plan->fit.k[i] || b.f_hi[i] != a.f_hi[i] || b.f_lo[i] != a.f_lo[i] ||
+        b.slot[i] != a.slot[i])
+      return BF_ERR_INVALID_ARG;
+  return BF_OK;
+}
+
+bf_status_t bf_filter_precomputed(bf_plan_t tables_plan, bf_plan_t plan, const void *I, float *out, int H,
+                                  int W, const void *ws, size_t ws_bytes, void *stream) {
+  bf_status_t st = bf_precomputed_compatible(tables_plan, plan);
+  if (st != BF_OK) return st;
+  st = check_image(plan, I, out, H, W);
+  if (st != BF_OK) return st;
+  const bf::Geometry g = precompute_geometry(tables_plan, H, W);
+  if (!ws || ws_bytes < g.bytes || ranges_overlap(ws, g.bytes, out, (size_t)H * W * 4)) return BF_ERR_INVALID_ARG;
+  return bf::launch_lookup(plan->dev_tables, plan->host_tables, g, I, out, nullptr, nullptr,
+                           static_cast<const int32_t *>(ws), stream);
+}
+
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   if (!plan || !info) return BF_ERR_INVALID_ARG;
   const bf::Fit &f = plan->fit;

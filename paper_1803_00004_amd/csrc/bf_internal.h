@@ -108,6 +108,15 @@ void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double
 // a region `width` columns wide: one of the compiled pitches, or 0 if none fits.
 int lds_pitch_for(int width);
 
+// The table kernel alone (tables of `host`'s terms, geometry g) and the
+// lookup kernel alone (taps and terms of `host`, reading tables laid out by
+// geometry g, which may hold more tables than `host` reads).
+bf_status_t launch_tables(const DevTables *dev, const DevTables &host, const Geometry &g,
+                          const void *I, int32_t *ws, void *stream);
+bf_status_t launch_lookup(const DevTables *dev, const DevTables &host, const Geometry &g,
+                          const void *I, float *out, float *num, float *den, const int32_t *ws,
+                          void *stream);
+
 // Launch the two kernels of one image on `stream` (hipStream_t): `dev` is
 // the device copy of `host`.
 bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geometry &g,

@@ -550,7 +550,7 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
     }
   };
 
-  const int n = p.n_images;
+  const int n = tab->n_images;  // this plan's tables (the workspace may hold more: p.n_images)
   using B0 = std::integral_constant<int, 0>;
   using B1 = std::integral_constant<int, 1>;
   if (DB) {
@@ -830,9 +830,8 @@ static bool kb_tile_eligible(const DevTables &h) {
 
 int lookup_kernel_kind(const DevTables &h) { return kb_tile_eligible(h) ? 1 : 0; }
 
-bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geometry &g,
-                          const void *I, float *out, float *num, float *den, int32_t *ws,
-                          void *stream) {
+bf_status_t launch_tables(const DevTables *dev, const DevTables &host, const Geometry &g,
+                          const void *I, int32_t *ws, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const ImageParams p = image_params(host, g);
   const int G = ka_chunks(g);
@@ -843,7 +842,15 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
   hipError_t e = host.in_u8 ? launch_ka<true>(G, one, ga, ba, s, I, p, dev, ws)
                             : launch_ka<false>(G, one, ga, ba, s, I, p, dev, ws);
   profile_mark(0, 0, stream);
-  if (e != hipSuccess) return BF_ERR_DEVICE;
+  return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
+}
+
+bf_status_t launch_lookup(const DevTables *dev, const DevTables &host, const Geometry &g,
+                          const void *I, float *out, float *num, float *den, const int32_t *ws,
+                          void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const ImageParams p = image_params(host, g);
+  hipError_t e;
   // LDS tile kernel when the staged region fits and the quadruplets' corner
   // addresses fit in registers, else the per-pixel kernel
   profile_mark(1, 1, stream);
@@ -860,6 +867,14 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
   }
   profile_mark(1, 0, stream);
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
+}
+
+bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geometry &g,
+                          const void *I, float *out, float *num, float *den, int32_t *ws,
+                          void *stream) {
+  bf_status_t st = launch_tables(dev, host, g, I, ws, stream);
+  if (st != BF_OK) return st;
+  return launch_lookup(dev, host, g, I, out, num, den, ws, stream);
 }
 
 template <bool U8, bool ONE>

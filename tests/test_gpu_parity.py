@@ -386,3 +386,26 @@ def test_tiling_and_autotuning_do_not_change_results(torch_dev):
     assert t in (64, 128, 256, 512)
     assert torch.equal(before, ref) and torch.equal(after, ref)
     bf.lib().bf_autotune_clear()
+
+
+def test_precomputed_tables_refilter(torch_dev):
+    """Tables built once under one plan serve later filters of the same image
+    under other plans (other sigma_s, sigma_r, fewer terms): each result
+    matches the oracle for its own plan and the direct filter within 1e-6."""
+    import torch
+    bf = _bf()
+    I_host = synth.gen_image(333, 517, 6, 0.03, 91)
+    I = torch.from_numpy(I_host).cuda()
+    tp = bf.Plan(8.0, 0.1, 24, 16, 6)
+    ws = bf.precompute(tp, I)
+    for ss, r, ns, sr, nr in [(8.0, 24, 6, 0.1, 16), (4.0, 12, 4, 0.2, 8), (2.0, 6, 4, 0.05, 16), (6.0, 18, 6, 0.3, 8)]:
+        p = bf.Plan(ss, sr, r, nr, ns)
+        assert bf.precomputed_compatible(tp, p) == bf.BF_OK
+        o = bf.filter_precomputed(tp, p, I, ws)
+        d = bf.filter(p, I)
+        torch.cuda.synchronize()
+        ref = oracle.expanded_box(I_host, oracle.make_plan(ss, r, ns, sr, nr))
+        err = np.abs(o.cpu().numpy() - ref).max()
+        _report("refilter sigma_s %g r %d N %d/%d from precomputed tables" % (ss, r, nr, ns), err)
+        assert err <= TIGHT
+        assert (o - d).abs().max().item() <= 1e-6

@@ -172,3 +172,19 @@ def test_batch_workspace_is_the_sum_of_aligned_parts():
     total = bf.batch_workspace_size(plans, shapes)
     parts = [p.workspace_size(h, w) for p, (h, w) in zip(plans, shapes)]
     assert total == 256 + sum((b + 255) // 256 * 256 for b in parts)
+
+
+def test_precomputed_tables_compatibility():
+    """Tables built under one plan serve plans with the same input type, a
+    radius no larger, no lone taps, and range terms equal to the first terms
+    of the tables' (same k, same T)."""
+    t = bf.Plan(16.0, 0.05, 48, 32, 4, host_only=True)
+    for ss in (2.0, 4.0, 8.0, 16.0):
+        for sr, nr in ((0.05, 32), (0.1, 16), (0.2, 8), (0.3, 8)):
+            assert bf.precomputed_compatible(t, bf.Plan(ss, sr, int(3 * ss), nr, 4, host_only=True)) == bf.BF_OK
+    assert bf.precomputed_compatible(t, bf.Plan(20.0, 0.1, 60, 16, 4, host_only=True)) == bf.BF_ERR_INVALID_ARG
+    small = bf.Plan(8.0, 0.1, 24, 8, 4, host_only=True)
+    assert bf.precomputed_compatible(small, bf.Plan(8.0, 0.1, 24, 16, 4, host_only=True)) == bf.BF_ERR_INVALID_ARG
+    # T = max(T_r, 1) grows past 1 for sigma_r = 0.5: other frequencies
+    assert bf.precomputed_compatible(t, bf.Plan(8.0, 0.5, 24, 8, 4, host_only=True)) == bf.BF_ERR_INVALID_ARG
+    assert bf.precomputed_compatible(t, bf.Plan(8.0, 0.1, 24, 8, 4, dtype="u8", host_only=True)) == bf.BF_ERR_INVALID_ARG
