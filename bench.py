@@ -126,6 +126,16 @@ def served(args):
     n_equal = sum(bool(torch.equal(outs[i], alone[i])) for i in range(n))
     log("[served] closed loop %.1f Mpix/s; one at a time %.1f Mpix/s; %d/%d results bitwise equal alone"
         % (thr_closed, thr_plain, n_equal, n))
+    # the same stream with direct summation where it is cheaper (small
+    # windows: those requests get the exact bilateral filter)
+    auto_plans = {k: bf.Plan(k[0], k[3], k[1], k[4], k[2], direct="auto") for k in plans}
+    n_direct = sum(1 for r in reqs if auto_plans[serve.plan_key(r)].info.direct)
+    serve.run_closed_loop(srv, reqs[:32], auto_plans, imgs[:32], outs[:32])
+    done_a, mk_a = serve.run_open_loop(srv, reqs, auto_plans, imgs, outs)
+    lat_a = serve.latency_summary(reqs, done_a)
+    _, mk_ac = serve.run_closed_loop(srv, reqs, auto_plans, imgs, outs)
+    log("[served] with direct summation for %d small-window requests: open loop %.1f Mpix/s p50 %.2f ms p99 %.2f ms; "
+        "closed loop %.1f Mpix/s" % (n_direct, px.sum() / mk_a / 1e6, lat_a["p50_ms"], lat_a["p99_ms"], px.sum() / mk_ac / 1e6))
     srv.close()
 
     ka_b = kb_b = kb_f = 0.0
@@ -154,7 +164,11 @@ def served(args):
                    "peak_requests_in_flight": st.peak_requests_in_flight,
                    "peak_workspace_bytes": int(st.peak_arena_bytes),
                    "batch_size_hist": {str(k): int(st.batch_size_hist[k]) for k in range(65) if st.batch_size_hist[k]},
-                   "results_bitwise_equal_alone": "%d/%d" % (n_equal, n)},
+                   "results_bitwise_equal_alone": "%d/%d" % (n_equal, n),
+                   "with_direct_auto": {"requests_direct": n_direct,
+                                        "open_loop_mpix_s": round(px.sum() / mk_a / 1e6, 2),
+                                        "p50_ms": round(lat_a["p50_ms"], 3), "p99_ms": round(lat_a["p99_ms"], 3),
+                                        "closed_loop_mpix_s": round(px.sum() / mk_ac / 1e6, 2)}},
         "plan_ms": round(plan_ms, 1),
         "kernel_ms_total": {"ka_sat": round(kms[0], 3), "kb_lookup": round(kms[1], 3)},
         "roofline": roof,

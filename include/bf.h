@@ -71,6 +71,17 @@ typedef enum { BF_IN_F32 = 0, BF_IN_U8 = 1 } bf_dtype_t;
 typedef enum { BF_PREC_PLAIN = 0, BF_PREC_REDUCED = 1 } bf_precision_t;
 
 #define BF_FLAG_HOST_ONLY 0x1u /* fit tables on the host only; no device work, no filtering */
+/* Direct summation (the paper's brute-force baseline "BFT"): Eq. BF itself
+ * with the exact Gaussian K_s on the square window [-r, r]^2 and the exact
+ * Gaussian K_r, summed in FP32 over in-image neighbours -- the true bilateral
+ * filter rather than its N-term expansion, and no workspace.  radius <= 32.
+ * DIRECT always filters this way; DIRECT_AUTO does so where its estimated
+ * cost, 8.5 (2r + 1)^2 vector operations per pixel, is below the expansion's,
+ * (1700 + n_images (85 + 10 quadruplets)) (1 + r / 120) (both fitted to
+ * MI355X timings): small windows, and mid-size ones with many range terms.
+ * bf_plan_info_t.direct says which. */
+#define BF_FLAG_DIRECT 0x2u
+#define BF_FLAG_DIRECT_AUTO 0x4u
 
 typedef struct {
   bf_dtype_t in_dtype;      /* input element type, default BF_IN_F32 */
@@ -151,6 +162,7 @@ typedef struct {
   int n_quads;        /* taps grouped in symmetric quadruplets (one box sum each) */
   int n_single;       /* taps outside any quadruplet */
   int lookup_kernel;  /* 1: LDS tile lookup kernel, 0: per-pixel lookup kernel */
+  int direct;         /* 1: filters by direct summation (BF_FLAG_DIRECT / _AUTO) */
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);

@@ -18,6 +18,8 @@ BF_KERNEL_GAUSSIAN = 0
 BF_IN_F32, BF_IN_U8 = 0, 1
 BF_PREC_PLAIN, BF_PREC_REDUCED = 0, 1
 BF_FLAG_HOST_ONLY = 0x1
+BF_FLAG_DIRECT = 0x2
+BF_FLAG_DIRECT_AUTO = 0x4
 
 EXPORTED = [
     "bf_plan_create", "bf_plan_destroy", "bf_workspace_size", "bf_filter", "bf_filter_ws",
@@ -51,7 +53,7 @@ class PlanInfo(ctypes.Structure):
                 ("n_images", ctypes.c_int), ("tile", ctypes.c_int), ("sat_shift", ctypes.c_int),
                 ("T_s", ctypes.c_double), ("T_r", ctypes.c_double), ("T", ctypes.c_double),
                 ("den_floor", ctypes.c_double), ("n_quads", ctypes.c_int), ("n_single", ctypes.c_int),
-                ("lookup_kernel", ctypes.c_int)]
+                ("lookup_kernel", ctypes.c_int), ("direct", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -131,11 +133,18 @@ class Plan:
     """A filter plan: both kernel expansions fitted (FP64, host) and uploaded."""
 
     def __init__(self, sigma_s, sigma_r, radius=0, n_range=8, n_spatial=4, dtype="f32",
-                 precision="plain", eps=0.0, span=0.0, tile=0, host_only=False):
+                 precision="plain", eps=0.0, span=0.0, tile=0, host_only=False, direct=False):
+        """direct: False (N-term expansion), True (direct summation of Eq. BF,
+        BF_FLAG_DIRECT) or "auto" (direct where its cost model is lower)."""
         self._h = ctypes.c_void_p()
+        flags = BF_FLAG_HOST_ONLY if host_only else 0
+        if direct == "auto":
+            flags |= BF_FLAG_DIRECT_AUTO
+        elif direct:
+            flags |= BF_FLAG_DIRECT
         opts = _Opts(BF_IN_U8 if dtype == "u8" else BF_IN_F32,
                      BF_PREC_REDUCED if precision == "reduced" else BF_PREC_PLAIN,
-                     float(eps), float(span), int(tile), BF_FLAG_HOST_ONLY if host_only else 0)
+                     float(eps), float(span), int(tile), flags)
         st = lib().bf_plan_create(ctypes.byref(self._h), BF_KERNEL_GAUSSIAN, BF_KERNEL_GAUSSIAN,
                                   float(sigma_s), float(sigma_r), int(radius),
                                   _Terms(int(n_range), int(n_spatial)), ctypes.byref(opts))

@@ -18,6 +18,7 @@ constexpr int kMaxChunks = 8;      // 256-column chunks of one table row (table 
 constexpr int kKA_Threads = 256;   // summed-area-table kernel block size (upper bound)
 constexpr int kMaxBatch = 24;      // images per batched launch (descriptors travel as kernel arguments)
 constexpr size_t kBatchHeadBytes = 256;  // batch workspace prefix: the K-B work-queue heads
+constexpr int kMaxDirectRadius = 32;     // direct summation window limit
 
 // Host-side result of the FP64 fit (Sec. IV, App. A/B).
 struct Fit {
@@ -73,6 +74,11 @@ struct DevTables {
   double den_floor;
   int in_u8;
   int n_images;
+  // direct summation (true BF over the (2r+1)^2 window)
+  int direct;
+  int direct_r;
+  float direct_c;                      // -log2(e) / (2 sigma_r^2), per input unit squared
+  const float *direct_ks;              // device: K_s(dy, dx) at (dy + r)(2r + 1) + dx + r
 };
 
 // Geometry of one image under a plan: tiles of `tile` outputs with their
@@ -107,6 +113,10 @@ void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double
 // Row pitch (int32 elements) of the LDS tile kernel's staged table region for
 // a region `width` columns wide: one of the compiled pitches, or 0 if none fits.
 int lds_pitch_for(int width);
+
+// Direct summation of Eq. BF for a plan with host.direct set.
+bf_status_t launch_direct(const DevTables &host, const void *I, float *out, float *num, float *den,
+                          int H, int W, void *stream);
 
 // The table kernel alone (tables of `host`'s terms, geometry g) and the
 // lookup kernel alone (taps and terms of `host`, reading tables laid out by
@@ -157,6 +167,7 @@ struct bf_plan_s {
   unsigned flags = 0;
   bf::DevTables host_tables{};
   bf::DevTables *dev_tables = nullptr;  // device copy
+  float *dev_direct_ks = nullptr;       // device K_s window of a direct plan
   void *own_ws = nullptr;               // workspace grown by bf_filter
   size_t own_ws_bytes = 0;
   int device = 0;

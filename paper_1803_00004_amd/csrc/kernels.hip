@@ -606,6 +606,81 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
 }
 
 // ---------------------------------------------------------------------------
+// Direct summation of Eq. BF (the brute-force baseline of the paper): one
+// thread per pixel, 64 x 4 pixels per block; the block's image tile with an
+// r-pixel halo and the K_s window are staged in LDS.  Neighbours outside the
+// image are staged as a large value whose range weight underflows to 0, so
+// the inner loop has no branch: w = K_s(d) 2^(c (v - v0)^2), num += w v,
+// den += w, in FP32 (den >= 1: the centre's weight).
+// ---------------------------------------------------------------------------
+template <bool U8>
+__global__ __launch_bounds__(256) void direct_bf(const void *__restrict__ I, int H, int W, int r,
+                                                 const float *__restrict__ Ks, float c,
+                                                 float *__restrict__ out, float *__restrict__ num_out,
+                                                 float *__restrict__ den_out) {
+  extern __shared__ float sh[];
+  const int K = 2 * r + 1, TW = 64 + 2 * r, TH = 4 + 2 * r;
+  float *ks = sh;
+  float *t = sh + K * K;
+  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 4;
+  for (int i = threadIdx.x; i < K * K; i += 256) ks[i] = Ks[i];
+  for (int i = threadIdx.x; i < TW * TH; i += 256) {
+    const int ty = i / TW, tx = i - ty * TW;
+    const int y = y0 - r + ty, x = x0 - r + tx;
+    float v = 1e18f;  // outside the image: (v - v0)^2 c underflows the weight to 0
+    if (y >= 0 && y < H && x >= 0 && x < W) {
+      const long long idx = (long long)y * W + x;
+      v = U8 ? (float)static_cast<const uint8_t *>(I)[idx] : static_cast<const float *>(I)[idx];
+    }
+    t[i] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int x = x0 + lane, y = y0 + row;
+  if (x >= W || y >= H) return;
+  const float *base = t + row * TW + lane;  // window corner (dy = -r, dx = -r)
+  const float v0 = base[r * TW + r];
+  float nu = 0.0f, de = 0.0f;
+  for (int dy = 0; dy < K; ++dy) {
+    const float *rowp = base + dy * TW;
+    const float *krow = ks + dy * K;
+    for (int dx = 0; dx < K; ++dx) {
+      const float v = rowp[dx];
+      const float d = v - v0;
+      const float w = krow[dx] * __builtin_amdgcn_exp2f(c * d * d);
+      nu = __builtin_fmaf(w, v, nu);
+      de += w;
+    }
+  }
+  const long long idx = (long long)y * W + x;
+  const float s = U8 ? 1.0f / 255.0f : 1.0f;
+  out[idx] = nu / de * s;
+  if (num_out) num_out[idx] = nu * s;
+  if (den_out) den_out[idx] = de;
+}
+
+bf_status_t launch_direct(const DevTables &host, const void *I, float *out, float *num, float *den,
+                          int H, int W, void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int r = host.direct_r, K = 2 * r + 1;
+  const size_t lds = ((size_t)K * K + (size_t)(64 + 2 * r) * (4 + 2 * r)) * sizeof(float);
+  dim3 grid((W + 63) / 64, (H + 3) / 4), block(256);
+  profile_mark(1, 1, stream);
+  if (host.in_u8) {
+    if (hipFuncSetAttribute((const void *)direct_bf<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return BF_ERR_DEVICE;
+    hipLaunchKernelGGL(direct_bf<true>, grid, block, lds, s, I, H, W, r, host.direct_ks, host.direct_c, out, num, den);
+  } else {
+    if (hipFuncSetAttribute((const void *)direct_bf<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return BF_ERR_DEVICE;
+    hipLaunchKernelGGL(direct_bf<false>, grid, block, lds, s, I, H, W, r, host.direct_ks, host.direct_c, out, num, den);
+  }
+  const hipError_t e = hipGetLastError();
+  profile_mark(1, 0, stream);
+  return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
+}
+
+// ---------------------------------------------------------------------------
 // Batches: every image of a batch runs in one launch per kernel.  The
 // per-image descriptors travel by value in the kernel arguments (nothing to
 // allocate, copy or keep alive, so a batch can be captured in a graph).
@@ -872,6 +947,7 @@ bf_status_t launch_lookup(const DevTables *dev, const DevTables &host, const Geo
 bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geometry &g,
                           const void *I, float *out, float *num, float *den, int32_t *ws,
                           void *stream) {
+  if (host.direct) return launch_direct(host, I, out, num, den, g.H, g.W, stream);
   bf_status_t st = launch_tables(dev, host, g, I, ws, stream);
   if (st != BF_OK) return st;
   return launch_lookup(dev, host, g, I, out, num, den, ws, stream);
@@ -1010,8 +1086,22 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
 }
 
-bf_status_t launch_batch(const BatchItem *items, int n, uint32_t *heads, void *stream) {
+bf_status_t launch_batch(const BatchItem *items_all, int n_all, uint32_t *heads, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // direct-summation requests need no tables: their own launches
+  std::vector<BatchItem> kept;
+  kept.reserve(n_all);
+  for (int i = 0; i < n_all; ++i) {
+    const BatchItem &it = items_all[i];
+    if (it.host->direct) {
+      bf_status_t st = launch_direct(*it.host, it.I, it.out, nullptr, nullptr, it.g.H, it.g.W, stream);
+      if (st != BF_OK) return st;
+    } else {
+      kept.push_back(it);
+    }
+  }
+  const BatchItem *items = kept.data();
+  const int n = (int)kept.size();
   // by input type, costliest first (largest tile count x tables x quadruplets)
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;

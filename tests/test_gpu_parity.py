@@ -409,3 +409,40 @@ def test_precomputed_tables_refilter(torch_dev):
         _report("refilter sigma_s %g r %d N %d/%d from precomputed tables" % (ss, r, nr, ns), err)
         assert err <= TIGHT
         assert (o - d).abs().max().item() <= 1e-6
+
+
+@pytest.mark.parametrize("H,W,ss,r,sr,dtype", [
+    (197, 263, 2.0, 6, 0.1, "f32"),   # ragged, several blocks, borders
+    (5, 300, 3.0, 9, 0.05, "f32"),    # image shorter than the window
+    (130, 129, 4.0, 12, 0.2, "u8"),
+    (64, 64, 8.0, 24, 0.3, "f32"),
+    (1, 1, 2.0, 6, 0.1, "f32"),
+])
+def test_direct_summation_vs_true_bf(torch_dev, H, W, ss, r, sr, dtype):
+    """Direct summation is Eq. BF with the exact kernels: the oracle's T1."""
+    bf = _bf()
+    I = synth.gen_image_u8(H, W, 4, 0.03, H + 7 * W) if dtype == "u8" else synth.gen_image(H, W, 4, 0.03, H + 7 * W)
+    p = bf.Plan(ss, sr, r, 8, 4, dtype=dtype, direct=True)
+    assert p.info.direct == 1
+    out = _run(torch_dev, p, I)
+    ref = oracle.true_bf(I, ss, r, sr)
+    err = np.abs(out - ref).max()
+    _report("direct %dx%d r %d %s vs T1" % (H, W, r, dtype), err)
+    assert err <= TIGHT
+
+
+def test_direct_plans_in_batches(torch_dev):
+    """Direct-summation requests mixed with expansion requests in a batch:
+    bitwise the single-image results."""
+    import torch
+    bf = _bf()
+    pd = bf.Plan(2.0, 0.05, 6, 32, 4, direct="auto")
+    pe = bf.Plan(4.0, 0.1, 12, 16, 4)
+    assert pd.info.direct == 1 and pe.info.direct == 0
+    imgs = [torch.from_numpy(synth.gen_image(h, w, 4, 0.03, h * w)).cuda() for h, w in ((120, 333), (77, 64), (256, 256))]
+    plans = [pd, pe, pd]
+    singles = [bf.filter(p, I).clone() for p, I in zip(plans, imgs)]
+    outs = bf.filter_batch(plans, imgs)
+    torch.cuda.synchronize()
+    for o, s in zip(outs, singles):
+        assert torch.equal(o, s)

@@ -188,3 +188,19 @@ def test_precomputed_tables_compatibility():
     # T = max(T_r, 1) grows past 1 for sigma_r = 0.5: other frequencies
     assert bf.precomputed_compatible(t, bf.Plan(8.0, 0.5, 24, 8, 4, host_only=True)) == bf.BF_ERR_INVALID_ARG
     assert bf.precomputed_compatible(t, bf.Plan(8.0, 0.1, 24, 8, 4, dtype="u8", host_only=True)) == bf.BF_ERR_INVALID_ARG
+
+
+def test_direct_summation_choice():
+    """Direct summation on request (radius <= 32) and, with the automatic
+    flag, only where its cost model beats the expansion: small windows with
+    many range terms."""
+    assert bf.Plan(3.0, 0.1, 9, 8, 4, host_only=True, direct=True).info.direct == 1
+    assert bf.Plan(3.0, 0.1, 9, 8, 4, host_only=True).info.direct == 0
+    assert bf.Plan(2.0, 0.05, 6, 32, 4, host_only=True, direct="auto").info.direct == 1
+    assert bf.Plan(8.0, 0.1, 24, 16, 6, host_only=True, direct="auto").info.direct == 0
+    assert bf.Plan(16.0, 0.05, 48, 32, 8, host_only=True, direct="auto").info.direct == 0
+    with pytest.raises(bf.BFError) as e:
+        bf.Plan(12.0, 0.1, 36, 8, 4, host_only=True, direct=True)
+    assert e.value.status == bf.BF_ERR_UNSUPPORTED
+    p = bf.Plan(2.0, 0.1, 6, 8, 4, host_only=True, direct=True)
+    assert p.workspace_size(500, 700) == 0
