@@ -6,12 +6,14 @@ expansions) and bfref.c (the filters T1, T2, T3).
 """
 from .fit import (spatial_fit, spatial_rectangles, range_fit, range_kernel_approx,
                   haar_family, haar_coefficient, gaussian_integral, truncation_radius,
-                  first_m_containing, cosine_coefficients, select_largest, PHI)
+                  first_m_containing, cosine_coefficients, select_largest, PHI,
+                  spatial_fit_2d, spatial_kernel_2d, range_kernel, cell_integrals, KINDS)
 from .filters import (Plan, make_plan, true_bf, expanded_brute, expanded_box,
                       correlate_rects, to_unit)
 
 __all__ = ["spatial_fit", "spatial_rectangles", "range_fit", "range_kernel_approx",
            "haar_family", "haar_coefficient", "gaussian_integral", "truncation_radius",
            "first_m_containing", "cosine_coefficients", "select_largest", "PHI",
+           "spatial_fit_2d", "spatial_kernel_2d", "range_kernel", "cell_integrals", "KINDS",
            "Plan", "make_plan", "true_bf", "expanded_brute", "expanded_box",
            "correlate_rects", "to_unit"]

@@ -30,10 +30,18 @@
 
 static inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+/* Kernels: kind 0 Gaussian exp(-x^2 / 2 sigma^2); kind 1 exponential
+ * exp(-|x| / sigma), radial in space (exp(-||d|| / sigma), not separable). */
+static inline double ks_weight(int kind, double d2, double sigma) {
+  return kind == 1 ? exp(-sqrt(d2) / sigma) : exp(-d2 / (2.0 * sigma * sigma));
+}
+static inline double kr_weight(int kind, double t, double sigma) {
+  return kind == 1 ? exp(-fabs(t) / sigma) : exp(-t * t / (2.0 * sigma * sigma));
+}
+
 /* T1: true bilateral filter at the listed pixels (all pixels if ys == NULL). */
-void ref_true_bf(const double *I, int H, int W, int r, double sigma_s, double sigma_r,
-                 const int *ys, const int *xs, long npix, double den_floor, double *out) {
-  const double is = 1.0 / (2.0 * sigma_s * sigma_s), ir = 1.0 / (2.0 * sigma_r * sigma_r);
+void ref_true_bf(const double *I, int H, int W, int r, double sigma_s, double sigma_r, int kind_s,
+                 int kind_r, const int *ys, const int *xs, long npix, double den_floor, double *out) {
   long n = ys ? npix : (long)H * W;
 #pragma omp parallel for schedule(dynamic, 64)
   for (long i = 0; i < n; ++i) {
@@ -46,7 +54,7 @@ void ref_true_bf(const double *I, int H, int W, int r, double sigma_s, double si
         int qx = px - dx;
         if (qx < 0 || qx >= W) continue;
         double Iq = I[(long)qy * W + qx], t = Ip - Iq;
-        double w = exp(-(double)(dx * dx + dy * dy) * is) * exp(-t * t * ir);
+        double w = ks_weight(kind_s, (double)(dx * dx + dy * dy), sigma_s) * kr_weight(kind_r, t, sigma_r);
         num += w * Iq;
         den += w;
       }

@@ -1,6 +1,7 @@
 """Python front end of the FP64 oracle filters (TEST INFRASTRUCTURE ONLY).
 
-T1 true_bf         : Eq. BF, Gaussian kernels, square window [-r, r]^2.
+T1 true_bf         : Eq. BF with the exact kernels (Gaussian or exponential),
+                     square window [-r, r]^2.
 T2 expanded_brute  : Eq. BF with the N-term expansions of both kernels, direct sum.
 T3 expanded_box    : the same through the cosine shift identity (Eq. 1D_N_terms)
                      and FP64 summed-area-table box sums of the Haar rectangles
@@ -12,7 +13,7 @@ import os
 import numpy as np
 
 from . import build as _build
-from .fit import spatial_fit, spatial_rectangles, range_fit
+from .fit import spatial_fit, spatial_fit_2d, spatial_kernel_2d, spatial_rectangles, range_fit
 
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -26,7 +27,8 @@ def _load():
             _build.build()
         lib = ctypes.CDLL(_build.LIB)
         lib.ref_true_bf.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                    ctypes.c_double, _ip, _ip, ctypes.c_long, ctypes.c_double, _dp]
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _ip, ctypes.c_long,
+                                    ctypes.c_double, _dp]
         lib.ref_expanded_brute.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                            ctypes.c_int, _dp, _dp, _ip, _ip, ctypes.c_long,
                                            ctypes.c_double, _dp, _dp, _dp]
@@ -54,10 +56,15 @@ def to_unit(I):
 class Plan:
     """Both kernel expansions for one parameter set."""
 
-    def __init__(self, sigma_s, radius, n_spatial, sigma_r, n_range, eps=0.01, span=1.0):
+    def __init__(self, sigma_s, radius, n_spatial, sigma_r, n_range, eps=0.01, span=1.0,
+                 kind_s="gaussian", kind_r="gaussian"):
         self.sigma_s, self.radius, self.sigma_r = sigma_s, radius, sigma_r
-        self.spatial = spatial_fit(sigma_s, radius, n_spatial)
-        self.range = range_fit(sigma_r, n_range, eps=eps, span=span)
+        self.kind_s, self.kind_r = kind_s, kind_r
+        if kind_s == "gaussian":
+            self.spatial = spatial_fit(sigma_s, radius, n_spatial)
+        else:
+            self.spatial = spatial_fit_2d(spatial_kernel_2d(kind_s, sigma_s), radius, n_spatial)
+        self.range = range_fit(sigma_r, n_range, eps=eps, span=span, kernel=kind_r)
         self.Ks = np.ascontiguousarray(self.spatial.K, dtype=np.float64)
         self.rects = np.ascontiguousarray(spatial_rectangles(self.spatial), dtype=np.float64)
         self.a = np.ascontiguousarray(self.range.a, dtype=np.float64)
@@ -80,14 +87,18 @@ def _pixels(H, W, ys, xs):
     return ys, xs, len(ys)
 
 
-def true_bf(I, sigma_s, radius, sigma_r, ys=None, xs=None, den_floor=0.0):
+_KIND = {"gaussian": 0, "exponential": 1}
+
+
+def true_bf(I, sigma_s, radius, sigma_r, ys=None, xs=None, den_floor=0.0, kind_s="gaussian",
+            kind_r="gaussian"):
     """T1 at all pixels (H x W result) or at the listed pixels (1-D result)."""
     I = np.ascontiguousarray(to_unit(I))
     H, W = I.shape
     ys, xs, n = _pixels(H, W, ys, xs)
     out = np.empty(n)
-    _load().ref_true_bf(_p(I), H, W, int(radius), float(sigma_s), float(sigma_r),
-                        _p(ys, _ip), _p(xs, _ip), n, float(den_floor), _p(out))
+    _load().ref_true_bf(_p(I), H, W, int(radius), float(sigma_s), float(sigma_r), _KIND[kind_s],
+                        _KIND[kind_r], _p(ys, _ip), _p(xs, _ip), n, float(den_floor), _p(out))
     return out.reshape(H, W) if ys is None else out
 
 

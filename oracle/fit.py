@@ -11,6 +11,8 @@ It computes, in double precision and straight from the paper's definitions:
   coefficients of Eq. Haar_2D_coefficients), its best N-term selection
   (Sec. III-A, Eq. N_term; Sec. IV-B, Eq. Haar_N_terms) and the box form of
   each selected 2-D Haar function (App. A, Table VI);
+* for a kernel that is not separable (the radial exponential), the same 2-D
+  coefficients from numerical integrals of K_s over the finest Haar cells;
 * the truncated-cosine expansion of the range kernel (Sec. III-B, Eq.
   1D_truncated_cos; Sec. IV-C, Eq. trigonometric_N_terms) with its best N-term
   selection out of the first 20N coefficients (App. B, Table VII).
@@ -50,9 +52,37 @@ def gaussian_integral(a, b, sigma):
     return sigma * math.sqrt(math.pi / 2.0) * (math.erf(b / s) - math.erf(a / s))
 
 
-def truncation_radius(sigma, eps=0.01):
-    """T = K^{-1}(eps) for a Gaussian K (Sec. IV-A): sigma * sqrt(2 ln(1/eps))."""
+def truncation_radius(sigma, eps=0.01, kind="gaussian"):
+    """T = K^{-1}(eps) (Sec. IV-A): sigma sqrt(2 ln(1/eps)) for the Gaussian,
+    sigma ln(1/eps) for the exponential exp(-|x| / sigma)."""
+    if kind == "exponential":
+        return sigma * math.log(1.0 / eps)
     return sigma * math.sqrt(2.0 * math.log(1.0 / eps))
+
+
+# ----------------------------------------------------------------------------
+# Other kernels (the method takes arbitrary kernels, Sec. I / Sec. V): the
+# exponential exp(-|x| / sigma) in range and the radially symmetric, not
+# separable exp(-||(x, y)|| / sigma) in space.
+# ----------------------------------------------------------------------------
+KINDS = ("gaussian", "exponential")
+
+
+def range_kernel(kind, sigma):
+    if kind == "gaussian":
+        return lambda t: gaussian(t, sigma)
+    if kind == "exponential":
+        return lambda t: np.exp(-np.abs(np.asarray(t, dtype=np.float64)) / sigma)
+    raise ValueError(kind)
+
+
+def spatial_kernel_2d(kind, sigma):
+    """K_s(x, y) as a function of the offset (vectorised)."""
+    if kind == "gaussian":
+        return lambda x, y: np.exp(-(x * x + y * y) / (2.0 * sigma * sigma))
+    if kind == "exponential":
+        return lambda x, y: np.exp(-np.sqrt(x * x + y * y) / sigma)
+    raise ValueError(kind)
 
 
 # ----------------------------------------------------------------------------
@@ -174,6 +204,72 @@ def spatial_fit(sigma_s, radius, n_spatial):
     return out
 
 
+def cell_integrals(kernel2d, T, n_cells, sub=4, nodes=12):
+    """M[j, i] = integral of K(x, y) over the finest cell (x in cell i, y in
+    cell j) of the grid of n_cells equal cells on [-T, T) per axis, by
+    composite tensor Gauss-Legendre (sub x sub panels of nodes^2 points per
+    cell).  The offset origin lies on cell corners, where the radial kernels
+    have their only non-smooth point."""
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    h = 2.0 * T / n_cells
+    # 1-D nodes / weights inside one cell, relative to its left edge
+    e = np.linspace(0.0, h, sub + 1)
+    lo, hi = e[:-1, None], e[1:, None]
+    t = (0.5 * (hi - lo) * x[None, :] + 0.5 * (hi + lo)).ravel()
+    wt = (0.5 * (hi - lo) * w[None, :]).ravel()
+    edges = -T + h * np.arange(n_cells)
+    M = np.empty((n_cells, n_cells))
+    for j in range(n_cells):
+        Y = edges[j] + t
+        for i in range(n_cells):
+            X = edges[i] + t
+            M[j, i] = wt @ kernel2d(X[None, :], Y[:, None]) @ wt
+    return M
+
+
+def spatial_fit_2d(kernel2d, radius, n_spatial):
+    """Best N_s-group Haar approximation of an arbitrary K_s on
+    [-T_s, T_s)^2 (Eq. Haar_2D_coefficients without separability): every 2-D
+    coefficient c_ab = <K, h_a(x) h_b(y)> / (||h_a||^2 ||h_b||^2) is a signed sum
+    of integrals of K over the finest cells (every Haar function up to level J
+    is constant on them)."""
+    T = radius + 0.5
+    J = max_level(T)
+    fam = haar_family(T, J)
+    n_cells = 2 ** (J + 1)
+    M = cell_integrals(kernel2d, T, n_cells)
+    centers = -T + (2.0 * T / n_cells) * (np.arange(n_cells) + 0.5)
+    Hm = np.array([f.sample(centers) for f in fam])        # functions x cells, +-1 / 0
+    norms = np.array([f.norm2() for f in fam])
+    C = (Hm @ M @ Hm.T) / np.outer(norms, norms)           # C[b, a]: h_b in y, h_a in x
+    levels = [PHI] + list(range(0, J + 1))
+    lev = np.array([f.level for f in fam])
+    groups = []
+    for lx in levels:
+        for ly in levels:
+            sb, sa = lev == ly, lev == lx
+            e = float(((C[np.ix_(sb, sa)] ** 2) * np.outer(norms[sb], norms[sa])).sum())
+            groups.append((_round_sig(e), lx, ly))
+    if not (1 <= n_spatial <= len(groups)):
+        raise ValueError("n_spatial must be in [1, %d]" % len(groups))
+    groups.sort(key=lambda g: (-g[0], g[1] + g[2], g[1]))
+    sel = [(lx, ly) for _, lx, ly in groups[:n_spatial]]
+    d = np.arange(-radius, radius + 1)
+    S = np.array([f.sample(d) for f in fam])               # functions x offsets
+    K = np.zeros((2 * radius + 1, 2 * radius + 1))
+    for lx, ly in sel:
+        sb, sa = lev == ly, lev == lx
+        K += S[sb].T @ C[np.ix_(sb, sa)] @ S[sa]
+    out = SpatialFit()
+    out.sigma, out.radius, out.T, out.J = None, radius, T, J
+    out.family, out.coef2 = fam, C
+    out.cells = M
+    out.groups_ranked = groups
+    out.selected = sel
+    out.K = K
+    return out
+
+
 def spatial_rectangles(fit):
     """The selected expansion written as weighted rectangles in offset space
     (App. A: phi*psi = B1 - B2, psi*psi = B1 - B2 + B3 - B4; Eq. 2D_box_N_terms).
@@ -184,12 +280,14 @@ def spatial_rectangles(fit):
     integers ceil(lo) .. ceil(hi) - 1)."""
     rows = []
     by_level = {}
-    for f, c in zip(fit.family, fit.coef):
-        by_level.setdefault(f.level, []).append((f, c))
+    C = getattr(fit, "coef2", None)
+    for i, f in enumerate(fit.family):
+        by_level.setdefault(f.level, []).append((i, f))
     for lx, ly in fit.selected:
-        for fx, cx in by_level[lx]:
-            for fy, cy in by_level[ly]:
-                w = cx * cy
+        for ia, fx in by_level[lx]:
+            for ib, fy in by_level[ly]:
+                # separable kernels: product of 1-D coefficients; otherwise the 2-D one
+                w = fit.coef[ia] * fit.coef[ib] if C is None else C[ib, ia]
                 if w == 0.0:
                     continue
                 for xlo, xhi, sx in fx.intervals():
@@ -248,9 +346,12 @@ def range_fit(sigma_r, n_range, eps=0.01, span=1.0, kernel=None):
     (k, a_k, omega_k = pi k / T)."""
     if not (1 <= n_range <= 64):
         raise ValueError("n_range must be in [1, 64]")
+    kind = "gaussian"
     if kernel is None:
         kernel = lambda t: gaussian(t, sigma_r)
-    T_r = truncation_radius(sigma_r, eps)
+    elif isinstance(kernel, str):
+        kind, kernel = kernel, range_kernel(kernel, sigma_r)
+    T_r = truncation_radius(sigma_r, eps, kind)
     T = max(T_r, span)
     M = max(20 * n_range, 2)
     a = cosine_coefficients(kernel, T, M)

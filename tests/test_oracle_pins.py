@@ -408,3 +408,143 @@ def test_planted_mistakes_are_caught(monkeypatch):
         den += a * c * oracle.correlate_rects(c, plan.rects)
     cos_only = num / den
     assert np.abs(cos_only - t2).max() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Other kernels: the exponential in range, the radial exponential in space
+# (not separable; 2-D coefficients from integrals over the finest cells)
+# ---------------------------------------------------------------------------
+def _anisotropic(a, b):
+    return lambda x, y: np.exp(-x * x / (2 * a * a) - y * y / (2 * b * b))
+
+
+@pytest.mark.parametrize("ss,r,ns", [(3.0, 9, 4), (5.0, 15, 6), (2.0, 6, 9)])
+def test_cell_fit_reproduces_separable_gaussian(ss, r, ns):
+    """The generic 2-D cell path applied to the Gaussian must give the closed-form
+    separable fit (products of erf-based 1-D coefficients)."""
+    a = oracle.spatial_fit(ss, r, ns)
+    b = oracle.spatial_fit_2d(oracle.spatial_kernel_2d("gaussian", ss), r, ns)
+    assert a.selected == b.selected
+    assert np.abs(a.K - b.K).max() < 1e-12
+    ra, rb = oracle.spatial_rectangles(a), oracle.spatial_rectangles(b)
+    assert ra.shape == rb.shape and np.abs(ra - rb).max() < 1e-12
+
+
+def test_cell_fit_orientation_anisotropic():
+    """exp(-x^2/2a^2 - y^2/2b^2) with a != b: C[b, a] is the product of the
+    y-coefficient (sigma b) and the x-coefficient (sigma a); a transposed
+    operand anywhere swaps them."""
+    r, sa, sb = 9, 1.5, 4.0
+    fit = oracle.spatial_fit_2d(_anisotropic(sa, sb), r, 6)
+    T = r + 0.5
+    cx = np.array([oracle.haar_coefficient(f, sa, T) for f in fit.family])
+    cy = np.array([oracle.haar_coefficient(f, sb, T) for f in fit.family])
+    assert np.abs(fit.coef2 - np.outer(cy, cx)).max() < 1e-13
+    # the sampled expansion is wider along y than along x
+    K = fit.K
+    assert K[r + 6, r] > K[r, r + 6]
+
+
+@pytest.mark.parametrize("cells", [(8, 8), (7, 8), (0, 0), (8, 11), (3, 15), (12, 5)])
+def test_cell_integrals_by_adaptive_quadrature(cells):
+    """Cell integrals of the radial exponential (cusp at the origin, a cell
+    corner) against scipy's adaptive dblquad."""
+    ss, T = 3.0, 9.5
+    n = 16
+    M = oracle.cell_integrals(oracle.spatial_kernel_2d("exponential", ss), T, n)
+    h = 2 * T / n
+    j, i = cells
+    ylo, xlo = -T + h * j, -T + h * i
+    ref, _ = integrate.dblquad(lambda y, x: math.exp(-math.hypot(x, y) / ss), xlo, xlo + h, ylo, ylo + h,
+                               epsabs=1e-14, epsrel=1e-13)
+    assert abs(M[j, i] - ref) <= 1e-8 * ref
+
+
+def test_cell_fit_full_expansion_is_cell_average():
+    """With every level group kept the Haar basis is complete on the finest
+    cells: the expansion at an offset is the average of K over its cell.
+    Asymmetric kernel, so index, sign and transpose mistakes show."""
+    r = 6
+    k = lambda x, y: np.exp(-((x - 0.7) ** 2) / 8.0 - ((y + 1.3) ** 2) / 3.0 - 0.1 * x * y)
+    T = r + 0.5
+    J = oracle.fit.max_level(T)
+    fit = oracle.spatial_fit_2d(k, r, (J + 2) ** 2)
+    n = 2 ** (J + 1)
+    h = 2 * T / n
+    M = oracle.cell_integrals(k, T, n)
+    d = np.arange(-r, r + 1)
+    cell = np.floor((d + T) / h).astype(int)
+    expect = M[np.ix_(cell, cell)] / (h * h)       # [dy, dx]
+    assert np.abs(fit.K - expect).max() < 1e-12
+
+
+def test_cell_fit_parseval_energy():
+    """Sum of every group's energy = squared L2 norm of the cell-average
+    projection, sum of M^2 / h^2 (Parseval on the orthogonal Haar basis)."""
+    r = 9
+    T = r + 0.5
+    J = oracle.fit.max_level(T)
+    fit = oracle.spatial_fit_2d(oracle.spatial_kernel_2d("exponential", 2.5), r, 1)
+    n = 2 ** (J + 1)
+    h = 2 * T / n
+    total = sum(e for e, _, _ in fit.groups_ranked)
+    assert abs(total - (fit.cells ** 2).sum() / (h * h)) < 1e-9 * total
+
+
+@pytest.mark.parametrize("sigma,span", [(0.1, 1.0), (0.3, 1.0), (0.05, 0.0)])
+def test_exponential_range_coefficients_closed_form(sigma, span):
+    """a_j of exp(-|t|/sigma) on [-T, T]: (2/T)(alpha - alpha e^{-alpha T}(-1)^j) /
+    (alpha^2 + (pi j / T)^2), a_0 = (1 - e^{-alpha T}) / (alpha T), alpha = 1/sigma;
+    T = max(sigma ln(1/eps), span)."""
+    fit = oracle.range_fit(sigma, 8, eps=0.01, span=span, kernel="exponential")
+    assert abs(fit.T_r - sigma * math.log(100.0)) < 1e-15
+    T, al = fit.T, 1.0 / sigma
+    j = np.arange(fit.M)
+    w = np.pi * j / T
+    cf = (2 / T) * (al - np.exp(-al * T) * al * (-1.0) ** j) / (al * al + w * w)
+    cf[0] = (1 - math.exp(-al * T)) / (al * T)
+    assert np.abs(cf - fit.a_all).max() < 1e-12 * cf[0]
+
+
+def _py_true_bf_kinds(I, ss, r, sr):
+    """Eq. BF with exp(-||d|| / ss) and exp(-|t| / sr), plain loops."""
+    H, W = I.shape
+    out = np.zeros_like(I)
+    for py in range(H):
+        for px in range(W):
+            num = den = 0.0
+            for qy in range(max(0, py - r), min(H, py + r + 1)):
+                for qx in range(max(0, px - r), min(W, px + r + 1)):
+                    w = math.exp(-math.hypot(py - qy, px - qx) / ss) * math.exp(-abs(I[py, px] - I[qy, qx]) / sr)
+                    num += w * I[qy, qx]
+                    den += w
+            out[py, px] = num / den
+    return out
+
+
+def test_true_bf_exponential_kinds_brute_force_tiny():
+    I = synth.gen_image(7, 9, 2, 0.05, 13).astype(np.float64)
+    ref = _py_true_bf_kinds(I, 1.5, 3, 0.2)
+    got = oracle.true_bf(I, 1.5, 3, 0.2, kind_s="exponential", kind_r="exponential")
+    assert np.abs(got - ref).max() < 1e-14
+
+
+def test_exponential_expansion_converges_to_true_bf():
+    """More range terms and all spatial groups: the expanded filter approaches
+    Eq. BF with the exponential kernels (the error shrinks)."""
+    I = synth.gen_image(32, 32, 3, 0.02, 21)
+    r = 7
+    ref = oracle.true_bf(I, 2.0, r, 0.2, kind_s="exponential", kind_r="exponential")
+    errs = []
+    for ns, nr in ((2, 4), (6, 12), (16, 40)):
+        p = oracle.make_plan(2.0, r, ns, 0.2, nr, kind_s="exponential", kind_r="exponential")
+        errs.append(np.abs(oracle.expanded_box(I, p) - ref).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.02
+
+
+def test_exponential_plan_T2_equals_T3():
+    """Shift identity and box sums hold for any kernel pair."""
+    I = synth.gen_image(33, 41, 3, 0.03, 5)
+    p = oracle.make_plan(2.5, 8, 6, 0.15, 12, kind_s="exponential", kind_r="exponential")
+    assert np.abs(oracle.expanded_brute(I, p) - oracle.expanded_box(I, p)).max() < 1e-11
