@@ -50,9 +50,18 @@ typedef enum {
   BF_ERR_UNSUPPORTED = 4    /* valid request this build does not implement */
 } bf_status_t;
 
-/* Kernel shapes.  Eq. BF asks for symmetric kernels decreasing on R+; the
- * Gaussian G_sigma(x) = exp(-x^2 / 2 sigma^2) (Sec. I) is the one implemented. */
-typedef enum { BF_KERNEL_GAUSSIAN = 0 } bf_kernel_t;
+/* Kernel shapes.  Eq. BF takes symmetric kernels decreasing on R+ and the
+ * expansions of Sec. III-IV take any such kernel (only their coefficients
+ * change):
+ *   GAUSSIAN     G_sigma(x) = exp(-x^2 / 2 sigma^2) (Sec. I); as K_s the
+ *                separable exp(-(dx^2 + dy^2) / 2 sigma_s^2); K^{-1}(eps) =
+ *                sigma sqrt(2 ln(1/eps)).
+ *   EXPONENTIAL  exp(-|x| / sigma); as K_s the radial, not separable
+ *                exp(-sqrt(dx^2 + dy^2) / sigma_s), whose 2-D Haar
+ *                coefficients are integrated numerically (radius <= 511);
+ *                K^{-1}(eps) = sigma ln(1/eps).
+ * K_s and K_r are chosen independently. */
+typedef enum { BF_KERNEL_GAUSSIAN = 0, BF_KERNEL_EXPONENTIAL = 1 } bf_kernel_t;
 
 /* Expansion sizes: n_range cosine terms (1..64) of K_r, n_spatial Haar level
  * groups (1..(J+2)^2, J = floor(log2(radius + 1/2))) of K_s.  A level group is
@@ -72,8 +81,8 @@ typedef enum { BF_PREC_PLAIN = 0, BF_PREC_REDUCED = 1 } bf_precision_t;
 
 #define BF_FLAG_HOST_ONLY 0x1u /* fit tables on the host only; no device work, no filtering */
 /* Direct summation (the paper's brute-force baseline "BFT"): Eq. BF itself
- * with the exact Gaussian K_s on the square window [-r, r]^2 and the exact
- * Gaussian K_r, summed in FP32 over in-image neighbours -- the true bilateral
+ * with the exact K_s on the square window [-r, r]^2 and the exact K_r (either
+ * kind), summed in FP32 over in-image neighbours -- the true bilateral
  * filter rather than its N-term expansion, and no workspace.  radius <= 32.
  * DIRECT always filters this way; DIRECT_AUTO does so where its estimated
  * cost, 8.5 (2r + 1)^2 vector operations per pixel, is below the expansion's,
@@ -96,10 +105,12 @@ typedef struct {
 /* Create a plan: FP64 host fit of both expansions (Sec. IV, App. B), tap
  * compilation, and upload of the tables to the current HIP device.
  *   sigma_s, sigma_r > 0 and finite (sigma_r in intensity units of [0, span]);
- *   radius >= 0 (0 -> ceil(K_s^{-1}(eps)) = ceil(sigma_s sqrt(2 ln(1/eps))));
+ *   radius >= 0 (0 -> ceil(K_s^{-1}(eps)), e.g. ceil(sigma_s sqrt(2 ln(1/eps)))
+ *     for the Gaussian);
  *   opts may be NULL (all defaults).
  * Errors: BF_ERR_INVALID_ARG for a NULL plan pointer or out-of-range
- * parameter, BF_ERR_UNSUPPORTED for another kernel kind, BF_ERR_OUT_OF_MEMORY,
+ * parameter, BF_ERR_UNSUPPORTED for another kernel kind (or an EXPONENTIAL
+ * K_s with radius > 511), BF_ERR_OUT_OF_MEMORY,
  * BF_ERR_DEVICE.  The plan owns its device tables until bf_plan_destroy. */
 bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, double sigma_s,
                            double sigma_r, int radius, bf_terms_t N, const bf_plan_opts_t *opts);

@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(_PKG, "libbf.so")
 
 BF_OK, BF_ERR_INVALID_ARG, BF_ERR_OUT_OF_MEMORY, BF_ERR_DEVICE, BF_ERR_UNSUPPORTED = range(5)
 BF_KERNEL_GAUSSIAN = 0
+BF_KERNEL_EXPONENTIAL = 1
+KERNELS = {"gaussian": BF_KERNEL_GAUSSIAN, "exponential": BF_KERNEL_EXPONENTIAL}
 BF_IN_F32, BF_IN_U8 = 0, 1
 BF_PREC_PLAIN, BF_PREC_REDUCED = 0, 1
 BF_FLAG_HOST_ONLY = 0x1
@@ -133,9 +135,11 @@ class Plan:
     """A filter plan: both kernel expansions fitted (FP64, host) and uploaded."""
 
     def __init__(self, sigma_s, sigma_r, radius=0, n_range=8, n_spatial=4, dtype="f32",
-                 precision="plain", eps=0.0, span=0.0, tile=0, host_only=False, direct=False):
+                 precision="plain", eps=0.0, span=0.0, tile=0, host_only=False, direct=False,
+                 kernel_s="gaussian", kernel_r="gaussian"):
         """direct: False (N-term expansion), True (direct summation of Eq. BF,
-        BF_FLAG_DIRECT) or "auto" (direct where its cost model is lower)."""
+        BF_FLAG_DIRECT) or "auto" (direct where its cost model is lower).
+        kernel_s / kernel_r: "gaussian" or "exponential" (bf_kernel_t)."""
         self._h = ctypes.c_void_p()
         flags = BF_FLAG_HOST_ONLY if host_only else 0
         if direct == "auto":
@@ -145,7 +149,7 @@ class Plan:
         opts = _Opts(BF_IN_U8 if dtype == "u8" else BF_IN_F32,
                      BF_PREC_REDUCED if precision == "reduced" else BF_PREC_PLAIN,
                      float(eps), float(span), int(tile), flags)
-        st = lib().bf_plan_create(ctypes.byref(self._h), BF_KERNEL_GAUSSIAN, BF_KERNEL_GAUSSIAN,
+        st = lib().bf_plan_create(ctypes.byref(self._h), KERNELS[kernel_s], KERNELS[kernel_r],
                                   float(sigma_s), float(sigma_r), int(radius),
                                   _Terms(int(n_range), int(n_spatial)), ctypes.byref(opts))
         _check(st, "bf_plan_create")

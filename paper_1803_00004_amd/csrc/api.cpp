@@ -90,7 +90,8 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
                            double sigma_r, int radius, bf_terms_t N, const bf_plan_opts_t *opts) {
   if (!plan) return BF_ERR_INVALID_ARG;
   *plan = nullptr;
-  if (K_s != BF_KERNEL_GAUSSIAN || K_r != BF_KERNEL_GAUSSIAN) {
+  auto known = [](bf_kernel_t k) { return k == BF_KERNEL_GAUSSIAN || k == BF_KERNEL_EXPONENTIAL; };
+  if (!known(K_s) || !known(K_r)) {
     if ((int)K_s < 0 || (int)K_r < 0) return BF_ERR_INVALID_ARG;
     return BF_ERR_UNSUPPORTED;
   }
@@ -106,7 +107,7 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
 
   bf_plan_s *p = new (std::nothrow) bf_plan_s();
   if (!p) return BF_ERR_OUT_OF_MEMORY;
-  bf_status_t st = bf::fit_plan(sigma_s, sigma_r, radius, N, eps, span, &p->fit);
+  bf_status_t st = bf::fit_plan((int)K_s, (int)K_r, sigma_s, sigma_r, radius, N, eps, span, &p->fit);
   if (st != BF_OK) {
     delete p;
     return st;
@@ -241,11 +242,16 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
     ks.resize((size_t)K * K);
     for (int dy = -r; dy <= r; ++dy)
       for (int dx = -r; dx <= r; ++dx)
-        ks[(size_t)(dy + r) * K + dx + r] = (float)std::exp(-(dx * dx + dy * dy) / (2.0 * sigma_s * sigma_s));
+        ks[(size_t)(dy + r) * K + dx + r] =
+            (float)(K_s == BF_KERNEL_EXPONENTIAL ? std::exp(-std::sqrt((double)(dx * dx + dy * dy)) / sigma_s)
+                                                 : std::exp(-(dx * dx + dy * dy) / (2.0 * sigma_s * sigma_s)));
     t.direct = 1;
     t.direct_r = r;
-    double c = -1.4426950408889634 / (2.0 * sigma_r * sigma_r);  // -log2(e) / (2 sigma_r^2)
-    if (o.in_dtype == BF_IN_U8) c /= 255.0 * 255.0;                  // differences in bytes
+    // K_r(d) = 2^(c d^2) (Gaussian) or 2^(c |d|) (exponential)
+    const double log2e = 1.4426950408889634;
+    t.direct_abs = K_r == BF_KERNEL_EXPONENTIAL;
+    double c = t.direct_abs ? -log2e / sigma_r : -log2e / (2.0 * sigma_r * sigma_r);
+    if (o.in_dtype == BF_IN_U8) c /= t.direct_abs ? 255.0 : 255.0 * 255.0;  // differences in bytes
     t.direct_c = (float)c;
   }
 

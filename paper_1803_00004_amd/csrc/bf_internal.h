@@ -19,6 +19,7 @@ constexpr int kKA_Threads = 256;   // summed-area-table kernel block size (upper
 constexpr int kMaxBatch = 24;      // images per batched launch (descriptors travel as kernel arguments)
 constexpr size_t kBatchHeadBytes = 256;  // batch workspace prefix: the K-B work-queue heads
 constexpr int kMaxDirectRadius = 32;     // direct summation window limit
+constexpr int kMaxCellFitRadius = 511;   // non-separable K_s: Haar levels <= 8 (cell integrals)
 
 // Host-side result of the FP64 fit (Sec. IV, App. A/B).
 struct Fit {
@@ -39,8 +40,8 @@ struct Fit {
 };
 
 // Fit both expansions; returns BF_OK or BF_ERR_INVALID_ARG.
-bf_status_t fit_plan(double sigma_s, double sigma_r, int radius, bf_terms_t N, double eps,
-                     double span, Fit *out);
+bf_status_t fit_plan(int kind_s, int kind_r, double sigma_s, double sigma_r, int radius,
+                     bf_terms_t N, double eps, double span, Fit *out);
 
 // Device-side constant tables of a plan (one upload per plan).
 struct DevTables {
@@ -77,7 +78,8 @@ struct DevTables {
   // direct summation (true BF over the (2r+1)^2 window)
   int direct;
   int direct_r;
-  float direct_c;                      // -log2(e) / (2 sigma_r^2), per input unit squared
+  int direct_abs;                      // range kernel in |d| (exponential) instead of d^2
+  float direct_c;                      // K_r(d) = 2^(c d^2), or 2^(c |d|) when direct_abs
   const float *direct_ks;              // device: K_s(dy, dx) at (dy + r)(2r + 1) + dx + r
 };
 

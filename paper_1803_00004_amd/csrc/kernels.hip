@@ -610,10 +610,11 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
 // thread per pixel, 64 x 4 pixels per block; the block's image tile with an
 // r-pixel halo and the K_s window are staged in LDS.  Neighbours outside the
 // image are staged as a large value whose range weight underflows to 0, so
-// the inner loop has no branch: w = K_s(d) 2^(c (v - v0)^2), num += w v,
-// den += w, in FP32 (den >= 1: the centre's weight).
+// the inner loop has no branch: w = K_s(d) 2^(c (v - v0)^2) (Gaussian K_r;
+// 2^(c |v - v0|) for the exponential), num += w v, den += w, in FP32
+// (den >= 1: the centre's weight).
 // ---------------------------------------------------------------------------
-template <bool U8>
+template <bool U8, bool ABS>
 __global__ __launch_bounds__(256) void direct_bf(const void *__restrict__ I, int H, int W, int r,
                                                  const float *__restrict__ Ks, float c,
                                                  float *__restrict__ out, float *__restrict__ num_out,
@@ -647,7 +648,7 @@ __global__ __launch_bounds__(256) void direct_bf(const void *__restrict__ I, int
     for (int dx = 0; dx < K; ++dx) {
       const float v = rowp[dx];
       const float d = v - v0;
-      const float w = krow[dx] * __builtin_amdgcn_exp2f(c * d * d);
+      const float w = krow[dx] * __builtin_amdgcn_exp2f(ABS ? c * __builtin_fabsf(d) : c * d * d);
       nu = __builtin_fmaf(w, v, nu);
       de += w;
     }
@@ -666,15 +667,18 @@ bf_status_t launch_direct(const DevTables &host, const void *I, float *out, floa
   const size_t lds = ((size_t)K * K + (size_t)(64 + 2 * r) * (4 + 2 * r)) * sizeof(float);
   dim3 grid((W + 63) / 64, (H + 3) / 4), block(256);
   profile_mark(1, 1, stream);
-  if (host.in_u8) {
-    if (hipFuncSetAttribute((const void *)direct_bf<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-      return BF_ERR_DEVICE;
-    hipLaunchKernelGGL(direct_bf<true>, grid, block, lds, s, I, H, W, r, host.direct_ks, host.direct_c, out, num, den);
-  } else {
-    if (hipFuncSetAttribute((const void *)direct_bf<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-      return BF_ERR_DEVICE;
-    hipLaunchKernelGGL(direct_bf<false>, grid, block, lds, s, I, H, W, r, host.direct_ks, host.direct_c, out, num, den);
-  }
+  auto go = [&](auto kernel) {
+    if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return false;
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, I, H, W, r, host.direct_ks, host.direct_c, out, num, den);
+    return true;
+  };
+  bool ok;
+  if (host.in_u8)
+    ok = host.direct_abs ? go(direct_bf<true, true>) : go(direct_bf<true, false>);
+  else
+    ok = host.direct_abs ? go(direct_bf<false, true>) : go(direct_bf<false, false>);
+  if (!ok) return BF_ERR_DEVICE;
   const hipError_t e = hipGetLastError();
   profile_mark(1, 0, stream);
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;

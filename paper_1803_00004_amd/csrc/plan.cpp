@@ -10,6 +10,9 @@
 //  * Taps: the sampled kernel is piecewise constant on rectangles (App. A,
 //    Table VI); its mixed second differences give the corners at which the
 //    four-reference box sums of Eq. sum_sat_sum_region_2D read the table.
+//    Other kernels (Sec. I: the expansion takes any symmetric kernel): the
+//    radial exponential exp(-||d|| / sigma_s), which is not separable, gets
+//    its 2-D coefficients from integrals over the finest Haar cells.
 //  * Range: best N-term truncated cosine approximation (Sec. III-B, Eq.
 //    1D_truncated_cos; Sec. IV-C, Eq. trigonometric_N_terms), coefficients by
 //    composite Gauss-Legendre quadrature, the N largest |a_k| among the first
@@ -101,15 +104,75 @@ void gauss_legendre(int n, std::vector<double> *x, std::vector<double> *w) {
   }
 }
 
+// Kernel profiles by kind (bf_kernel_t): 0 Gaussian, 1 exponential.
+double range_profile(int kind, double t, double sigma) {
+  return kind == BF_KERNEL_EXPONENTIAL ? std::exp(-std::fabs(t) / sigma)
+                                       : std::exp(-t * t / (2.0 * sigma * sigma));
+}
+double spatial_profile(int kind, double x, double y, double sigma) {
+  return kind == BF_KERNEL_EXPONENTIAL ? std::exp(-std::sqrt(x * x + y * y) / sigma)
+                                       : std::exp(-(x * x + y * y) / (2.0 * sigma * sigma));
+}
+// K^{-1}(eps) of the 1-D profile (Sec. IV-A).
+double kernel_inverse(int kind, double sigma, double eps) {
+  return kind == BF_KERNEL_EXPONENTIAL ? sigma * std::log(1.0 / eps)
+                                       : sigma * std::sqrt(2.0 * std::log(1.0 / eps));
+}
+
+// Integrals of K_s over the cells [x0, x0 + h) x [y0, y0 + h) of the quadrant
+// x, y >= 0 of a grid with corner at the origin: Q[jy * n + ix], n cells per
+// axis.  The cell at the origin holds the kernel's only non-smooth point
+// (radial kernels) in its corner; there the square is split along its
+// diagonal and each triangle mapped onto the unit square with the Jacobian
+// vanishing at the corner (x = h s, y = h s t), which makes the integrand
+// smooth.  Elsewhere: 2 x 2 panels of 10 x 10 Gauss-Legendre nodes per cell.
+void quadrant_cell_integrals(int kind, double sigma, double h, int n, std::vector<double> *Q) {
+  std::vector<double> gx, gw, cx, cw;
+  gauss_legendre(10, &gx, &gw);
+  for (int p = 0; p < 2; ++p)
+    for (int i = 0; i < 10; ++i) {
+      cx.push_back(0.25 * h * (gx[i] + 1.0) + 0.5 * h * p);  // node offset inside a cell
+      cw.push_back(0.25 * h * gw[i]);
+    }
+  Q->assign((size_t)n * n, 0.0);
+  for (int jy = 0; jy < n; ++jy)
+    for (int ix = 0; ix < n; ++ix) {
+      if (ix == 0 && jy == 0) continue;
+      double s = 0.0;
+      for (size_t a = 0; a < cx.size(); ++a) {
+        double row = 0.0;
+        for (size_t b = 0; b < cx.size(); ++b)
+          row += cw[b] * spatial_profile(kind, ix * h + cx[b], jy * h + cx[a], sigma);
+        s += cw[a] * row;
+      }
+      (*Q)[(size_t)jy * n + ix] = s;
+    }
+  std::vector<double> dx, dw;
+  gauss_legendre(24, &dx, &dw);
+  double s = 0.0;
+  for (size_t a = 0; a < dx.size(); ++a) {
+    const double u = 0.5 * (dx[a] + 1.0), wu = 0.5 * dw[a];  // radial-like coordinate
+    for (size_t b = 0; b < dx.size(); ++b) {
+      const double v = 0.5 * (dx[b] + 1.0), wv = 0.5 * dw[b];
+      const double jac = h * h * u;
+      s += wu * wv * jac * (spatial_profile(kind, h * u, h * u * v, sigma) +   // y <= x
+                            spatial_profile(kind, h * u * v, h * u, sigma));   // x <= y
+    }
+  }
+  (*Q)[0] = s;
+}
+
 }  // namespace
 
-bf_status_t fit_plan(double sigma_s, double sigma_r, int radius, bf_terms_t N, double eps,
-                     double span, Fit *out) {
+bf_status_t fit_plan(int kind_s, int kind_r, double sigma_s, double sigma_r, int radius,
+                     bf_terms_t N, double eps, double span, Fit *out) {
   if (!(sigma_s > 0) || !std::isfinite(sigma_s) || !(sigma_r > 0) || !std::isfinite(sigma_r) ||
       !(eps > 0 && eps < 1) || !(span >= 0) || !std::isfinite(span))
     return BF_ERR_INVALID_ARG;
-  if (radius == 0) radius = (int)std::ceil(sigma_s * std::sqrt(2.0 * std::log(1.0 / eps)));
+  if (radius == 0) radius = (int)std::ceil(kernel_inverse(kind_s, sigma_s, eps));
   if (radius < 1 || radius > 1024) return BF_ERR_INVALID_ARG;
+  // the cell integrals of a non-separable kernel cost O((2^J)^2) evaluations
+  if (kind_s != BF_KERNEL_GAUSSIAN && radius > kMaxCellFitRadius) return BF_ERR_UNSUPPORTED;
   if (N.n_range < 1 || N.n_range > kMaxTerms) return BF_ERR_INVALID_ARG;
 
   Fit f;
@@ -124,41 +187,148 @@ bf_status_t fit_plan(double sigma_s, double sigma_r, int radius, bf_terms_t N, d
   const int n_levels = J + 2;  // phi, 0..J
   if (N.n_spatial < 1 || N.n_spatial > n_levels * n_levels) return BF_ERR_INVALID_ARG;
   const std::vector<Haar> fam = haar_family(T, J);
-  std::vector<double> c(fam.size());
-  std::vector<double> e1(n_levels, 0.0);  // index level + 1
-  for (size_t i = 0; i < fam.size(); ++i) {
-    const Haar &h = fam[i];
-    if (h.level < 0)
-      c[i] = gauss_int(h.lo, h.hi, sigma_s) / (2.0 * T);
-    else
-      c[i] = std::ldexp(1.0, h.level) *
-             (gauss_int(h.lo, h.mid, sigma_s) - gauss_int(h.mid, h.hi, sigma_s)) / (2.0 * T);
-    e1[h.level + 1] += c[i] * c[i] * (h.hi - h.lo);
-  }
   struct Group { double e; int lx, ly; };
   std::vector<Group> groups;
-  for (int lx = -1; lx <= J; ++lx)
-    for (int ly = -1; ly <= J; ++ly)
-      groups.push_back({round_sig12(e1[lx + 1] * e1[ly + 1]), lx, ly});
-  std::sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) {
-    if (a.e != b.e) return a.e > b.e;
-    if (a.lx + a.ly != b.lx + b.ly) return a.lx + a.ly < b.lx + b.ly;
-    return a.lx < b.lx;
-  });
+  auto rank_groups = [&]() {
+    std::sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) {
+      if (a.e != b.e) return a.e > b.e;
+      if (a.lx + a.ly != b.lx + b.ly) return a.lx + a.ly < b.lx + b.ly;
+      return a.lx < b.lx;
+    });
+  };
   const int ks = 2 * radius + 1;
-  // u_l(d) = sum_{b in level l} c_b b(d), d in [-r, r]
-  std::vector<double> u((size_t)n_levels * ks, 0.0);
-  for (size_t i = 0; i < fam.size(); ++i)
-    for (int d = -radius; d <= radius; ++d)
-      u[(size_t)(fam[i].level + 1) * ks + d + radius] += c[i] * fam[i].sample((double)d);
   f.K.assign((size_t)ks * ks, 0.0);
-  for (int g = 0; g < N.n_spatial; ++g) {
-    const int lx = groups[g].lx, ly = groups[g].ly;
-    f.group_lx.push_back(lx);
-    f.group_ly.push_back(ly);
-    const double *ux = &u[(size_t)(lx + 1) * ks], *uy = &u[(size_t)(ly + 1) * ks];
-    for (int iy = 0; iy < ks; ++iy)
-      for (int ix = 0; ix < ks; ++ix) f.K[(size_t)iy * ks + ix] += uy[iy] * ux[ix];
+  if (kind_s == BF_KERNEL_GAUSSIAN) {
+    // separable: 2-D coefficients are products of 1-D ones (closed form)
+    std::vector<double> c(fam.size());
+    std::vector<double> e1(n_levels, 0.0);  // index level + 1
+    for (size_t i = 0; i < fam.size(); ++i) {
+      const Haar &h = fam[i];
+      if (h.level < 0)
+        c[i] = gauss_int(h.lo, h.hi, sigma_s) / (2.0 * T);
+      else
+        c[i] = std::ldexp(1.0, h.level) *
+               (gauss_int(h.lo, h.mid, sigma_s) - gauss_int(h.mid, h.hi, sigma_s)) / (2.0 * T);
+      e1[h.level + 1] += c[i] * c[i] * (h.hi - h.lo);
+    }
+    for (int lx = -1; lx <= J; ++lx)
+      for (int ly = -1; ly <= J; ++ly)
+        groups.push_back({round_sig12(e1[lx + 1] * e1[ly + 1]), lx, ly});
+    rank_groups();
+    // u_l(d) = sum_{b in level l} c_b b(d), d in [-r, r]
+    std::vector<double> u((size_t)n_levels * ks, 0.0);
+    for (size_t i = 0; i < fam.size(); ++i)
+      for (int d = -radius; d <= radius; ++d)
+        u[(size_t)(fam[i].level + 1) * ks + d + radius] += c[i] * fam[i].sample((double)d);
+    for (int g = 0; g < N.n_spatial; ++g) {
+      const int lx = groups[g].lx, ly = groups[g].ly;
+      f.group_lx.push_back(lx);
+      f.group_ly.push_back(ly);
+      const double *ux = &u[(size_t)(lx + 1) * ks], *uy = &u[(size_t)(ly + 1) * ks];
+      for (int iy = 0; iy < ks; ++iy)
+        for (int ix = 0; ix < ks; ++ix) f.K[(size_t)iy * ks + ix] += uy[iy] * ux[ix];
+    }
+  } else {
+    // Not separable.  Every Haar function up to level J is constant on the
+    // n = 2^(J+1) finest cells of [-T, T): it is +-1 on one or two aligned
+    // blocks of n / 2^e cells (e = 0 for phi, level + 1 for psi), so
+    // <K, h_a(x) h_b(y)> is a signed sum of block sums of the cell-integral
+    // matrix.  The block sums of every (e_x, e_y) come from pairwise sums of
+    // the finer ones (positive terms: no cancellation, and mirrored blocks get
+    // bitwise equal sums, so the symmetric taps pair exactly).
+    // c_ab = <K, h_a h_b> / (|h_a|^2 |h_b|^2).
+    const int n = 1 << (J + 1), n2 = n / 2, E = J + 2;  // block exponents e = 0 .. J + 1
+    const double h = 2.0 * T / n;
+    std::vector<double> Q;
+    quadrant_cell_integrals(kind_s, sigma_s, h, n2, &Q);  // kernel even in x and in y
+    // X[ex]: n rows x 2^ex column blocks; B[ex][ey]: 2^ey x 2^ex blocks
+    std::vector<std::vector<double>> X(E);
+    X[E - 1].resize((size_t)n * n);
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const int qi = i >= n2 ? i - n2 : n2 - 1 - i, qj = j >= n2 ? j - n2 : n2 - 1 - j;
+        X[E - 1][(size_t)j * n + i] = Q[(size_t)qj * n2 + qi];
+      }
+    for (int ex = E - 2; ex >= 0; --ex) {
+      const int w = 1 << ex;
+      X[ex].resize((size_t)n * w);
+      for (int j = 0; j < n; ++j)
+        for (int c = 0; c < w; ++c)
+          X[ex][(size_t)j * w + c] = X[ex + 1][(size_t)j * 2 * w + 2 * c] + X[ex + 1][(size_t)j * 2 * w + 2 * c + 1];
+    }
+    std::vector<std::vector<double>> B((size_t)E * E);
+    for (int ex = 0; ex < E; ++ex) {
+      const int w = 1 << ex;
+      B[(size_t)ex * E + E - 1] = X[ex];
+      for (int ey = E - 2; ey >= 0; --ey) {
+        const int hgt = 1 << ey;
+        const std::vector<double> &fine = B[(size_t)ex * E + ey + 1];
+        std::vector<double> &out = B[(size_t)ex * E + ey];
+        out.resize((size_t)hgt * w);
+        for (int r = 0; r < hgt; ++r)
+          for (int c = 0; c < w; ++c) out[(size_t)r * w + c] = fine[(size_t)2 * r * w + c] + fine[(size_t)(2 * r + 1) * w + c];
+      }
+    }
+    struct Piece { int e, blk; double sign; };
+    auto pieces = [&](const Haar &f, Piece *pc) {  // returns the count
+      if (f.level < 0) {
+        pc[0] = {0, 0, 1.0};
+        return 1;
+      }
+      const int e = f.level + 1;
+      const int blk = (int)std::lround((f.lo + T) / h) / (n >> e);
+      pc[0] = {e, blk, 1.0};
+      pc[1] = {e, blk + 1, -1.0};
+      return 2;
+    };
+    const size_t nf = fam.size();
+    std::vector<double> C(nf * nf);  // C[b * nf + a]: h_a in x, h_b in y
+    std::vector<double> e2((size_t)n_levels * n_levels, 0.0);
+    for (size_t b = 0; b < nf; ++b)
+      for (size_t a = 0; a < nf; ++a) {
+        const Haar &fa = fam[a], &fb = fam[b];
+        Piece pa[2], pb[2];
+        const int na_p = pieces(fa, pa), nb_p = pieces(fb, pb);
+        double ip = 0.0;
+        for (int u = 0; u < nb_p; ++u)
+          for (int v = 0; v < na_p; ++v) {
+            const std::vector<double> &blk = B[(size_t)pa[v].e * E + pb[u].e];
+            ip += pb[u].sign * pa[v].sign * blk[(size_t)pb[u].blk * (1 << pa[v].e) + pa[v].blk];
+          }
+        const double na = fa.hi - fa.lo, nb = fb.hi - fb.lo;
+        const double cab = ip / (na * nb);
+        C[b * nf + a] = cab;
+        e2[(size_t)(fa.level + 1) * n_levels + fb.level + 1] += cab * cab * na * nb;
+      }
+    // energies of groups that vanish by symmetry are quadrature noise: below
+    // 1e-12 of the largest they are zero, and the level rule orders them
+    const double floor_e = 1e-12 * *std::max_element(e2.begin(), e2.end());
+    for (int lx = -1; lx <= J; ++lx)
+      for (int ly = -1; ly <= J; ++ly) {
+        const double e = e2[(size_t)(lx + 1) * n_levels + ly + 1];
+        groups.push_back({e > floor_e ? round_sig12(e) : 0.0, lx, ly});
+      }
+    rank_groups();
+    // K(dy, dx) += sum_{a in lx} h_a(dx) sum_{b in ly} c_ab h_b(dy)
+    std::vector<double> col(ks);
+    for (int g = 0; g < N.n_spatial; ++g) {
+      const int lx = groups[g].lx, ly = groups[g].ly;
+      f.group_lx.push_back(lx);
+      f.group_ly.push_back(ly);
+      for (size_t a = 0; a < nf; ++a) {
+        if (fam[a].level != lx) continue;
+        std::fill(col.begin(), col.end(), 0.0);
+        for (size_t b = 0; b < nf; ++b) {
+          if (fam[b].level != ly) continue;
+          for (int d = -radius; d <= radius; ++d) col[d + radius] += C[b * nf + a] * fam[b].sample((double)d);
+        }
+        for (int dx = -radius; dx <= radius; ++dx) {
+          const double hx = fam[a].sample((double)dx);
+          if (hx == 0.0) continue;
+          for (int iy = 0; iy < ks; ++iy) f.K[(size_t)iy * ks + dx + radius] += hx * col[iy];
+        }
+      }
+    }
   }
   double kmax = 0;
   f.sum_abs_K = 0;
@@ -199,7 +369,7 @@ bf_status_t fit_plan(double sigma_s, double sigma_r, int radius, bf_terms_t N, d
   }
 
   // ---------------- range ----------------
-  f.T_r = sigma_r * std::sqrt(2.0 * std::log(1.0 / eps));
+  f.T_r = kernel_inverse(kind_r, sigma_r, eps);
   f.T = std::max(f.T_r, span);
   const int M = std::max(20 * N.n_range, 2);
   const int panels = std::max(256, 4 * M);
@@ -214,7 +384,7 @@ bf_status_t fit_plan(double sigma_s, double sigma_r, int radius, bf_terms_t N, d
     for (int i = 0; i < 16; ++i) {
       const double tt = lo + 0.5 * h * (gx[i] + 1.0);
       t.push_back(tt);
-      fw.push_back(0.5 * h * gw[i] * std::exp(-tt * tt / (2.0 * sigma_r * sigma_r)));
+      fw.push_back(0.5 * h * gw[i] * range_profile(kind_r, tt, sigma_r));
     }
   }
   std::vector<double> a(M);

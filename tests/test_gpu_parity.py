@@ -398,17 +398,63 @@ def test_precomputed_tables_refilter(torch_dev):
     I = torch.from_numpy(I_host).cuda()
     tp = bf.Plan(8.0, 0.1, 24, 16, 6)
     ws = bf.precompute(tp, I)
-    for ss, r, ns, sr, nr in [(8.0, 24, 6, 0.1, 16), (4.0, 12, 4, 0.2, 8), (2.0, 6, 4, 0.05, 16), (6.0, 18, 6, 0.3, 8)]:
-        p = bf.Plan(ss, sr, r, nr, ns)
+    for ss, r, ns, sr, nr, ks, kr in [(8.0, 24, 6, 0.1, 16, "gaussian", "gaussian"),
+                                      (4.0, 12, 4, 0.2, 8, "gaussian", "gaussian"),
+                                      (2.0, 6, 4, 0.05, 16, "gaussian", "gaussian"),
+                                      (6.0, 18, 6, 0.3, 8, "gaussian", "gaussian"),
+                                      (3.0, 14, 6, 0.1, 12, "exponential", "exponential")]:
+        # the tables hold C.I, S.I, C, S at omega_k = pi k / T: any kernel pair
+        # whose series has the same T and a prefix of k reuses them
+        p = bf.Plan(ss, sr, r, nr, ns, kernel_s=ks, kernel_r=kr)
         assert bf.precomputed_compatible(tp, p) == bf.BF_OK
         o = bf.filter_precomputed(tp, p, I, ws)
         d = bf.filter(p, I)
         torch.cuda.synchronize()
-        ref = oracle.expanded_box(I_host, oracle.make_plan(ss, r, ns, sr, nr))
+        ref = oracle.expanded_box(I_host, oracle.make_plan(ss, r, ns, sr, nr, kind_s=ks, kind_r=kr))
         err = np.abs(o.cpu().numpy() - ref).max()
-        _report("refilter sigma_s %g r %d N %d/%d from precomputed tables" % (ss, r, nr, ns), err)
+        _report("refilter %s/%s sigma_s %g r %d N %d/%d from precomputed tables" % (ks, kr, ss, r, nr, ns), err)
         assert err <= TIGHT
         assert (o - d).abs().max().item() <= 1e-6
+
+
+@pytest.mark.parametrize("H,W,ks,kr,ss,r,ns,sr,nr,dtype", [
+    (300, 517, "exponential", "exponential", 3.0, 14, 6, 0.1, 12, "f32"),   # default exp radius
+    (197, 263, "exponential", "gaussian", 2.0, 8, 4, 0.1, 8, "u8"),
+    (130, 129, "gaussian", "exponential", 4.0, 12, 4, 0.2, 16, "f32"),
+    (64, 700, "exponential", "exponential", 8.0, 37, 9, 0.05, 24, "u8"),
+    (5, 33, "exponential", "exponential", 2.0, 8, 6, 0.15, 10, "f32"),   # image smaller than the window
+])
+def test_exponential_kernels_vs_oracle(torch_dev, H, W, ks, kr, ss, r, ns, sr, nr, dtype):
+    """Other kernel shapes change only the fitted coefficients: the same
+    kernels filter them, against the oracle's T3 for the same kernel pair."""
+    bf = _bf()
+    I = synth.gen_image_u8(H, W, 5, 0.03, H * 3 + W) if dtype == "u8" else synth.gen_image(H, W, 5, 0.03, H * 3 + W)
+    p = bf.Plan(ss, sr, r, nr, ns, dtype=dtype, kernel_s=ks, kernel_r=kr)
+    o = oracle.make_plan(ss, r, ns, sr, nr, kind_s=ks, kind_r=kr)
+    out = _run(torch_dev, p, I)
+    ref = oracle.expanded_box(I, o)
+    err = np.abs(out - ref).max()
+    _report("K_s %s K_r %s %dx%d r %d %s vs T3" % (ks, kr, H, W, r, dtype), err)
+    true_err = np.abs(out - oracle.true_bf(I, ss, r, sr, kind_s=ks, kind_r=kr)).max()
+    _report("  same vs true BF (reported)", true_err)
+    assert err <= TIGHT
+
+
+@pytest.mark.parametrize("H,W,ks,kr,ss,r,sr,dtype", [
+    (197, 263, "exponential", "exponential", 2.0, 9, 0.1, "f32"),
+    (130, 129, "gaussian", "exponential", 3.0, 9, 0.2, "u8"),
+    (77, 64, "exponential", "gaussian", 4.0, 18, 0.05, "f32"),
+])
+def test_direct_summation_exponential_vs_true_bf(torch_dev, H, W, ks, kr, ss, r, sr, dtype):
+    bf = _bf()
+    I = synth.gen_image_u8(H, W, 4, 0.03, H + 5 * W) if dtype == "u8" else synth.gen_image(H, W, 4, 0.03, H + 5 * W)
+    p = bf.Plan(ss, sr, r, 8, 4, dtype=dtype, direct=True, kernel_s=ks, kernel_r=kr)
+    assert p.info.direct == 1
+    out = _run(torch_dev, p, I)
+    ref = oracle.true_bf(I, ss, r, sr, kind_s=ks, kind_r=kr)
+    err = np.abs(out - ref).max()
+    _report("direct K_s %s K_r %s %dx%d r %d %s vs T1" % (ks, kr, H, W, r, dtype), err)
+    assert err <= TIGHT
 
 
 @pytest.mark.parametrize("H,W,ss,r,sr,dtype", [

@@ -457,7 +457,7 @@ def test_cell_integrals_by_adaptive_quadrature(cells):
     ylo, xlo = -T + h * j, -T + h * i
     ref, _ = integrate.dblquad(lambda y, x: math.exp(-math.hypot(x, y) / ss), xlo, xlo + h, ylo, ylo + h,
                                epsabs=1e-14, epsrel=1e-13)
-    assert abs(M[j, i] - ref) <= 1e-8 * ref
+    assert abs(M[j, i] - ref) <= 1e-12 * ref
 
 
 def test_cell_fit_full_expansion_is_cell_average():

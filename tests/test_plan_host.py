@@ -143,9 +143,54 @@ def test_invalid_plan_arguments(kw):
 def test_default_radius_and_unsupported():
     p = bf.Plan(3.0, 0.1, 0, 8, 4, host_only=True)
     assert p.info.radius == int(np.ceil(3.0 * np.sqrt(2 * np.log(100))))
+    p = bf.Plan(3.0, 0.1, 0, 8, 4, host_only=True, kernel_s="exponential")
+    assert p.info.radius == int(np.ceil(3.0 * np.log(100)))
+    p = bf.Plan(3.0, 0.1, 9, 8, 4, host_only=True, kernel_r="exponential")
+    assert abs(p.info.T_r - 0.1 * np.log(100)) < 1e-15
     h = ctypes.c_void_p()
-    st = bf.lib().bf_plan_create(ctypes.byref(h), 1, 0, 3.0, 0.1, 9, bf._Terms(8, 4), None)
+    st = bf.lib().bf_plan_create(ctypes.byref(h), 2, 0, 3.0, 0.1, 9, bf._Terms(8, 4), None)
     assert st == bf.BF_ERR_UNSUPPORTED
+    st = bf.lib().bf_plan_create(ctypes.byref(h), 0, 7, 3.0, 0.1, 9, bf._Terms(8, 4), None)
+    assert st == bf.BF_ERR_UNSUPPORTED
+    st = bf.lib().bf_plan_create(ctypes.byref(h), -1, 0, 3.0, 0.1, 9, bf._Terms(8, 4), None)
+    assert st == bf.BF_ERR_INVALID_ARG
+    # the cell fit of a non-separable K_s is bounded in radius
+    st = bf.lib().bf_plan_create(ctypes.byref(h), 1, 0, 3.0, 0.1, 600, bf._Terms(8, 4), None)
+    assert st == bf.BF_ERR_UNSUPPORTED
+
+
+KIND_CASES = [("exponential", "gaussian", 3.0, 9, 4, 0.1, 8), ("exponential", "exponential", 2.0, 8, 6, 0.15, 10),
+              ("gaussian", "exponential", 3.0, 9, 4, 0.1, 8), ("exponential", "exponential", 5.0, 23, 9, 0.1, 16),
+              ("exponential", "gaussian", 1.0, 3, 9, 0.3, 4)]
+
+
+@pytest.mark.parametrize("ks,kr,ss,r,ns,sr,nr", KIND_CASES)
+def test_kernel_kinds_match_oracle(ks, kr, ss, r, ns, sr, nr):
+    """The library's fit of the exponential kernels (its own quadrature of the
+    cell integrals, prefix-table block sums) against the oracle's; the cell
+    integrals agree to the two quadratures' errors, near FP64 rounding)."""
+    p = bf.Plan(ss, sr, r, nr, ns, host_only=True, kernel_s=ks, kernel_r=kr)
+    o = oracle.make_plan(ss, r, ns, sr, nr, kind_s=ks, kind_r=kr)
+    assert p.spatial_groups() == o.spatial.selected
+    assert np.abs(p.spatial_kernel() - o.Ks).max() <= 1e-12 * np.abs(o.Ks).max()
+    k, a, w = p.range_terms()
+    assert k.tolist() == o.range.k.tolist()
+    assert np.abs(a - o.a).max() <= 1e-13
+    assert np.abs(w - o.omega).max() <= 1e-13
+    info = p.info
+    assert abs(info.T - o.range.T) < 1e-15
+    # both kernels are symmetric: every tap pairs into a quadruplet
+    assert info.n_single == 0 and 4 * info.n_quads == info.n_taps
+    # the taps reproduce the oracle's rectangle correlation
+    dy, dx, tw = p.taps()
+    g = synth.gen_image(40, 37, 4, 0.05, 3).astype(np.float64) - 0.3
+    S = _excl_sat(g)
+    ys, xs = np.mgrid[0:40, 0:37]
+    corr = np.zeros(g.shape)
+    for a_, b_, c_ in zip(dy, dx, tw):
+        corr += c_ * S[np.clip(ys + a_, 0, 40), np.clip(xs + b_, 0, 37)]
+    ref = oracle.correlate_rects(g, o.rects)
+    assert np.abs(corr - ref).max() < 1e-7
 
 
 def test_filter_rejects_bad_calls_without_touching_the_device():
