@@ -204,26 +204,46 @@ def spatial_fit(sigma_s, radius, n_spatial):
     return out
 
 
-def cell_integrals(kernel2d, T, n_cells, sub=4, nodes=12):
-    """M[j, i] = integral of K(x, y) over the finest cell (x in cell i, y in
-    cell j) of the grid of n_cells equal cells on [-T, T) per axis, by
-    composite tensor Gauss-Legendre (sub x sub panels of nodes^2 points per
-    cell).  The offset origin lies on cell corners, where the radial kernels
-    have their only non-smooth point."""
-    x, w = np.polynomial.legendre.leggauss(nodes)
-    h = 2.0 * T / n_cells
-    # 1-D nodes / weights inside one cell, relative to its left edge
+def _square_integral(kernel2d, x0, y0, h, sub, x, w):
+    """Tensor Gauss-Legendre over [x0, x0 + h) x [y0, y0 + h), sub x sub panels."""
     e = np.linspace(0.0, h, sub + 1)
     lo, hi = e[:-1, None], e[1:, None]
     t = (0.5 * (hi - lo) * x[None, :] + 0.5 * (hi + lo)).ravel()
     wt = (0.5 * (hi - lo) * w[None, :]).ravel()
+    return wt @ kernel2d((x0 + t)[None, :], (y0 + t)[:, None]) @ wt
+
+
+def cell_integrals(kernel2d, T, n_cells, sub=4, nodes=12, grading=24):
+    """M[j, i] = integral of K(x, y) over the finest cell (x in cell i, y in
+    cell j) of the grid of n_cells equal cells on [-T, T) per axis, by
+    composite tensor Gauss-Legendre (sub x sub panels of nodes^2 points per
+    cell).  The offset origin is a corner of four cells, and there radial
+    kernels have their only non-smooth point: those cells are split toward the
+    origin into squares of halving size (each L-shaped ring as three squares
+    that keep their distance from the corner), the last tiny corner square
+    taken as its area times K at its centre."""
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    h = 2.0 * T / n_cells
     edges = -T + h * np.arange(n_cells)
     M = np.empty((n_cells, n_cells))
     for j in range(n_cells):
-        Y = edges[j] + t
         for i in range(n_cells):
-            X = edges[i] + t
-            M[j, i] = wt @ kernel2d(X[None, :], Y[:, None]) @ wt
+            x0, y0 = edges[i], edges[j]
+            sx = 1.0 if abs(x0) < 1e-9 * h else (-1.0 if abs(x0 + h) < 1e-9 * h else 0.0)
+            sy = 1.0 if abs(y0) < 1e-9 * h else (-1.0 if abs(y0 + h) < 1e-9 * h else 0.0)
+            if sx == 0.0 or sy == 0.0:
+                M[j, i] = _square_integral(kernel2d, x0, y0, h, sub, x, w)
+                continue
+            # mirror onto the quadrant cell [0, h)^2 with its corner at the origin
+            k = lambda X, Y: kernel2d(sx * X, sy * Y)
+            total, s = 0.0, h
+            for _ in range(grading):
+                q = 0.5 * s
+                total += (_square_integral(k, q, 0.0, q, 1, x, w) + _square_integral(k, 0.0, q, q, 1, x, w)
+                          + _square_integral(k, q, q, q, 1, x, w))
+                s = q
+            total += s * s * float(k(np.array(0.5 * s), np.array(0.5 * s)))
+            M[j, i] = total
     return M
 
 
@@ -244,12 +264,16 @@ def spatial_fit_2d(kernel2d, radius, n_spatial):
     C = (Hm @ M @ Hm.T) / np.outer(norms, norms)           # C[b, a]: h_b in y, h_a in x
     levels = [PHI] + list(range(0, J + 1))
     lev = np.array([f.level for f in fam])
-    groups = []
+    energy = {}
     for lx in levels:
         for ly in levels:
             sb, sa = lev == ly, lev == lx
-            e = float(((C[np.ix_(sb, sa)] ** 2) * np.outer(norms[sb], norms[sa])).sum())
-            groups.append((_round_sig(e), lx, ly))
+            energy[lx, ly] = float(((C[np.ix_(sb, sa)] ** 2) * np.outer(norms[sb], norms[sa])).sum())
+    # groups whose coefficients vanish by symmetry hold only quadrature noise:
+    # below 1e-12 of the largest energy they count as zero (ties then fall to
+    # the level rule, as for the closed-form separable coefficients)
+    floor = 1e-12 * max(energy.values())
+    groups = [(_round_sig(e) if e > floor else 0.0, lx, ly) for (lx, ly), e in energy.items()]
     if not (1 <= n_spatial <= len(groups)):
         raise ValueError("n_spatial must be in [1, %d]" % len(groups))
     groups.sort(key=lambda g: (-g[0], g[1] + g[2], g[1]))
