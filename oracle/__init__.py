@@ -9,11 +9,11 @@ from .fit import (spatial_fit, spatial_rectangles, range_fit, range_kernel_appro
                   first_m_containing, cosine_coefficients, select_largest, PHI,
                   spatial_fit_2d, spatial_kernel_2d, range_kernel, cell_integrals, KINDS)
 from .filters import (Plan, make_plan, true_bf, expanded_brute, expanded_box,
-                      correlate_rects, to_unit)
+                      correlate_rects, to_unit, expanded_rangebox, expanded_sat3d, box_levels)
 
 __all__ = ["spatial_fit", "spatial_rectangles", "range_fit", "range_kernel_approx",
            "haar_family", "haar_coefficient", "gaussian_integral", "truncation_radius",
            "first_m_containing", "cosine_coefficients", "select_largest", "PHI",
            "spatial_fit_2d", "spatial_kernel_2d", "range_kernel", "cell_integrals", "KINDS",
            "Plan", "make_plan", "true_bf", "expanded_brute", "expanded_box",
-           "correlate_rects", "to_unit"]
+           "correlate_rects", "to_unit", "expanded_rangebox", "expanded_sat3d", "box_levels"]

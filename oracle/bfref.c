@@ -19,7 +19,13 @@
  *                          the rectangles of the Haar box representation
  *                          (App. A, Eq. 2D_box_N_terms).
  *
- * Conventions shared by all three: the weight of source pixel q for output p
+ *   T4  ref_expanded_rangebox  the paper's own regime for 8-bit images:
+ *                          the range series on [-T_r, T_r] times the range box
+ *                          (Eq. trigonometric_N_terms with its box factor,
+ *                          Eq. 1D_box_N_terms), summed pixel by pixel; the box
+ *                          keeps q when |Z(p) - Z(q)| <= 255 T_r in levels.
+ *
+ * Conventions shared by all of them: the weight of source pixel q for output p
  * is K_s(p - q) K_r(I(p) - I(q)); only in-image q contribute (borders);
  * out = num / den when den > den_floor, else out = I(p).
  */
@@ -185,4 +191,39 @@ int ref_correlate_rects(const double *g, int H, int W, const double *rects, int 
   correlate_rects(S, H, W, rects, nrect, corr);
   free(S);
   return 0;
+}
+
+/* T4: the expanded form with the range box, 8-bit levels Z (I = Z / 255).
+ * zr = 255 T_r: source q counts for output p when |Z(p) - Z(q)| <= zr. */
+void ref_expanded_rangebox(const uint8_t *Z, int H, int W, int r, const double *Ks, int nterms,
+                           const double *a, const double *omega, double zr, const int *ys,
+                           const int *xs, long npix, double den_floor, double *out,
+                           double *num_out, double *den_out) {
+  const int ks = 2 * r + 1;
+  long n = ys ? npix : (long)H * W;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long i = 0; i < n; ++i) {
+    int py = ys ? ys[i] : (int)(i / W), px = ys ? xs[i] : (int)(i % W);
+    const int zp = Z[(long)py * W + px];
+    double Ip = zp / 255.0, num = 0.0, den = 0.0;
+    for (int dy = -r; dy <= r; ++dy) {
+      int qy = py - dy;
+      if (qy < 0 || qy >= H) continue;
+      for (int dx = -r; dx <= r; ++dx) {
+        int qx = px - dx;
+        if (qx < 0 || qx >= W) continue;
+        const int zq = Z[(long)qy * W + qx];
+        if (fabs((double)(zp - zq)) > zr) continue; /* outside the range box */
+        double ws = Ks[(dy + r) * ks + (dx + r)];
+        if (ws == 0.0) continue;
+        double Iq = zq / 255.0, t = Ip - Iq, kr = 0.0;
+        for (int k = 0; k < nterms; ++k) kr += a[k] * cos(omega[k] * t);
+        num += ws * kr * Iq;
+        den += ws * kr;
+      }
+    }
+    out[i] = den > den_floor ? num / den : Ip;
+    if (num_out) num_out[i] = num;
+    if (den_out) den_out[i] = den;
+  }
 }

@@ -6,8 +6,17 @@ T2 expanded_brute  : Eq. BF with the N-term expansions of both kernels, direct s
 T3 expanded_box    : the same through the cosine shift identity (Eq. 1D_N_terms)
                      and FP64 summed-area-table box sums of the Haar rectangles
                      (Eqs. sum_sat_2D .. sum_sat_sum_region_2D, App. A).
+T4 expanded_rangebox : the paper's own regime for 8-bit images: range series on
+                     [-T_r, T_r] (T = T_r) times the range box |Z(p) - Z(q)| <=
+                     255 T_r (Eq. 1D_box_N_terms), direct sum.
+T5 expanded_sat3d  : the same quantity the paper's way: auxiliary volumes
+                     F(y, z) = G(y) delta_{Z(y)}(z) over the 256 levels, 3-D
+                     summed-area tables (Eqs. sat_sum_3D_1/2, sat_sum_1D) and
+                     cube sums per Haar rectangle (Eq. numerator_2D_box_N_terms);
+                     numpy, small images only.
 """
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -29,6 +38,9 @@ def _load():
         lib.ref_true_bf.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _ip, ctypes.c_long,
                                     ctypes.c_double, _dp]
+        lib.ref_expanded_rangebox.argtypes = [ctypes.POINTER(ctypes.c_uint8), ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_double,
+                                              _ip, _ip, ctypes.c_long, ctypes.c_double, _dp, _dp, _dp]
         lib.ref_expanded_brute.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                            ctypes.c_int, _dp, _dp, _ip, _ip, ctypes.c_long,
                                            ctypes.c_double, _dp, _dp, _dp]
@@ -140,4 +152,83 @@ def correlate_rects(g, rects):
     out = np.empty((H, W))
     if _load().ref_correlate_rects(_p(g), H, W, _p(rects), len(rects), _p(out)) != 0:
         raise MemoryError("oracle allocation failed")
+    return out
+
+
+def _levels(I):
+    Z = np.asarray(I)
+    if Z.dtype != np.uint8:
+        raise TypeError("the range-box regime is defined for 8-bit images")
+    return np.ascontiguousarray(Z)
+
+
+def box_levels(plan):
+    """255 T_r: the range box half-width in 8-bit levels (a level difference d
+    is inside the box when |d| <= 255 T_r)."""
+    return 255.0 * plan.range.T_r
+
+
+def expanded_rangebox(Z, plan, ys=None, xs=None, return_parts=False):
+    """T4 for an 8-bit image Z.  The plan must put the range series on
+    [-T_r, T_r] (span = 0)."""
+    Z = _levels(Z)
+    if abs(plan.range.T - plan.range.T_r) > 0:
+        raise ValueError("the range-box regime takes T = T_r (make the plan with span=0)")
+    H, W = Z.shape
+    ys, xs, n = _pixels(H, W, ys, xs)
+    out, num, den = np.empty(n), np.empty(n), np.empty(n)
+    _load().ref_expanded_rangebox(Z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), H, W,
+                                  int(plan.radius), _p(plan.Ks), len(plan.a), _p(plan.a),
+                                  _p(plan.omega), box_levels(plan), _p(ys, _ip), _p(xs, _ip), n,
+                                  plan.den_floor, _p(out), _p(num), _p(den))
+    shp = (H, W) if ys is None else (n,)
+    if return_parts:
+        return out.reshape(shp), num.reshape(shp), den.reshape(shp)
+    return out.reshape(shp)
+
+
+def expanded_sat3d(Z, plan, return_parts=False):
+    """T5: T4 computed with the paper's dimension promotion and 3-D summed-area
+    tables (small images: four H x W x 256 volumes per range term)."""
+    Z = _levels(Z).astype(np.int64)
+    H, W = Z.shape
+    I = Z / 255.0
+    zr = int(math.floor(box_levels(plan)))
+    zlo = np.clip(Z - zr, 0, 255)
+    zhi = np.clip(Z + zr, 0, 255) + 1          # exclusive
+    yy, xx = np.mgrid[0:H, 0:W]
+    num = np.zeros((H, W))
+    den = np.zeros((H, W))
+
+    def sat3(G):
+        F = np.zeros((H + 1, W + 1, 257))
+        F[yy + 1, xx + 1, Z + 1] = G           # F(y, z) = G(y) delta_{Z(y)}(z)
+        return F.cumsum(0).cumsum(1).cumsum(2)
+
+    def cube(S, y0, y1, x0, x1, z0, z1):       # sum over [y0, y1) x [x0, x1) x [z0, z1)
+        s = 0.0
+        for Y, sy in ((y1, 1), (y0, -1)):
+            for X, sx in ((x1, 1), (x0, -1)):
+                s = s + sy * sx * (S[Y, X, z1] - S[Y, X, z0])
+        return s
+
+    def correlate_cube(S):
+        acc = np.zeros((H, W))
+        for ey0, ey1, ex0, ex1, w in plan.rects:
+            # sources q = p - e with e in the rectangle, clipped to the image
+            y0 = np.clip(yy - int(ey1), 0, H)
+            y1 = np.clip(yy - int(ey0) + 1, 0, H)
+            x0 = np.clip(xx - int(ex1), 0, W)
+            x1 = np.clip(xx - int(ex0) + 1, 0, W)
+            ok = (y1 > y0) & (x1 > x0)
+            acc += w * np.where(ok, cube(S, y0, np.maximum(y1, y0), x0, np.maximum(x1, x0), zlo, zhi), 0.0)
+        return acc
+
+    for a, om in zip(plan.a, plan.omega):
+        c, s_ = np.cos(om * I), np.sin(om * I)
+        num += a * (c * correlate_cube(sat3(c * I)) + s_ * correlate_cube(sat3(s_ * I)))
+        den += a * (c * correlate_cube(sat3(c)) + s_ * correlate_cube(sat3(s_)))
+    out = np.where(den > plan.den_floor, num / np.where(den == 0, 1, den), I)
+    if return_parts:
+        return out, num, den
     return out

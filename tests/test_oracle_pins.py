@@ -548,3 +548,72 @@ def test_exponential_plan_T2_equals_T3():
     I = synth.gen_image(33, 41, 3, 0.03, 5)
     p = oracle.make_plan(2.5, 8, 6, 0.15, 12, kind_s="exponential", kind_r="exponential")
     assert np.abs(oracle.expanded_brute(I, p) - oracle.expanded_box(I, p)).max() < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# The paper's own regime for 8-bit images: T = T_r and the range box
+# (T4 direct sum, T5 dimension promotion with 3-D summed-area tables)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("H,W,ss,r,ns,sr,nr,seed", [
+    (23, 31, 2.0, 6, 4, 0.1, 5, 4), (17, 12, 1.5, 4, 6, 0.05, 8, 5), (20, 26, 3.0, 9, 4, 0.2, 3, 6),
+    (1, 1, 2.0, 6, 4, 0.1, 5, 7), (3, 40, 2.0, 6, 5, 0.08, 5, 8)])
+def test_rangebox_direct_sum_equals_3d_tables(H, W, ss, r, ns, sr, nr, seed):
+    """T4 (the definition summed pixel by pixel) and T5 (auxiliary volumes over
+    256 levels and 3-D summed-area tables, Eqs. sat_sum_3D_1/2) agree."""
+    Z = synth.gen_image_u8(H, W, 3, 0.03, seed)
+    p = oracle.make_plan(ss, r, ns, sr, nr, span=0.0)
+    assert p.range.T == p.range.T_r
+    a, na, da = oracle.expanded_rangebox(Z, p, return_parts=True)
+    b, nb, db = oracle.expanded_sat3d(Z, p, return_parts=True)
+    assert np.abs(na - nb).max() < 1e-12 and np.abs(da - db).max() < 1e-12
+    assert np.abs(a - b).max() < 1e-12
+
+
+def test_rangebox_wide_box_is_the_plain_expansion():
+    """With 255 T_r >= 255 every level difference is inside the box: T4 = T2."""
+    Z = synth.gen_image_u8(24, 28, 3, 0.03, 9)
+    p = oracle.make_plan(2.0, 6, 4, 0.45, 8, span=0.0)
+    assert oracle.box_levels(p) >= 255
+    assert np.abs(oracle.expanded_rangebox(Z, p) - oracle.expanded_brute(Z, p)).max() < 1e-15
+
+
+def _range_exact_with_box(Z, p, sr):
+    """Eq. BF with the plan's K~_s, the exact Gaussian K_r and the range box."""
+    H, W = Z.shape
+    I = Z / 255.0
+    r = p.radius
+    zr = oracle.box_levels(p)
+    out = np.zeros((H, W))
+    for py in range(H):
+        for px in range(W):
+            y0, y1, x0, x1 = max(0, py - r), min(H, py + r + 1), max(0, px - r), min(W, px + r + 1)
+            q = I[y0:y1, x0:x1]
+            dz = np.abs(Z[y0:y1, x0:x1].astype(int) - int(Z[py, px]))
+            ks = p.Ks[r + py - y1 + 1:r + py - y0 + 1, r + px - x1 + 1:r + px - x0 + 1][::-1, ::-1]
+            w = ks * np.exp(-(I[py, px] - q) ** 2 / (2 * sr * sr)) * (dz <= zr)
+            out[py, px] = (w * q).sum() / w.sum()
+    return out
+
+
+def test_rangebox_converges_in_range_terms():
+    """Range series on [-T_r, T_r]: few terms suffice in this regime (Sec. VI:
+    five terms; the kernel error at N = 5 is 3.8e-3) and the filter converges
+    to Eq. BF with the exact range kernel inside the box."""
+    Z = synth.gen_image_u8(24, 28, 3, 0.03, 9)
+    sr = 0.1
+    errs = []
+    for nr in (2, 3, 5, 16):
+        p = oracle.make_plan(2.0, 6, 4, sr, nr, span=0.0)
+        errs.append(np.abs(oracle.expanded_rangebox(Z, p) - _range_exact_with_box(Z, p, sr)).max())
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[2] < 2e-4
+    p = oracle.make_plan(2.0, 6, 4, sr, 5, span=0.0)
+    t = np.linspace(-p.range.T_r, p.range.T_r, 4001)
+    kerr = np.abs(oracle.range_kernel_approx(p.range, t) - np.exp(-t * t / (2 * sr * sr))).max()
+    assert 3.0e-3 < kerr < 4.0e-3
+
+
+def test_rangebox_constant_image_is_unchanged():
+    Z = np.full((9, 13), 77, dtype=np.uint8)
+    p = oracle.make_plan(2.0, 6, 4, 0.1, 5, span=0.0)
+    assert np.abs(oracle.expanded_rangebox(Z, p) - 77 / 255.0).max() < 1e-14
