@@ -91,6 +91,20 @@ typedef enum { BF_PREC_PLAIN = 0, BF_PREC_REDUCED = 1 } bf_precision_t;
  * bf_plan_info_t.direct says which. */
 #define BF_FLAG_DIRECT 0x2u
 #define BF_FLAG_DIRECT_AUTO 0x4u
+/* The paper's own regime for 8-bit input (Eq. trigonometric_N_terms with its
+ * range box, Eqs. 1D_box_N_terms / numerator_2D_box_N_terms): the range
+ * series lies on [-T_r, T_r] (T = T_r; span is ignored) and a source pixel q
+ * counts for output p only when |Z(p) - Z(q)| <= 255 T_r in levels.  Few
+ * range terms then suffice whatever sigma_r (five give a kernel error of
+ * 3.8e-3 at sigma_r = 0.1).  The cube sums over the promoted intensity axis
+ * are taken as rectangle sums of the level-window slab per output level (the
+ * sliding z window): one kernel, no workspace, cost about (distinct levels
+ * per 32 x 32 tile) x (term images) x (32 + 2r + 1)^2 per tile.
+ * BF_IN_U8 only (BF_ERR_UNSUPPORTED otherwise), radius <= 64, not with the
+ * DIRECT flags (BF_ERR_INVALID_ARG); no pre-computed tables, no autotuning.
+ * bf_plan_info_t.range_box and .box_levels (floor(255 T_r), at most 255)
+ * describe it. */
+#define BF_FLAG_RANGE_BOX 0x8u
 
 typedef struct {
   bf_dtype_t in_dtype;      /* input element type, default BF_IN_F32 */
@@ -174,6 +188,8 @@ typedef struct {
   int n_single;       /* taps outside any quadruplet */
   int lookup_kernel;  /* 1: LDS tile lookup kernel, 0: per-pixel lookup kernel */
   int direct;         /* 1: filters by direct summation (BF_FLAG_DIRECT / _AUTO) */
+  int range_box;      /* 1: the 8-bit range-box regime (BF_FLAG_RANGE_BOX) */
+  int box_levels;     /* its level window half-width floor(255 T_r); -1 otherwise */
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);

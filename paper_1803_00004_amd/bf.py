@@ -22,6 +22,7 @@ BF_PREC_PLAIN, BF_PREC_REDUCED = 0, 1
 BF_FLAG_HOST_ONLY = 0x1
 BF_FLAG_DIRECT = 0x2
 BF_FLAG_DIRECT_AUTO = 0x4
+BF_FLAG_RANGE_BOX = 0x8
 
 EXPORTED = [
     "bf_plan_create", "bf_plan_destroy", "bf_workspace_size", "bf_filter", "bf_filter_ws",
@@ -55,7 +56,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_images", ctypes.c_int), ("tile", ctypes.c_int), ("sat_shift", ctypes.c_int),
                 ("T_s", ctypes.c_double), ("T_r", ctypes.c_double), ("T", ctypes.c_double),
                 ("den_floor", ctypes.c_double), ("n_quads", ctypes.c_int), ("n_single", ctypes.c_int),
-                ("lookup_kernel", ctypes.c_int), ("direct", ctypes.c_int)]
+                ("lookup_kernel", ctypes.c_int), ("direct", ctypes.c_int), ("range_box", ctypes.c_int),
+                ("box_levels", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -136,16 +138,20 @@ class Plan:
 
     def __init__(self, sigma_s, sigma_r, radius=0, n_range=8, n_spatial=4, dtype="f32",
                  precision="plain", eps=0.0, span=0.0, tile=0, host_only=False, direct=False,
-                 kernel_s="gaussian", kernel_r="gaussian"):
+                 kernel_s="gaussian", kernel_r="gaussian", range_box=False):
         """direct: False (N-term expansion), True (direct summation of Eq. BF,
         BF_FLAG_DIRECT) or "auto" (direct where its cost model is lower).
-        kernel_s / kernel_r: "gaussian" or "exponential" (bf_kernel_t)."""
+        kernel_s / kernel_r: "gaussian" or "exponential" (bf_kernel_t).
+        range_box: the paper's own 8-bit regime, T = T_r with the range box
+        (BF_FLAG_RANGE_BOX; dtype "u8" only)."""
         self._h = ctypes.c_void_p()
         flags = BF_FLAG_HOST_ONLY if host_only else 0
         if direct == "auto":
             flags |= BF_FLAG_DIRECT_AUTO
         elif direct:
             flags |= BF_FLAG_DIRECT
+        if range_box:
+            flags |= BF_FLAG_RANGE_BOX
         opts = _Opts(BF_IN_U8 if dtype == "u8" else BF_IN_F32,
                      BF_PREC_REDUCED if precision == "reduced" else BF_PREC_PLAIN,
                      float(eps), float(span), int(tile), flags)

@@ -46,7 +46,7 @@ TuneKey tune_key(const bf_plan_s *p, int H, int W) {
 }
 
 bool tunable(const bf_plan_s *p) {
-  return p->tile == 0 && p->host_tables.n_single == 0 && !p->host_tables.direct;
+  return p->tile == 0 && p->host_tables.n_single == 0 && !p->host_tables.direct && !p->host_tables.range_box;
 }
 
 bf::Geometry geometry_with(const bf_plan_s *p, int H, int W, int tile_override, int kb_single,
@@ -56,7 +56,8 @@ bf::Geometry geometry_with(const bf_plan_s *p, int H, int W, int tile_override, 
   bf::choose_tiling(H, W, p->fit.radius, p->host_tables.n_terms, tile_override ? tile_override : p->tile,
                     p->gmax, box_edge, &tile, &q);
   // a direct plan keeps no tables: an empty workspace
-  bf::Geometry g = bf::make_geometry(H, W, tile, p->fit.radius, p->host_tables.direct ? 0 : p->host_tables.n_images, q);
+  const bool no_tables = p->host_tables.direct || p->host_tables.range_box;
+  bf::Geometry g = bf::make_geometry(H, W, tile, p->fit.radius, no_tables ? 0 : p->host_tables.n_images, q);
   g.kb_single = kb_single;
   g.ka_one = ka_one;
   return g;
@@ -107,7 +108,17 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
 
   bf_plan_s *p = new (std::nothrow) bf_plan_s();
   if (!p) return BF_ERR_OUT_OF_MEMORY;
-  bf_status_t st = bf::fit_plan((int)K_s, (int)K_r, sigma_s, sigma_r, radius, N, eps, span, &p->fit);
+  // the paper's own 8-bit regime: series on [-T_r, T_r] (span 0) and the range box
+  const bool range_box = (o.flags & BF_FLAG_RANGE_BOX) != 0;
+  if (range_box && (o.flags & (BF_FLAG_DIRECT | BF_FLAG_DIRECT_AUTO))) {
+    delete p;
+    return BF_ERR_INVALID_ARG;
+  }
+  if (range_box && o.in_dtype != BF_IN_U8) {
+    delete p;
+    return BF_ERR_UNSUPPORTED;
+  }
+  bf_status_t st = bf::fit_plan((int)K_s, (int)K_r, sigma_s, sigma_r, radius, N, eps, range_box ? 0.0 : span, &p->fit);
   if (st != BF_OK) {
     delete p;
     return st;
@@ -226,6 +237,15 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   // Cost model in vector operations per pixel, fitted to MI355X timings of
   // both paths at 1920 x 1080: direct 8.5 (2r + 1)^2; expansion
   // (1700 + n_images (85 + 10 quadruplets)) (1 + r / 120).
+  if (range_box) {
+    if (f.radius > bf::kMaxRangeBoxRadius || t.n_single != 0) {
+      delete p;
+      return BF_ERR_UNSUPPORTED;
+    }
+    t.range_box = 1;
+    t.direct_r = f.radius;
+    t.box_zr = (int)std::min(255.0, std::floor(255.0 * f.T_r));
+  }
   bool direct = (o.flags & BF_FLAG_DIRECT) != 0;
   if (!direct && (o.flags & BF_FLAG_DIRECT_AUTO) && f.radius <= bf::kMaxDirectRadius) {
     const double e = (double)(2 * f.radius + 1) * (2 * f.radius + 1);
@@ -513,7 +533,7 @@ bf_status_t bf_precompute_size(bf_plan_t tables_plan, int H, int W, size_t *byte
 bf_status_t bf_precompute(bf_plan_t tables_plan, const void *I, int H, int W, void *ws, size_t ws_bytes,
                           void *stream) {
   if (!tables_plan || !I || !ws || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
-  if (tables_plan->host_tables.direct) return BF_ERR_UNSUPPORTED;
+  if (tables_plan->host_tables.direct || tables_plan->host_tables.range_box) return BF_ERR_UNSUPPORTED;
   if (tables_plan->flags & BF_FLAG_HOST_ONLY) return BF_ERR_INVALID_ARG;
   const bf::Geometry g = precompute_geometry(tables_plan, H, W);
   const size_t in_bytes = (size_t)H * W * (tables_plan->in_dtype == BF_IN_U8 ? 1 : 4);
@@ -524,7 +544,9 @@ bf_status_t bf_precompute(bf_plan_t tables_plan, const void *I, int H, int W, vo
 
 bf_status_t bf_precomputed_compatible(bf_plan_t tables_plan, bf_plan_t plan) {
   if (!tables_plan || !plan) return BF_ERR_INVALID_ARG;
-  if (tables_plan->host_tables.direct || plan->host_tables.direct) return BF_ERR_UNSUPPORTED;
+  if (tables_plan->host_tables.direct || plan->host_tables.direct || tables_plan->host_tables.range_box ||
+      plan->host_tables.range_box)
+    return BF_ERR_UNSUPPORTED;
   const bf::DevTables &a = tables_plan->host_tables, &b = plan->host_tables;
   if (tables_plan->in_dtype != plan->in_dtype) return BF_ERR_INVALID_ARG;
   if (plan->fit.radius > tables_plan->fit.radius) return BF_ERR_INVALID_ARG;  // halo too small
@@ -563,6 +585,8 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   info->n_quads = plan->host_tables.n_quads;
   info->lookup_kernel = bf::lookup_kernel_kind(plan->host_tables);
   info->direct = plan->host_tables.direct;
+  info->range_box = plan->host_tables.range_box;
+  info->box_levels = plan->host_tables.range_box ? plan->host_tables.box_zr : -1;
   info->n_single = plan->host_tables.n_single;
   if (plan->host_tables.n_single == 0) {  // q depends on r and gmax only
     int tile = 0, q = 0;

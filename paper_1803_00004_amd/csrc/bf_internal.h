@@ -81,6 +81,10 @@ struct DevTables {
   int direct_abs;                      // range kernel in |d| (exponential) instead of d^2
   float direct_c;                      // K_r(d) = 2^(c d^2), or 2^(c |d|) when direct_abs
   const float *direct_ks;              // device: K_s(dy, dx) at (dy + r)(2r + 1) + dx + r
+                                       // (direct_r also holds the radius of range-box plans)
+  // range-box regime for 8-bit input (T = T_r, Eq. 1D_box_N_terms)
+  int range_box;
+  int box_zr;                          // level window half-width floor(255 T_r), <= 255
 };
 
 // Geometry of one image under a plan: tiles of `tile` outputs with their
@@ -115,6 +119,13 @@ void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double
 // Row pitch (int32 elements) of the LDS tile kernel's staged table region for
 // a region `width` columns wide: one of the compiled pitches, or 0 if none fits.
 int lds_pitch_for(int width);
+
+// The range-box regime (host.range_box) of an 8-bit image: one launch, no
+// workspace; BF_ERR_UNSUPPORTED when its staged region exceeds LDS.
+bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const void *I, float *out, float *num,
+                            float *den, int H, int W, void *stream);
+size_t rangebox_lds_bytes(const DevTables &host);
+constexpr int kMaxRangeBoxRadius = 64;
 
 // Direct summation of Eq. BF for a plan with host.direct set.
 bf_status_t launch_direct(const DevTables &host, const void *I, float *out, float *num, float *den,

@@ -492,3 +492,62 @@ def test_direct_plans_in_batches(torch_dev):
     torch.cuda.synchronize()
     for o, s in zip(outs, singles):
         assert torch.equal(o, s)
+
+
+@pytest.mark.parametrize("H,W,ss,r,ns,sr,nr", [
+    (300, 517, 2.0, 6, 4, 0.1, 5),     # several tiles, ragged tails
+    (197, 263, 3.0, 9, 6, 0.05, 8),
+    (130, 129, 8.0, 24, 6, 0.1, 5),
+    (70, 90, 16.0, 48, 8, 0.2, 3),
+    (64, 64, 20.0, 64, 4, 0.1, 5),     # largest radius of the regime
+    (5, 40, 2.0, 6, 4, 0.1, 5),        # image shorter than the window
+    (1, 1, 2.0, 6, 4, 0.1, 5),
+])
+def test_range_box_regime_vs_oracle(torch_dev, H, W, ss, r, ns, sr, nr):
+    """The paper's own 8-bit regime (T = T_r, range box) against the oracle's
+    direct sum T4."""
+    bf = _bf()
+    Z = synth.gen_image_u8(H, W, 5, 0.03, H * 7 + W)
+    p = bf.Plan(ss, sr, r, nr, ns, dtype="u8", range_box=True)
+    o = oracle.make_plan(ss, r, ns, sr, nr, span=0.0)
+    assert p.info.range_box == 1 and p.info.box_levels == int(np.floor(oracle.box_levels(o)))
+    assert abs(p.info.T - o.range.T_r) < 1e-15
+    out = _run(torch_dev, p, Z)
+    ref = oracle.expanded_rangebox(Z, o)
+    err = np.abs(out - ref).max()
+    _report("range box %dx%d r %d N %d zr %d vs T4" % (H, W, r, nr, p.info.box_levels), err)
+    assert err <= TIGHT
+
+
+def test_range_box_1080p_sampled(torch_dev):
+    """1920 x 1080 8-bit image, sigma_s 8 (r 24), sigma_r 0.1, five range terms:
+    2048 sampled pixels (borders, tile seams) against T4."""
+    bf = _bf()
+    H, W = 1080, 1920
+    Z = synth.gen_image_u8(H, W, 40, 0.03, 2)
+    p = bf.Plan(8.0, 0.1, 24, 5, 6, dtype="u8", range_box=True)
+    o = oracle.make_plan(8.0, 24, 6, 0.1, 5, span=0.0)
+    out = _run(torch_dev, p, Z)
+    rng = np.random.default_rng(5)
+    ys = np.concatenate([rng.integers(0, H, 1536), [0, H - 1, 31, 32, 0, H - 1], rng.integers(0, H, 506)])
+    xs = np.concatenate([rng.integers(0, W, 1536), [0, W - 1, 32, 31, W - 1, 0], rng.integers(0, W, 506)])
+    ref = oracle.expanded_rangebox(Z, o, ys=ys, xs=xs)
+    err = np.abs(out[ys, xs] - ref).max()
+    _report("range box 1080p sampled vs T4", err)
+    assert err <= TIGHT
+
+
+def test_range_box_in_batches(torch_dev):
+    """Range-box requests mixed with expansion requests in one batch: bitwise
+    the single-image results."""
+    import torch
+    bf = _bf()
+    pz = bf.Plan(3.0, 0.1, 9, 5, 4, dtype="u8", range_box=True)
+    pe = bf.Plan(3.0, 0.1, 9, 16, 4, dtype="u8")
+    imgs = [torch.from_numpy(synth.gen_image_u8(h, w, 4, 0.03, h + w)).cuda() for h, w in ((120, 333), (77, 64), (256, 256))]
+    plans = [pz, pe, pz]
+    singles = [bf.filter(p, I).clone() for p, I in zip(plans, imgs)]
+    outs = bf.filter_batch(plans, imgs)
+    torch.cuda.synchronize()
+    for o, s in zip(outs, singles):
+        assert torch.equal(o, s)

@@ -249,3 +249,26 @@ def test_direct_summation_choice():
     assert e.value.status == bf.BF_ERR_UNSUPPORTED
     p = bf.Plan(2.0, 0.1, 6, 8, 4, host_only=True, direct=True)
     assert p.workspace_size(500, 700) == 0
+
+
+def test_range_box_plan_rules():
+    """BF_FLAG_RANGE_BOX: 8-bit input only, T = T_r whatever span, radius <= 64,
+    not with the direct flags; no workspace, no pre-computed tables."""
+    p = bf.Plan(3.0, 0.1, 9, 5, 4, dtype="u8", range_box=True, span=2.0, host_only=True)
+    assert p.info.range_box == 1 and abs(p.info.T - p.info.T_r) < 1e-15
+    assert p.info.box_levels == int(np.floor(255 * 0.1 * np.sqrt(2 * np.log(100))))
+    assert p.workspace_size(1080, 1920) == 0
+    wide = bf.Plan(3.0, 0.5, 9, 5, 4, dtype="u8", range_box=True, host_only=True)
+    assert wide.info.box_levels == 255
+    with pytest.raises(bf.BFError) as e:
+        bf.Plan(3.0, 0.1, 9, 5, 4, dtype="f32", range_box=True, host_only=True)
+    assert e.value.status == bf.BF_ERR_UNSUPPORTED
+    with pytest.raises(bf.BFError) as e:
+        bf.Plan(25.0, 0.1, 75, 5, 4, dtype="u8", range_box=True, host_only=True)
+    assert e.value.status == bf.BF_ERR_UNSUPPORTED
+    with pytest.raises(bf.BFError) as e:
+        bf.Plan(3.0, 0.1, 9, 5, 4, dtype="u8", range_box=True, direct=True, host_only=True)
+    assert e.value.status == bf.BF_ERR_INVALID_ARG
+    o = oracle.make_plan(3.0, 9, 4, 0.1, 5, span=0.0)
+    k, a, w = p.range_terms()
+    assert k.tolist() == o.range.k.tolist() and np.abs(a - o.a).max() < 1e-13
