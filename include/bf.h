@@ -98,9 +98,10 @@ typedef enum { BF_PREC_PLAIN = 0, BF_PREC_REDUCED = 1 } bf_precision_t;
  * range terms then suffice whatever sigma_r (five give a kernel error of
  * 3.8e-3 at sigma_r = 0.1).  The cube sums over the promoted intensity axis
  * are taken as rectangle sums of the level-window slab per output level (the
- * sliding z window): one kernel, no workspace, cost about (distinct levels
- * per 32 x 32 tile) x (term images) x (32 + 2r + 1)^2 per tile.
- * BF_IN_U8 only (BF_ERR_UNSUPPORTED otherwise), radius <= 64, not with the
+ * sliding z window), with the range terms folded into one weight per level
+ * difference: one kernel, no workspace, two tables of (32 + 2r + 1)^2 per
+ * distinct level of each 32 x 32 output tile, whatever the number of terms.
+ * BF_IN_U8 only (BF_ERR_UNSUPPORTED otherwise), radius <= 48, not with the
  * DIRECT flags (BF_ERR_INVALID_ARG); no pre-computed tables, no autotuning.
  * bf_plan_info_t.range_box and .box_levels (floor(255 T_r), at most 255)
  * describe it. */

@@ -245,6 +245,22 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
     t.range_box = 1;
     t.direct_r = f.radius;
     t.box_zr = (int)std::min(255.0, std::floor(255.0 * f.T_r));
+    // the range terms folded per level difference d = L - z (8-bit input)
+    double wmax = 0.0;
+    for (int d = -255; d <= 255; ++d) {
+      double w = 0.0;
+      if (std::abs(d) <= t.box_zr)
+        for (size_t i = 0; i < f.k.size(); ++i) w += f.a[i] * std::cos(f.omega[i] * (d / 255.0));
+      t.box_w[d + 255] = w;
+      wmax = std::max(wmax, std::fabs(w));
+    }
+    // slab values |W(d) z / 255| <= wmax are stored as round(v 2^q); every box
+    // of a quadruplet lies inside the (2r+1)^2 window, so q is the largest
+    // shift (<= 24) with (2r + 1)^2 (wmax 2^q + 1) <= 2^31 - 1
+    const double area = (double)(2 * f.radius + 1) * (2 * f.radius + 1);
+    int q = 24;
+    while (q > 0 && area * (wmax * std::ldexp(1.0, q) + 1.0) > 2147483647.0) --q;
+    t.box_scale = std::ldexp(1.0, q);
   }
   bool direct = (o.flags & BF_FLAG_DIRECT) != 0;
   if (!direct && (o.flags & BF_FLAG_DIRECT_AUTO) && f.radius <= bf::kMaxDirectRadius) {
@@ -588,7 +604,9 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   info->range_box = plan->host_tables.range_box;
   info->box_levels = plan->host_tables.range_box ? plan->host_tables.box_zr : -1;
   info->n_single = plan->host_tables.n_single;
-  if (plan->host_tables.n_single == 0) {  // q depends on r and gmax only
+  if (plan->host_tables.range_box) {
+    info->sat_shift = (int)std::lround(std::log2(plan->host_tables.box_scale));
+  } else if (plan->host_tables.n_single == 0) {  // q depends on r and gmax only
     int tile = 0, q = 0;
     bf::choose_tiling(64, 64, f.radius, plan->host_tables.n_terms, 64, plan->gmax, 2 * f.radius + 1, &tile, &q);
     info->sat_shift = q;

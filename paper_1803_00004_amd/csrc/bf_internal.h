@@ -85,6 +85,8 @@ struct DevTables {
   // range-box regime for 8-bit input (T = T_r, Eq. 1D_box_N_terms)
   int range_box;
   int box_zr;                          // level window half-width floor(255 T_r), <= 255
+  double box_scale;                    // 2^q of the slab tables
+  double box_w[511];                   // W(d) = sum_k a_k cos(omega_k d / 255) [|d| <= zr] at d + 255
 };
 
 // Geometry of one image under a plan: tiles of `tile` outputs with their
@@ -125,7 +127,7 @@ int lds_pitch_for(int width);
 bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const void *I, float *out, float *num,
                             float *den, int H, int W, void *stream);
 size_t rangebox_lds_bytes(const DevTables &host);
-constexpr int kMaxRangeBoxRadius = 64;
+constexpr int kMaxRangeBoxRadius = 48;
 
 // Direct summation of Eq. BF for a plan with host.direct set.
 bf_status_t launch_direct(const DevTables &host, const void *I, float *out, float *num, float *den,

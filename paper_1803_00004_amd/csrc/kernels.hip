@@ -686,28 +686,35 @@ bf_status_t launch_direct(const DevTables &host, const void *I, float *out, floa
 
 // ---------------------------------------------------------------------------
 // K-Z: the paper's own regime for 8-bit images (range series on [-T_r, T_r]
-// times the range box, Eq. 1D_box_N_terms / numerator_2D_box_N_terms).  The
-// cube sum over a Haar rectangle x the level window [z_p - zr, z_p + zr] of
-// the auxiliary volume F(y, z) = G(y) delta_{Z(y)}(z) is, for every output
-// pixel of level L, the rectangle sum of the slab G(y) [|Z(y) - L| <= zr]:
-// the z-window sliding sum over the promoted dimension.  One block per 32 x 32
-// output tile stages the levels of the region its taps read, then for every
-// level L present among its outputs and every term image builds the slab's
-// summed-area table in LDS (row pass, then column pass, both as DPP wave
-// scans, int32 with wrapping adds) and lets the pixels of level L read their
-// quadruplet boxes from it.  Term values are the table kernel's fixed-point
-// integers (the byte itself and a count of one for k = 0).  No workspace.
+// times the range box, Eqs. 1D_box_N_terms / numerator_2D_box_N_terms).  A
+// cube sum over a Haar rectangle and the level window [z_p - zr, z_p + zr] of
+// the auxiliary volume F(y, z) = G(y) delta_{Z(y)}(z) is, for an output pixel
+// of level L, the rectangle sum of the slab G(y) [|Z(y) - L| <= zr] (the
+// sliding window over the promoted intensity axis).  For 8-bit input the
+// output's modulation cos / sin(omega_k L) is fixed by L, so the range terms
+// fold into one weight per level difference before the box sums:
+//   num(p) = sum_rect w_rect sum_{y in rect} W(L - Z(y)) I(y),
+//   den(p) = sum_rect w_rect sum_{y in rect} W(L - Z(y)),
+//   W(d) = sum_k a_k cos(omega_k d / 255) [|d| <= zr]   (tabulated in FP64),
+// two tables per output level whatever the number of range terms.  One block
+// per 32 x 32 output tile stages the levels of the region its taps read; for
+// every level L among its outputs it builds both slab tables at once in LDS
+// (int2 entries; row pass then column pass, each a DPP wave scan with int32
+// wrapping adds of round(v 2^q)) and the pixels of level L read their
+// quadruplet boxes.  No workspace.
 // ---------------------------------------------------------------------------
 constexpr int kZTile = 32;
+constexpr int kZThreads = 512;
 
-__global__ __launch_bounds__(256) void kz_rangebox(const uint8_t *__restrict__ I, int H, int W,
-                                                   const DevTables *__restrict__ tab, float scale,
-                                                   double inv_scale, float *__restrict__ out,
-                                                   float *__restrict__ num_out, float *__restrict__ den_out) {
+__global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restrict__ I, int H, int W,
+                                                         const DevTables *__restrict__ tab,
+                                                         float *__restrict__ out, float *__restrict__ num_out,
+                                                         float *__restrict__ den_out) {
+  constexpr int NW = kZThreads / 64, PPT = kZTile * kZTile / kZThreads;  // waves, pixels per thread
   extern __shared__ int4 kz_lds4[];
-  int *lut = reinterpret_cast<int *>(kz_lds4);  // [4][256]
-  uint32_t *mask = reinterpret_cast<uint32_t *>(lut + 4 * 256);  // 256 bits of output levels
-  int *sat = reinterpret_cast<int *>(mask + 8);
+  int2 *lut = reinterpret_cast<int2 *>(kz_lds4);                     // [256]: (num, den) slab values
+  uint32_t *mask = reinterpret_cast<uint32_t *>(lut + 256);          // 256 bits of output levels
+  int2 *sat = reinterpret_cast<int2 *>(mask + 8);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tiles_x = (W + kZTile - 1) / kZTile;
@@ -715,135 +722,96 @@ __global__ __launch_bounds__(256) void kz_rangebox(const uint8_t *__restrict__ I
   const int cy0 = min(max(ty0 + tab->tap_dy_min, 0), H), cy1 = min(max(ty0 + kZTile - 1 + tab->tap_dy_max, 0), H);
   const int cx0 = min(max(tx0 + tab->tap_dx_min, 0), W), cx1 = min(max(tx0 + kZTile - 1 + tab->tap_dx_max, 0), W);
   const int RS = cy1 - cy0, RC = cx1 - cx0;  // source rows / columns of the region
-  const int P = (RC + 1) | 1;                // odd pitch: column scans are bank-conflict free
+  const int P = (RC + 1) | 1;                // odd pitch (in int2): column scans are bank-conflict free
   uint8_t *lv = reinterpret_cast<uint8_t *>(sat + (RS + 1) * P);
   const int zr = tab->box_zr;
+  const double scale = tab->box_scale;
 
-  for (int i = tid; i < RS * RC; i += 256) {
+  for (int i = tid; i < RS * RC; i += kZThreads) {
     const int y = i / RC, x = i - y * RC;
     lv[i] = I[(long long)(cy0 + y) * W + cx0 + x];
   }
-  for (int x = tid; x < P; x += 256) sat[x] = 0;  // row 0 and column 0 stay zero
-  for (int y = tid; y <= RS; y += 256) sat[y * P] = 0;
+  for (int x = tid; x < P; x += kZThreads) sat[x] = make_int2(0, 0);  // row 0 and column 0 stay zero
+  for (int y = tid; y <= RS; y += kZThreads) sat[y * P] = make_int2(0, 0);
   if (tid < 8) mask[tid] = 0;
   __syncthreads();
-  int zp[4], py[4], px[4];
-  bool valid[4];
+  int zp[PPT], py[PPT], px[PPT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int pi = tid + 256 * i;
-    py[i] = ty0 + (pi >> 5);
-    px[i] = tx0 + (pi & 31);
-    valid[i] = py[i] < H && px[i] < W;
-    zp[i] = valid[i] ? (int)I[(long long)py[i] * W + px[i]] : -1;
-    if (valid[i]) atomicOr(&mask[zp[i] >> 5], 1u << (zp[i] & 31));
+  for (int i = 0; i < PPT; ++i) {
+    const int pi = tid + kZThreads * i;
+    py[i] = ty0 + pi / kZTile;
+    px[i] = tx0 + pi % kZTile;
+    zp[i] = (py[i] < H && px[i] < W) ? (int)I[(long long)py[i] * W + px[i]] : -1;
+    if (zp[i] >= 0) atomicOr(&mask[zp[i] >> 5], 1u << (zp[i] & 31));
   }
-  double num[4] = {0.0, 0.0, 0.0, 0.0}, den[4] = {0.0, 0.0, 0.0, 0.0};
   const int nq = tab->n_quads;
-
-  for (int t = 0; t < tab->n_terms; ++t) {
-    const bool k0 = tab->k_is_zero[t] != 0;
-    const float f_hi = tab->f_hi[t], f_lo = tab->f_lo[t];
-    __syncthreads();  // the previous term's table reads are done
-    {
-      const int b = tid;  // one byte value per thread
-      if (k0) {
-        lut[b] = b;          // I, in bytes
-        lut[256 + b] = 1;    // the count of the denominator
-      } else {
-        const float pxv = (float)b;
-        const float xs = pxv * (1.0f / 255.0f) * scale;
-        const float fr = phase_rev(f_hi, f_lo, pxv);
-        const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
-        lut[b] = __float2int_rn(C * xs);
-        lut[256 + b] = __float2int_rn(S * xs);
-        lut[512 + b] = __float2int_rn(C * scale);
-        lut[768 + b] = __float2int_rn(S * scale);
+  for (int wd = 0; wd < 8; ++wd) {
+    __syncthreads();  // the mask is complete
+    uint32_t bits = (uint32_t)__builtin_amdgcn_readfirstlane((int)mask[wd]);
+    while (bits) {
+      const int L = wd * 32 + __builtin_ctz(bits);
+      bits &= bits - 1;
+      if (tid < 256) {  // slab values of level L at source level z = tid
+        const int z = tid;
+        const double w = tab->box_w[L - z + 255];
+        lut[z] = make_int2(__double2int_rn(w * (z * (1.0 / 255.0)) * scale), __double2int_rn(w * scale));
       }
-    }
-    const int nimg = k0 ? 2 : 4;
-    double acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) acc[i][m] = 0.0;
-    __syncthreads();
-    for (int wd = 0; wd < 8; ++wd) {
-      uint32_t bits = (uint32_t)__builtin_amdgcn_readfirstlane((int)mask[wd]);
-      while (bits) {
-        const int L = wd * 32 + __builtin_ctz(bits);
-        bits &= bits - 1;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          if (m >= nimg) break;
-          const int *lm = lut + 256 * m;
-          // row pass: wave per region row, 64 columns per scan, carry between chunks
-          for (int y = wave; y < RS; y += 4) {
-            uint32_t carry = 0;
-            for (int c0 = 0; c0 < RC; c0 += 64) {
-              const int x = c0 + lane;
-              uint32_t v = 0;
-              if (x < RC) {
-                const int z = lv[y * RC + x];
-                if (abs(z - L) <= zr) v = (uint32_t)lm[z];
-              }
-              const uint32_t sc = wave_inclusive_scan(v) + carry;
-              if (x < RC) sat[(y + 1) * P + x + 1] = (int)sc;
-              carry = (uint32_t)__builtin_amdgcn_readlane((int)sc, 63);
-            }
+      __syncthreads();
+      // row pass: wave per region row, 64 columns per scan, carry between chunks
+      for (int y = wave; y < RS; y += NW) {
+        uint32_t cn = 0, cd = 0;
+        for (int c0 = 0; c0 < RC; c0 += 64) {
+          const int x = c0 + lane;
+          int2 v = make_int2(0, 0);
+          if (x < RC) {
+            const int z = lv[y * RC + x];
+            if (abs(z - L) <= zr) v = lut[z];
           }
-          __syncthreads();
-          // column pass: wave per region column, 64 rows per scan
-          for (int x = wave; x < RC; x += 4) {
-            uint32_t carry = 0;
-            for (int r0 = 0; r0 < RS; r0 += 64) {
-              const int y = r0 + lane;
-              const uint32_t v = y < RS ? (uint32_t)sat[(y + 1) * P + x + 1] : 0u;
-              const uint32_t sc = wave_inclusive_scan(v) + carry;
-              if (y < RS) sat[(y + 1) * P + x + 1] = (int)sc;
-              carry = (uint32_t)__builtin_amdgcn_readlane((int)sc, 63);
-            }
-          }
-          __syncthreads();
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (zp[i] != L) continue;
-            double sacc = 0.0;
-            for (int q = 0; q < nq; ++q) {
-              const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
-              const int Ya = min(max(py[i] + dy, 0), H) - cy0, Yb = min(max(py[i] + 1 - dy, 0), H) - cy0;
-              const int Xa = min(max(px[i] + dx, 0), W) - cx0, Xb = min(max(px[i] + 1 - dx, 0), W) - cx0;
-              const int box = box_of(sat[Ya * P + Xa], sat[Yb * P + Xa], sat[Ya * P + Xb], sat[Yb * P + Xb]);
-              sacc = __builtin_fma(tab->quad_w[q], (double)box, sacc);
-            }
-            acc[i][m] = sacc;
-          }
-          __syncthreads();  // before the next table overwrites this one
+          const uint32_t sn = wave_inclusive_scan((uint32_t)v.x) + cn;
+          const uint32_t sd = wave_inclusive_scan((uint32_t)v.y) + cd;
+          if (x < RC) sat[(y + 1) * P + x + 1] = make_int2((int)sn, (int)sd);
+          cn = (uint32_t)__builtin_amdgcn_readlane((int)sn, 63);
+          cd = (uint32_t)__builtin_amdgcn_readlane((int)sd, 63);
         }
       }
-    }
-    const double a = tab->a[t];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (!valid[i]) continue;
-      if (k0) {
-        num[i] = __builtin_fma(a * (1.0 / 255.0), acc[i][0], num[i]);
-        den[i] = __builtin_fma(a, acc[i][1], den[i]);
-      } else {
-        const float fr = phase_rev(f_hi, f_lo, (float)zp[i]);
-        const double C = (double)__builtin_amdgcn_cosf(fr), S = (double)__builtin_amdgcn_sinf(fr);
-        num[i] = __builtin_fma(a * inv_scale, C * acc[i][0] + S * acc[i][1], num[i]);
-        den[i] = __builtin_fma(a * inv_scale, C * acc[i][2] + S * acc[i][3], den[i]);
+      __syncthreads();
+      // column pass: wave per region column, 64 rows per scan
+      for (int x = wave; x < RC; x += NW) {
+        uint32_t cn = 0, cd = 0;
+        for (int r0 = 0; r0 < RS; r0 += 64) {
+          const int y = r0 + lane;
+          const int2 v = y < RS ? sat[(y + 1) * P + x + 1] : make_int2(0, 0);
+          const uint32_t sn = wave_inclusive_scan((uint32_t)v.x) + cn;
+          const uint32_t sd = wave_inclusive_scan((uint32_t)v.y) + cd;
+          if (y < RS) sat[(y + 1) * P + x + 1] = make_int2((int)sn, (int)sd);
+          cn = (uint32_t)__builtin_amdgcn_readlane((int)sn, 63);
+          cd = (uint32_t)__builtin_amdgcn_readlane((int)sd, 63);
+        }
       }
-    }
-  }
+      __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (!valid[i]) continue;
-    const long long idx = (long long)py[i] * W + px[i];
-    out[idx] = den[i] > tab->den_floor ? (float)(num[i] / den[i]) : (float)zp[i] * (1.0f / 255.0f);
-    if (num_out) num_out[idx] = (float)num[i];
-    if (den_out) den_out[idx] = (float)den[i];
+      for (int i = 0; i < PPT; ++i) {
+        if (zp[i] != L) continue;
+        double num = 0.0, den = 0.0;
+        for (int q = 0; q < nq; ++q) {
+          const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
+          const int Ya = min(max(py[i] + dy, 0), H) - cy0, Yb = min(max(py[i] + 1 - dy, 0), H) - cy0;
+          const int Xa = min(max(px[i] + dx, 0), W) - cx0, Xb = min(max(px[i] + 1 - dx, 0), W) - cx0;
+          const int2 a = sat[Ya * P + Xa], b = sat[Yb * P + Xa], c = sat[Ya * P + Xb], d = sat[Yb * P + Xb];
+          const double w = tab->quad_w[q];
+          num = __builtin_fma(w, (double)box_of(a.x, b.x, c.x, d.x), num);
+          den = __builtin_fma(w, (double)box_of(a.y, b.y, c.y, d.y), den);
+        }
+        const double inv = 1.0 / scale;
+        num *= inv;
+        den *= inv;
+        const long long idx = (long long)py[i] * W + px[i];
+        out[idx] = den > tab->den_floor ? (float)(num / den) : (float)L * (1.0f / 255.0f);
+        if (num_out) num_out[idx] = (float)num;
+        if (den_out) den_out[idx] = (float)den;
+      }
+      __syncthreads();  // before the next level overwrites the tables
+    }
   }
 }
 
@@ -851,14 +819,12 @@ size_t rangebox_lds_bytes(const DevTables &host) {
   const int RS = kZTile - 1 + host.tap_dy_max - host.tap_dy_min;  // largest region
   const int RC = kZTile - 1 + host.tap_dx_max - host.tap_dx_min;
   const int P = (RC + 1) | 1;
-  return 4 * 256 * 4 + 32 + (size_t)(RS + 1) * P * 4 + (size_t)RS * RC;
+  return 256 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)RS * RC;
 }
 
 bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const void *I, float *out, float *num,
                             float *den, int H, int W, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int tile = 0, q = 0;
-  choose_tiling(H, W, host.direct_r, host.n_terms, 64, 1.0, 2 * host.direct_r + 1, &tile, &q);
   const size_t lds = rangebox_lds_bytes(host);
   if (lds > 160 * 1024) return BF_ERR_UNSUPPORTED;
   const int blocks = ((W + kZTile - 1) / kZTile) * ((H + kZTile - 1) / kZTile);
@@ -866,8 +832,8 @@ bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const v
   if (hipFuncSetAttribute((const void *)kz_rangebox, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
       hipSuccess)
     return BF_ERR_DEVICE;
-  hipLaunchKernelGGL(kz_rangebox, dim3(blocks), dim3(256), lds, s, static_cast<const uint8_t *>(I), H, W, dev,
-                     std::ldexp(1.0f, q), std::ldexp(1.0, -q), out, num, den);
+  hipLaunchKernelGGL(kz_rangebox, dim3(blocks), dim3(kZThreads), lds, s, static_cast<const uint8_t *>(I), H, W,
+                     dev, out, num, den);
   const hipError_t e = hipGetLastError();
   profile_mark(1, 0, stream);
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;

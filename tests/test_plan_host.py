@@ -252,7 +252,7 @@ def test_direct_summation_choice():
 
 
 def test_range_box_plan_rules():
-    """BF_FLAG_RANGE_BOX: 8-bit input only, T = T_r whatever span, radius <= 64,
+    """BF_FLAG_RANGE_BOX: 8-bit input only, T = T_r whatever span, radius <= 48,
     not with the direct flags; no workspace, no pre-computed tables."""
     p = bf.Plan(3.0, 0.1, 9, 5, 4, dtype="u8", range_box=True, span=2.0, host_only=True)
     assert p.info.range_box == 1 and abs(p.info.T - p.info.T_r) < 1e-15
@@ -264,7 +264,7 @@ def test_range_box_plan_rules():
         bf.Plan(3.0, 0.1, 9, 5, 4, dtype="f32", range_box=True, host_only=True)
     assert e.value.status == bf.BF_ERR_UNSUPPORTED
     with pytest.raises(bf.BFError) as e:
-        bf.Plan(25.0, 0.1, 75, 5, 4, dtype="u8", range_box=True, host_only=True)
+        bf.Plan(20.0, 0.1, 60, 5, 4, dtype="u8", range_box=True, host_only=True)
     assert e.value.status == bf.BF_ERR_UNSUPPORTED
     with pytest.raises(bf.BFError) as e:
         bf.Plan(3.0, 0.1, 9, 5, 4, dtype="u8", range_box=True, direct=True, host_only=True)
