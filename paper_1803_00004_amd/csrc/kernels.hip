@@ -705,12 +705,14 @@ bf_status_t launch_direct(const DevTables &host, const void *I, float *out, floa
 // ---------------------------------------------------------------------------
 constexpr int kZTile = 32;
 constexpr int kZThreads = 512;
+constexpr int kZWaves = kZThreads / 64;
+constexpr int kZSeg = 16;  // region rows per wave (region <= 128 rows: radius <= 48)
 
 __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restrict__ I, int H, int W,
                                                          const DevTables *__restrict__ tab,
                                                          float *__restrict__ out, float *__restrict__ num_out,
                                                          float *__restrict__ den_out) {
-  constexpr int NW = kZThreads / 64, PPT = kZTile * kZTile / kZThreads;  // waves, pixels per thread
+  constexpr int PPT = kZTile * kZTile / kZThreads;  // pixels per thread
   extern __shared__ int4 kz_lds4[];
   int2 *lut = reinterpret_cast<int2 *>(kz_lds4);                     // [256]: (num, den) slab values
   uint32_t *mask = reinterpret_cast<uint32_t *>(lut + 256);          // 256 bits of output levels
@@ -721,32 +723,79 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   const int ty0 = (blockIdx.x / tiles_x) * kZTile, tx0 = (blockIdx.x % tiles_x) * kZTile;
   const int cy0 = min(max(ty0 + tab->tap_dy_min, 0), H), cy1 = min(max(ty0 + kZTile - 1 + tab->tap_dy_max, 0), H);
   const int cx0 = min(max(tx0 + tab->tap_dx_min, 0), W), cx1 = min(max(tx0 + kZTile - 1 + tab->tap_dx_max, 0), W);
-  const int RS = cy1 - cy0, RC = cx1 - cx0;  // source rows / columns of the region
-  const int P = (RC + 1) | 1;                // odd pitch (in int2): column scans are bank-conflict free
-  uint8_t *lv = reinterpret_cast<uint8_t *>(sat + (RS + 1) * P);
+  const int RS = cy1 - cy0, RC = cx1 - cx0;  // source rows / columns of the region (<= 128 each)
+  const int P = RC + 2;                      // table pitch in int2
+  int2 *carry = sat + (RS + 1) * P;          // [kZWaves][RC + 1]: table totals of the segments above
+  // the region's levels while they are staged; afterwards the pixel lists
+  uint8_t *lv = reinterpret_cast<uint8_t *>(carry + kZWaves * (RC + 1));
+  int *start = reinterpret_cast<int *>(lv);       // [257]: first list slot of each output level
+  int *cursor = start + 257;                       // [256]
+  int *segoff = cursor + 256;                      // [129]: carry row of table row Y
+  uint16_t *list = reinterpret_cast<uint16_t *>(segoff + 129);  // [1024]: tile pixels by level
   const int zr = tab->box_zr;
   const double scale = tab->box_scale;
+  // wave w builds the region rows [w seg, (w + 1) seg) with sums restarting at
+  // its first row; lane l holds the columns 2l, 2l + 1
+  const int seg = (RS + kZWaves - 1) / kZWaves;
+  const int ry0 = wave * seg, nrows = max(0, min(seg, RS - ry0));
 
   for (int i = tid; i < RS * RC; i += kZThreads) {
     const int y = i / RC, x = i - y * RC;
     lv[i] = I[(long long)(cy0 + y) * W + cx0 + x];
   }
-  for (int x = tid; x < P; x += kZThreads) sat[x] = make_int2(0, 0);  // row 0 and column 0 stay zero
+  for (int x = tid; x < P; x += kZThreads) sat[x] = make_int2(0, 0);  // table row 0 and column 0 stay zero
   for (int y = tid; y <= RS; y += kZThreads) sat[y * P] = make_int2(0, 0);
   if (tid < 8) mask[tid] = 0;
   __syncthreads();
-  int zp[PPT], py[PPT], px[PPT];
+  // the wave's levels in registers, two columns per lane (512: outside the region)
+  uint32_t zq[kZSeg];
+#pragma unroll
+  for (int i = 0; i < kZSeg; ++i) {
+    const int y = ry0 + i, x = 2 * lane;
+    const uint32_t a = (i < nrows && x < RC) ? lv[y * RC + x] : 512u;
+    const uint32_t b = (i < nrows && x + 1 < RC) ? lv[y * RC + x + 1] : 512u;
+    zq[i] = a | (b << 16);
+  }
+  __syncthreads();  // lv is dead: its bytes now hold the level lists
+  for (int i = tid; i < 257 + 256; i += kZThreads) start[i] = 0;  // start and cursor
+  for (int Y = tid; Y <= RS; Y += kZThreads) segoff[Y] = Y == 0 ? 0 : ((Y - 1) / seg) * (RC + 1);
+  __syncthreads();
+  int zp[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
     const int pi = tid + kZThreads * i;
-    py[i] = ty0 + pi / kZTile;
-    px[i] = tx0 + pi % kZTile;
-    zp[i] = (py[i] < H && px[i] < W) ? (int)I[(long long)py[i] * W + px[i]] : -1;
-    if (zp[i] >= 0) atomicOr(&mask[zp[i] >> 5], 1u << (zp[i] & 31));
+    const int py = ty0 + pi / kZTile, px = tx0 + pi % kZTile;
+    zp[i] = (py < H && px < W) ? (int)I[(long long)py * W + px] : -1;
+    if (zp[i] >= 0) {
+      atomicOr(&mask[zp[i] >> 5], 1u << (zp[i] & 31));
+      atomicAdd(&cursor[zp[i]], 1);
+    }
   }
+  __syncthreads();
+  if (wave == 0) {  // exclusive prefix of the level counts: four levels per lane
+    int c[4], t = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      c[k] = cursor[4 * lane + k];
+      t += c[k];
+    }
+    int e = (int)wave_inclusive_scan((uint32_t)t) - t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      start[4 * lane + k] = e;
+      cursor[4 * lane + k] = e;
+      e += c[k];
+    }
+    if (lane == 63) start[256] = e;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PPT; ++i)
+    if (zp[i] >= 0) list[atomicAdd(&cursor[zp[i]], 1)] = (uint16_t)(tid + kZThreads * i);
+
   const int nq = tab->n_quads;
   for (int wd = 0; wd < 8; ++wd) {
-    __syncthreads();  // the mask is complete
+    __syncthreads();  // the mask and the lists are complete
     uint32_t bits = (uint32_t)__builtin_amdgcn_readfirstlane((int)mask[wd]);
     while (bits) {
       const int L = wd * 32 + __builtin_ctz(bits);
@@ -757,47 +806,57 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
         lut[z] = make_int2(__double2int_rn(w * (z * (1.0 / 255.0)) * scale), __double2int_rn(w * scale));
       }
       __syncthreads();
-      // row pass: wave per region row, 64 columns per scan, carry between chunks
-      for (int y = wave; y < RS; y += NW) {
-        uint32_t cn = 0, cd = 0;
-        for (int c0 = 0; c0 < RC; c0 += 64) {
-          const int x = c0 + lane;
-          int2 v = make_int2(0, 0);
-          if (x < RC) {
-            const int z = lv[y * RC + x];
-            if (abs(z - L) <= zr) v = lut[z];
-          }
-          const uint32_t sn = wave_inclusive_scan((uint32_t)v.x) + cn;
-          const uint32_t sd = wave_inclusive_scan((uint32_t)v.y) + cd;
-          if (x < RC) sat[(y + 1) * P + x + 1] = make_int2((int)sn, (int)sd);
-          cn = (uint32_t)__builtin_amdgcn_readlane((int)sn, 63);
-          cd = (uint32_t)__builtin_amdgcn_readlane((int)sd, 63);
-        }
-      }
-      __syncthreads();
-      // column pass: wave per region column, 64 rows per scan
-      for (int x = wave; x < RC; x += NW) {
-        uint32_t cn = 0, cd = 0;
-        for (int r0 = 0; r0 < RS; r0 += 64) {
-          const int y = r0 + lane;
-          const int2 v = y < RS ? sat[(y + 1) * P + x + 1] : make_int2(0, 0);
-          const uint32_t sn = wave_inclusive_scan((uint32_t)v.x) + cn;
-          const uint32_t sd = wave_inclusive_scan((uint32_t)v.y) + cd;
-          if (y < RS) sat[(y + 1) * P + x + 1] = make_int2((int)sn, (int)sd);
-          cn = (uint32_t)__builtin_amdgcn_readlane((int)sn, 63);
-          cd = (uint32_t)__builtin_amdgcn_readlane((int)sd, 63);
-        }
-      }
-      __syncthreads();
+      // column sums down the wave's rows in registers, a row scan across the
+      // lanes per row: the table of the segment, restarted at its first row
+      uint32_t c0n = 0, c0d = 0, c1n = 0, c1d = 0;
 #pragma unroll
-      for (int i = 0; i < PPT; ++i) {
-        if (zp[i] != L) continue;
+      for (int i = 0; i < kZSeg; ++i) {
+        if (i >= nrows) break;
+        const int za = (int)(zq[i] & 0xffffu), zb = (int)(zq[i] >> 16);
+        int2 va = make_int2(0, 0), vb = make_int2(0, 0);
+        if (abs(za - L) <= zr) va = lut[za];
+        if (abs(zb - L) <= zr) vb = lut[zb];
+        c0n += (uint32_t)va.x;
+        c0d += (uint32_t)va.y;
+        c1n += (uint32_t)vb.x;
+        c1d += (uint32_t)vb.y;
+        const uint32_t tn = c0n + c1n, td = c0d + c1d;
+        const uint32_t en = wave_inclusive_scan(tn) - tn, ed = wave_inclusive_scan(td) - td;
+        const int x = 2 * lane;
+        int2 *row = sat + (ry0 + i + 1) * P + x + 1;
+        if (x < RC) row[0] = make_int2((int)(en + c0n), (int)(ed + c0d));
+        if (x + 1 < RC) row[1] = make_int2((int)(en + tn), (int)(ed + td));
+      }
+      __syncthreads();
+      // carries: totals of the segments above, per table column
+      for (int X = tid; X <= RC; X += kZThreads) {
+        uint32_t rn = 0, rd = 0;
+        for (int w = 0; w < kZWaves; ++w) {
+          carry[w * (RC + 1) + X] = make_int2((int)rn, (int)rd);
+          const int last = min((w + 1) * seg, RS);  // table row of the segment's last region row
+          if (w * seg < RS) {
+            const int2 v = sat[last * P + X];
+            rn += (uint32_t)v.x;
+            rd += (uint32_t)v.y;
+          }
+        }
+      }
+      __syncthreads();
+      auto corner = [&](int Y, int X) -> int2 {  // table entry (Y, X) of level L's slabs (row 0: zero)
+        const int2 v = sat[Y * P + X], c = carry[segoff[Y] + X];
+        return make_int2((int)((uint32_t)v.x + (uint32_t)c.x), (int)((uint32_t)v.y + (uint32_t)c.y));
+      };
+      // the pixels of level L, one per thread
+      const int s0 = start[L], cnt = start[L + 1] - s0;
+      for (int j = tid; j < cnt; j += kZThreads) {
+        const int pi = list[s0 + j];
+        const int py = ty0 + pi / kZTile, px = tx0 + pi % kZTile;
         double num = 0.0, den = 0.0;
         for (int q = 0; q < nq; ++q) {
           const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
-          const int Ya = min(max(py[i] + dy, 0), H) - cy0, Yb = min(max(py[i] + 1 - dy, 0), H) - cy0;
-          const int Xa = min(max(px[i] + dx, 0), W) - cx0, Xb = min(max(px[i] + 1 - dx, 0), W) - cx0;
-          const int2 a = sat[Ya * P + Xa], b = sat[Yb * P + Xa], c = sat[Ya * P + Xb], d = sat[Yb * P + Xb];
+          const int Ya = min(max(py + dy, 0), H) - cy0, Yb = min(max(py + 1 - dy, 0), H) - cy0;
+          const int Xa = min(max(px + dx, 0), W) - cx0, Xb = min(max(px + 1 - dx, 0), W) - cx0;
+          const int2 a = corner(Ya, Xa), b = corner(Yb, Xa), c = corner(Ya, Xb), d = corner(Yb, Xb);
           const double w = tab->quad_w[q];
           num = __builtin_fma(w, (double)box_of(a.x, b.x, c.x, d.x), num);
           den = __builtin_fma(w, (double)box_of(a.y, b.y, c.y, d.y), den);
@@ -805,7 +864,7 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
         const double inv = 1.0 / scale;
         num *= inv;
         den *= inv;
-        const long long idx = (long long)py[i] * W + px[i];
+        const long long idx = (long long)py * W + px;
         out[idx] = den > tab->den_floor ? (float)(num / den) : (float)L * (1.0f / 255.0f);
         if (num_out) num_out[idx] = (float)num;
         if (den_out) den_out[idx] = (float)den;
@@ -818,8 +877,10 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
 size_t rangebox_lds_bytes(const DevTables &host) {
   const int RS = kZTile - 1 + host.tap_dy_max - host.tap_dy_min;  // largest region
   const int RC = kZTile - 1 + host.tap_dx_max - host.tap_dx_min;
-  const int P = (RC + 1) | 1;
-  return 256 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)RS * RC;
+  if (RS > kZWaves * kZSeg || RC > 128) return (size_t)-1;
+  const int P = RC + 2;
+  const size_t lists = (257 + 256 + 129) * 4 + 1024 * 2;  // share the bytes of the staged levels
+  return 256 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)kZWaves * (RC + 1) * 8 + std::max((size_t)RS * RC, lists);
 }
 
 bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const void *I, float *out, float *num,
