@@ -7,6 +7,10 @@ resident in HBM: term modulation + summed-area tables (kernel 0) and tap
 lookup, accumulation and normalisation (kernel 1).  The plan (FP64 host fit)
 is built once per parameter set, timed separately and reported as plan_ms.
 
+cfg6_1080p_u8_box: the paper's own 8-bit regime (range series on [-T_r,
+T_r] with the range box, BF_FLAG_RANGE_BOX): one kernel per image; its
+roofline counts the integer adds of the level-slab tables it builds.
+
 cfg4_served: one pass of the 512-request served stream through the
 library's request loop (open loop, Poisson arrivals); value is pixels served
 per second over the makespan, with p50/p99 latency, and beside it the same
@@ -30,6 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpix/s at fixed max-abs err vs FP64 oracle; served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
+INT32_PEAK_TOPS = 39.3     # 256 CUs x 64 lanes x 2.4 GHz, one 32-bit add per lane per clock
 
 
 def log(*a):
@@ -205,12 +210,14 @@ def oracle_one_core(workload, n):
     from synth.images import CONFIGS
     c = CONFIGS[workload]
     I_host = synth.config_image(workload)
-    op = oracle.make_plan(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"])
+    box = c.get("range_box", False)
+    op = oracle.make_plan(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"],
+                          **({"span": 0.0} if box else {}))
     rng = np.random.default_rng(13)
     ys = rng.integers(0, c["H"], n).astype(np.int32)
     xs = rng.integers(0, c["W"], n).astype(np.int32)
     t0 = time.perf_counter()
-    oracle.expanded_brute(I_host, op, ys, xs)
+    (oracle.expanded_rangebox if box else oracle.expanded_brute)(I_host, op, ys, xs)
     dt = time.perf_counter() - t0
     print(json.dumps({"mpix_s": n / dt / 1e6, "seconds": dt, "pixels": n}))
 
@@ -228,6 +235,117 @@ def one_core_baseline(workload, n):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def slab_table_adds(Z, plan_info, tile=32):
+    """Algorithmic integer adds of the range-box kernel on image Z: for every
+    32 x 32 output tile, two slab tables (numerator, denominator) per distinct
+    output level, each (region rows + 1) x (region columns + 1) entries built
+    with two adds (row and column recurrences of Eq. sum_sat_recurrence_2D)."""
+    H, W = Z.shape
+    dy_lo, dy_hi = plan_info["tap_dy_min"], plan_info["tap_dy_max"]
+    dx_lo, dx_hi = plan_info["tap_dx_min"], plan_info["tap_dx_max"]
+    adds = 0
+    for ty in range(0, H, tile):
+        rs = min(max(ty + tile - 1 + dy_hi, 0), H) - min(max(ty + dy_lo, 0), H)
+        for tx in range(0, W, tile):
+            rc = min(max(tx + tile - 1 + dx_hi, 0), W) - min(max(tx + dx_lo, 0), W)
+            levels = len(np.unique(Z[ty:ty + tile, tx:tx + tile]))
+            adds += levels * 2 * 2 * (rs + 1) * (rc + 1)
+    return adds
+
+
+def range_box(args):
+    import torch
+    import synth
+    from synth.images import CONFIGS
+    from paper_1803_00004_amd import bf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = args.workload
+    c = CONFIGS[w]
+    H, W = c["H"], c["W"]
+    Z = synth.config_image(w)
+    one_core = None
+    if not args.no_cpu:
+        log("[bench] oracle T4 on 16384 sampled pixels, one core (child process)")
+        one_core = one_core_baseline(w, 16384)
+    t0 = time.perf_counter()
+    plan = bf.Plan(c["sigma_s"], c["sigma_r"], c["radius"], c["n_range"], c["n_spatial"], dtype="u8",
+                   range_box=True)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info
+    log("[bench] plan %.1f ms: %s" % (plan_ms, info.as_dict()))
+    dy, dx, _ = plan.taps()
+    taps = {"tap_dy_min": int(dy.min()), "tap_dy_max": int(dy.max()), "tap_dx_min": int(dx.min()),
+            "tap_dx_max": int(dx.max())}
+    dev = torch.device("cuda:0")
+    I = torch.from_numpy(Z).to(dev)
+    out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        bf.filter(plan, I, out=out, stream=stream)
+    torch.cuda.synchronize()
+    bf.profile_enable(True)
+    bf.profile_read()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(args.steps):
+        bf.filter(plan, I, out=out, stream=stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = start.elapsed_time(end) / args.steps
+    kms, kl = bf.profile_read()
+    bf.profile_enable(False)
+    k_ms = kms[1] / max(1, kl[1])
+    mpix = H * W / (ms_per_step * 1e-3) / 1e6
+    adds = slab_table_adds(Z, taps)
+    tops = adds / (k_ms * 1e-3) / 1e12
+    log("[bench] %.4f ms/step  %.1f Mpix/s  kz_rangebox %.4f ms, %.3g table adds (%.2f TOP/s)"
+        % (ms_per_step, mpix, k_ms, adds, tops))
+    result = {
+        "metric": METRIC, "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i32+f64", "data": "synthetic (seeded gradient noise + step edges + Gaussian noise)",
+        "config": {"workload": "%s: %dx%d u8, Gaussian sigma_s=%g r=%d, sigma_r=%g, N_r=%d, N_s=%d, "
+                               "T = T_r with the range box (level window +-%d)"
+                               % (w, W, H, c["sigma_s"], c["radius"], c["sigma_r"], c["n_range"],
+                                  c["n_spatial"], info.box_levels),
+                   "H": H, "W": W, "box_levels": info.box_levels, "sat_shift": info.sat_shift},
+        "plan_ms": round(plan_ms, 2),
+        "kernel_ms": {"kz_rangebox": round(k_ms, 5)},
+        "roofline": {"bound": "alu", "achieved": tops, "peak": INT32_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": tops / INT32_PEAK_TOPS, "traffic": None, "kernel": "kz_rangebox",
+                     "kernel_ms": k_ms, "algorithmic_adds": adds},
+    }
+    if not args.no_cpu:
+        import oracle
+        op = oracle.make_plan(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"], span=0.0)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        n = 262144  # about 2 s of 16 host cores
+        rng = np.random.default_rng(11)
+        ys, xs = rng.integers(0, H, n).astype(np.int32), rng.integers(0, W, n).astype(np.int32)
+        log("[bench] oracle T4 on %d sampled pixels (%d threads)" % (n, threads))
+        t0 = time.perf_counter()
+        ref = oracle.expanded_rangebox(Z, op, ys, xs)
+        cpu_s = time.perf_counter() - t0
+        out_host = out.cpu().numpy().astype(np.float64)
+        err = float(np.abs(out_host[ys, xs] - ref).max())
+        t1 = oracle.true_bf(Z, c["sigma_s"], c["radius"], c["sigma_r"], ys[:4096], xs[:4096])
+        result["max_abs_err_vs_oracle"] = err
+        result["max_abs_err_vs_true_bf_4096px"] = float(np.abs(out_host[ys[:4096], xs[:4096]] - t1).max())
+        result["cpu_baseline"] = {"value": round(n / cpu_s / 1e6, 4), "unit": "Mpix/s", "cores": threads,
+                                  "kind": "oracle", "seconds": round(cpu_s, 2),
+                                  "sample": "%d random pixels of the %dx%d image, oracle T4 (FP64 direct sum "
+                                            "with the range box)" % (n, W, H)}
+        if one_core:
+            result["cpu_baseline"]["one_core"] = {
+                "value": round(one_core["mpix_s"], 5), "unit": "Mpix/s", "cores": 1,
+                "sample": "%d random pixels, oracle T4" % one_core["pixels"],
+                "seconds": round(one_core["seconds"], 2)}
+        log("[bench] max-abs err vs oracle T4 %.3e" % err)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     if len(sys.argv) == 4 and sys.argv[1] == "--oracle-one-core":
         return oracle_one_core(sys.argv[2], int(sys.argv[3]))
@@ -236,7 +354,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg2_1080p",
-                    choices=["cfg1_256", "cfg2_1080p", "cfg3_4096", "cfg4_served", "cfg5_4096_u8"])
+                    choices=["cfg1_256", "cfg2_1080p", "cfg3_4096", "cfg4_served", "cfg5_4096_u8",
+                             "cfg6_1080p_u8_box"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (no error check)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (heuristic tiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -250,6 +369,8 @@ def main():
 
     if args.workload == "cfg4_served":
         return served(args)
+    if args.workload == "cfg6_1080p_u8_box":
+        return range_box(args)
 
     import torch
     import synth

@@ -84,7 +84,7 @@ def gen_image_u8(H, W, edges, noise_sd, seed):
     return np.rint(gen_image(H, W, edges, noise_sd, seed).astype(np.float64) * 255.0).astype(np.uint8)
 
 
-# The five workloads: image recipe and filter parameters.
+# The workloads: image recipe and filter parameters.
 CONFIGS = {
     "cfg1_256": dict(H=256, W=256, edges=6, noise=0.02, seed=1, sigma_s=3.0, radius=9,
                      sigma_r=0.1, n_range=8, n_spatial=4, dtype="f32"),
@@ -94,6 +94,9 @@ CONFIGS = {
                       sigma_r=0.05, n_range=32, n_spatial=8, dtype="f32"),
     "cfg5_4096_u8": dict(H=4096, W=4096, edges=150, noise=0.03, seed=3, sigma_s=16.0, radius=48,
                          sigma_r=0.05, n_range=32, n_spatial=8, dtype="u8"),
+    # the paper's own 8-bit regime: series on [-T_r, T_r] with the range box, five terms
+    "cfg6_1080p_u8_box": dict(H=1080, W=1920, edges=40, noise=0.03, seed=2, sigma_s=8.0, radius=24,
+                              sigma_r=0.1, n_range=5, n_spatial=6, dtype="u8", range_box=True),
 }
 
 
