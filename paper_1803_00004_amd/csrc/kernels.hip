@@ -703,15 +703,17 @@ bf_status_t launch_direct(const DevTables &host, const void *I, float *out, floa
 // wrapping adds of round(v 2^q)) and the pixels of level L read their
 // quadruplet boxes.  No workspace.
 // ---------------------------------------------------------------------------
-constexpr int kZTile = 32;
-constexpr int kZThreads = 512;
-constexpr int kZWaves = kZThreads / 64;
-constexpr int kZSeg = 16;  // region rows per wave (region <= 128 rows: radius <= 48)
+// Output tiles of 64 x 64 (1024 threads) where their region fits in LDS, else
+// 32 x 32 (512 threads); the region is at most 128 x 128 levels either way.
+constexpr int kZMaxRegion = 128;
 
+template <int kZTile, int kZThreads>
 __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restrict__ I, int H, int W,
                                                          const DevTables *__restrict__ tab,
                                                          float *__restrict__ out, float *__restrict__ num_out,
                                                          float *__restrict__ den_out) {
+  constexpr int kZWaves = kZThreads / 64;
+  constexpr int kZSeg = kZMaxRegion / kZWaves;      // region rows per wave
   constexpr int PPT = kZTile * kZTile / kZThreads;  // pixels per thread
   extern __shared__ int4 kz_lds4[];
   int2 *lut = reinterpret_cast<int2 *>(kz_lds4);                     // [256]: (num, den) slab values
@@ -731,7 +733,7 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   int *start = reinterpret_cast<int *>(lv);       // [257]: first list slot of each output level
   int *cursor = start + 257;                       // [256]
   int *segoff = cursor + 256;                      // [129]: carry row of table row Y
-  uint16_t *list = reinterpret_cast<uint16_t *>(segoff + 129);  // [1024]: tile pixels by level
+  uint16_t *list = reinterpret_cast<uint16_t *>(segoff + 129);  // [kZTile^2]: tile pixels by level
   const int zr = tab->box_zr;
   const double scale = tab->box_scale;
   // wave w builds the region rows [w seg, (w + 1) seg) with sums restarting at
@@ -874,27 +876,42 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   }
 }
 
-size_t rangebox_lds_bytes(const DevTables &host) {
-  const int RS = kZTile - 1 + host.tap_dy_max - host.tap_dy_min;  // largest region
-  const int RC = kZTile - 1 + host.tap_dx_max - host.tap_dx_min;
-  if (RS > kZWaves * kZSeg || RC > 128) return (size_t)-1;
+template <int TE, int NT>
+static size_t rangebox_lds(const DevTables &host) {
+  const int RS = TE - 1 + host.tap_dy_max - host.tap_dy_min;  // largest region
+  const int RC = TE - 1 + host.tap_dx_max - host.tap_dx_min;
+  if (RS > kZMaxRegion || RC > kZMaxRegion) return (size_t)-1;
   const int P = RC + 2;
-  const size_t lists = (257 + 256 + 129) * 4 + 1024 * 2;  // share the bytes of the staged levels
-  return 256 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)kZWaves * (RC + 1) * 8 + std::max((size_t)RS * RC, lists);
+  const size_t lists = (257 + 256 + 129) * 4 + TE * TE * 2;  // share the bytes of the staged levels
+  return 256 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)(NT / 64) * (RC + 1) * 8 + std::max((size_t)RS * RC, lists);
+}
+
+constexpr size_t kLdsLimit = 160 * 1024;
+
+size_t rangebox_lds_bytes(const DevTables &host) {
+  const size_t a = rangebox_lds<64, 1024>(host);
+  return a <= kLdsLimit ? a : rangebox_lds<32, 512>(host);
 }
 
 bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const void *I, float *out, float *num,
                             float *den, int H, int W, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t lds = rangebox_lds_bytes(host);
-  if (lds > 160 * 1024) return BF_ERR_UNSUPPORTED;
-  const int blocks = ((W + kZTile - 1) / kZTile) * ((H + kZTile - 1) / kZTile);
+  const size_t l64 = rangebox_lds<64, 1024>(host), l32 = rangebox_lds<32, 512>(host);
+  const bool big = l64 <= kLdsLimit;
+  const size_t lds = big ? l64 : l32;
+  if (lds > kLdsLimit) return BF_ERR_UNSUPPORTED;
+  const int te = big ? 64 : 32;
+  const int blocks = ((W + te - 1) / te) * ((H + te - 1) / te);
+  const void *fn = big ? (const void *)kz_rangebox<64, 1024> : (const void *)kz_rangebox<32, 512>;
   profile_mark(1, 1, stream);
-  if (hipFuncSetAttribute((const void *)kz_rangebox, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-      hipSuccess)
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return BF_ERR_DEVICE;
-  hipLaunchKernelGGL(kz_rangebox, dim3(blocks), dim3(kZThreads), lds, s, static_cast<const uint8_t *>(I), H, W,
-                     dev, out, num, den);
+  if (big)
+    hipLaunchKernelGGL((kz_rangebox<64, 1024>), dim3(blocks), dim3(1024), lds, s, static_cast<const uint8_t *>(I),
+                       H, W, dev, out, num, den);
+  else
+    hipLaunchKernelGGL((kz_rangebox<32, 512>), dim3(blocks), dim3(512), lds, s, static_cast<const uint8_t *>(I),
+                       H, W, dev, out, num, den);
   const hipError_t e = hipGetLastError();
   profile_mark(1, 0, stream);
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;

@@ -499,7 +499,8 @@ def test_direct_plans_in_batches(torch_dev):
     (197, 263, 3.0, 9, 6, 0.05, 8),
     (130, 129, 8.0, 24, 6, 0.1, 5),
     (70, 90, 16.0, 48, 8, 0.2, 3),
-    (64, 64, 16.0, 48, 4, 0.1, 5),     # largest radius of the regime
+    (150, 170, 10.0, 30, 6, 0.1, 5),   # largest radius of the 64 x 64 output tiles
+    (64, 64, 16.0, 48, 4, 0.1, 5),     # largest radius of the regime (32 x 32 output tiles)
     (77, 61, 2.0, 6, 4, 0.1, 24),      # many range terms: same cost
     (5, 40, 2.0, 6, 4, 0.1, 5),        # image shorter than the window
     (1, 1, 2.0, 6, 4, 0.1, 5),
