@@ -706,6 +706,7 @@ bf_status_t launch_direct(const DevTables &host, const void *I, float *out, floa
 // Output tiles of 64 x 64 (1024 threads) where their region fits in LDS, else
 // 32 x 32 (512 threads); the region is at most 128 x 128 levels either way.
 constexpr int kZMaxRegion = 128;
+constexpr int kZPitch = kZMaxRegion + 2;
 
 template <int kZTile, int kZThreads>
 __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restrict__ I, int H, int W,
@@ -716,8 +717,10 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   constexpr int kZSeg = kZMaxRegion / kZWaves;      // region rows per wave
   constexpr int PPT = kZTile * kZTile / kZThreads;  // pixels per thread
   extern __shared__ int4 kz_lds4[];
-  int2 *lut = reinterpret_cast<int2 *>(kz_lds4);                     // [256]: (num, den) slab values
-  uint32_t *mask = reinterpret_cast<uint32_t *>(lut + 256);          // 256 bits of output levels
+  // [264]: (num, den) slab values of the current level by source level; zero
+  // outside the level window and at 256 (sources outside the region)
+  int2 *lut = reinterpret_cast<int2 *>(kz_lds4);
+  uint32_t *mask = reinterpret_cast<uint32_t *>(lut + 264);          // 256 bits of output levels
   int2 *sat = reinterpret_cast<int2 *>(mask + 8);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -726,7 +729,7 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   const int cy0 = min(max(ty0 + tab->tap_dy_min, 0), H), cy1 = min(max(ty0 + kZTile - 1 + tab->tap_dy_max, 0), H);
   const int cx0 = min(max(tx0 + tab->tap_dx_min, 0), W), cx1 = min(max(tx0 + kZTile - 1 + tab->tap_dx_max, 0), W);
   const int RS = cy1 - cy0, RC = cx1 - cx0;  // source rows / columns of the region (<= 128 each)
-  const int P = RC + 2;                      // table pitch in int2
+  const int P = kZPitch;                     // table pitch in int2: every lane's two columns fit
   int2 *carry = sat + (RS + 1) * P;          // [kZWaves][RC + 1]: table totals of the segments above
   // the region's levels while they are staged; afterwards the pixel lists
   uint8_t *lv = reinterpret_cast<uint8_t *>(carry + kZWaves * (RC + 1));
@@ -734,7 +737,6 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   int *cursor = start + 257;                       // [256]
   int *segoff = cursor + 256;                      // [129]: carry row of table row Y
   uint16_t *list = reinterpret_cast<uint16_t *>(segoff + 129);  // [kZTile^2]: tile pixels by level
-  const int zr = tab->box_zr;
   const double scale = tab->box_scale;
   // wave w builds the region rows [w seg, (w + 1) seg) with sums restarting at
   // its first row; lane l holds the columns 2l, 2l + 1
@@ -749,14 +751,15 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   for (int y = tid; y <= RS; y += kZThreads) sat[y * P] = make_int2(0, 0);
   if (tid < 8) mask[tid] = 0;
   __syncthreads();
-  // the wave's levels in registers, two columns per lane (512: outside the region)
+  // the wave's levels in registers as byte offsets into the slab values, two
+  // columns per lane (level 256: outside the region)
   uint32_t zq[kZSeg];
 #pragma unroll
   for (int i = 0; i < kZSeg; ++i) {
     const int y = ry0 + i, x = 2 * lane;
-    const uint32_t a = (i < nrows && x < RC) ? lv[y * RC + x] : 512u;
-    const uint32_t b = (i < nrows && x + 1 < RC) ? lv[y * RC + x + 1] : 512u;
-    zq[i] = a | (b << 16);
+    const uint32_t a = (i < nrows && x < RC) ? lv[y * RC + x] : 256u;
+    const uint32_t b = (i < nrows && x + 1 < RC) ? lv[y * RC + x + 1] : 256u;
+    zq[i] = (a * 8u) | ((b * 8u) << 16);
   }
   __syncthreads();  // lv is dead: its bytes now hold the level lists
   for (int i = tid; i < 257 + 256; i += kZThreads) start[i] = 0;  // start and cursor
@@ -804,8 +807,10 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
       bits &= bits - 1;
       if (tid < 256) {  // slab values of level L at source level z = tid
         const int z = tid;
-        const double w = tab->box_w[L - z + 255];
+        const double w = tab->box_w[L - z + 255];  // zero outside the window
         lut[z] = make_int2(__double2int_rn(w * (z * (1.0 / 255.0)) * scale), __double2int_rn(w * scale));
+      } else if (tid == 256) {
+        lut[256] = make_int2(0, 0);
       }
       __syncthreads();
       // column sums down the wave's rows in registers, a row scan across the
@@ -814,20 +819,18 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
 #pragma unroll
       for (int i = 0; i < kZSeg; ++i) {
         if (i >= nrows) break;
-        const int za = (int)(zq[i] & 0xffffu), zb = (int)(zq[i] >> 16);
-        int2 va = make_int2(0, 0), vb = make_int2(0, 0);
-        if (abs(za - L) <= zr) va = lut[za];
-        if (abs(zb - L) <= zr) vb = lut[zb];
+        const char *lb = reinterpret_cast<const char *>(lut);
+        const int2 va = *reinterpret_cast<const int2 *>(lb + (zq[i] & 0xffffu));
+        const int2 vb = *reinterpret_cast<const int2 *>(lb + (zq[i] >> 16));
         c0n += (uint32_t)va.x;
         c0d += (uint32_t)va.y;
         c1n += (uint32_t)vb.x;
         c1d += (uint32_t)vb.y;
         const uint32_t tn = c0n + c1n, td = c0d + c1d;
         const uint32_t en = wave_inclusive_scan(tn) - tn, ed = wave_inclusive_scan(td) - td;
-        const int x = 2 * lane;
-        int2 *row = sat + (ry0 + i + 1) * P + x + 1;
-        if (x < RC) row[0] = make_int2((int)(en + c0n), (int)(ed + c0d));
-        if (x + 1 < RC) row[1] = make_int2((int)(en + tn), (int)(ed + td));
+        int2 *row = sat + (ry0 + i + 1) * P + 2 * lane + 1;  // columns past the region: padding
+        row[0] = make_int2((int)(en + c0n), (int)(ed + c0d));
+        row[1] = make_int2((int)(en + tn), (int)(ed + td));
       }
       __syncthreads();
       // carries: totals of the segments above, per table column
@@ -881,9 +884,9 @@ static size_t rangebox_lds(const DevTables &host) {
   const int RS = TE - 1 + host.tap_dy_max - host.tap_dy_min;  // largest region
   const int RC = TE - 1 + host.tap_dx_max - host.tap_dx_min;
   if (RS > kZMaxRegion || RC > kZMaxRegion) return (size_t)-1;
-  const int P = RC + 2;
+  const int P = kZPitch;
   const size_t lists = (257 + 256 + 129) * 4 + TE * TE * 2;  // share the bytes of the staged levels
-  return 256 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)(NT / 64) * (RC + 1) * 8 + std::max((size_t)RS * RC, lists);
+  return 264 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)(NT / 64) * (RC + 1) * 8 + std::max((size_t)RS * RC, lists);
 }
 
 constexpr size_t kLdsLimit = 160 * 1024;
