@@ -708,19 +708,33 @@ bf_status_t launch_direct(const DevTables &host, const void *I, float *out, floa
 constexpr int kZMaxRegion = 128;
 constexpr int kZPitch = kZMaxRegion + 2;
 
+// Inclusive prefix sum within each 16-lane row of a wave (the first steps of
+// wave_inclusive_scan).
+__device__ __forceinline__ uint32_t row16_inclusive_scan(uint32_t v) {
+  uint32_t x = v;
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);   // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);   // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x113, 0xf, 0xf, true);   // row_shr:3
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xe, false);  // row_shr:4, lanes 4..15 of a row
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xc, false);  // row_shr:8, lanes 8..15 of a row
+  return x;
+}
+
 template <int kZTile, int kZThreads>
 __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restrict__ I, int H, int W,
                                                          const DevTables *__restrict__ tab,
                                                          float *__restrict__ out, float *__restrict__ num_out,
                                                          float *__restrict__ den_out) {
   constexpr int kZWaves = kZThreads / 64;
+  static_assert(kZWaves <= 16, "segment carries are scanned in 16-lane rows");
   constexpr int kZSeg = kZMaxRegion / kZWaves;      // region rows per wave
   constexpr int PPT = kZTile * kZTile / kZThreads;  // pixels per thread
   extern __shared__ int4 kz_lds4[];
-  // [264]: (num, den) slab values of the current level by source level; zero
-  // outside the level window and at 256 (sources outside the region)
-  int2 *lut = reinterpret_cast<int2 *>(kz_lds4);
-  uint32_t *mask = reinterpret_cast<uint32_t *>(lut + 264);          // 256 bits of output levels
+  // two buffers of [264] (num, den) slab values by source level (the current
+  // level's and the next one's); zero outside the level window and at 256
+  // (sources outside the region)
+  int2 *luts = reinterpret_cast<int2 *>(kz_lds4);
+  uint32_t *mask = reinterpret_cast<uint32_t *>(luts + 2 * 264);    // 256 bits of output levels
   int2 *sat = reinterpret_cast<int2 *>(mask + 8);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -731,12 +745,12 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   const int RS = cy1 - cy0, RC = cx1 - cx0;  // source rows / columns of the region (<= 128 each)
   const int P = kZPitch;                     // table pitch in int2: every lane's two columns fit
   int2 *carry = sat + (RS + 1) * P;          // [kZWaves][RC + 1]: table totals of the segments above
-  // the region's levels while they are staged; afterwards the pixel lists
-  uint8_t *lv = reinterpret_cast<uint8_t *>(carry + kZWaves * (RC + 1));
-  int *start = reinterpret_cast<int *>(lv);       // [257]: first list slot of each output level
-  int *cursor = start + 257;                       // [256]
-  int *segoff = cursor + 256;                      // [129]: carry row of table row Y
-  uint16_t *list = reinterpret_cast<uint16_t *>(segoff + 129);  // [kZTile^2]: tile pixels by level
+  int *start = reinterpret_cast<int *>(carry + kZWaves * (RC + 1));  // [257]: first list slot per level
+  int *cursor = start + 257;                                          // [256]
+  int *segoff = cursor + 256;                                         // [129]: carry row of table row Y
+  int *levels = segoff + 129;                                         // [256]: the output levels present
+  uint16_t *list = reinterpret_cast<uint16_t *>(levels + 256);        // [kZTile^2]: tile pixels by level
+  uint8_t *lv = reinterpret_cast<uint8_t *>(sat);  // the region's levels, staged before the tables exist
   const double scale = tab->box_scale;
   // wave w builds the region rows [w seg, (w + 1) seg) with sums restarting at
   // its first row; lane l holds the columns 2l, 2l + 1
@@ -747,8 +761,8 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
     const int y = i / RC, x = i - y * RC;
     lv[i] = I[(long long)(cy0 + y) * W + cx0 + x];
   }
-  for (int x = tid; x < P; x += kZThreads) sat[x] = make_int2(0, 0);  // table row 0 and column 0 stay zero
-  for (int y = tid; y <= RS; y += kZThreads) sat[y * P] = make_int2(0, 0);
+  for (int i = tid; i < 257 + 256; i += kZThreads) start[i] = 0;  // start and cursor
+  for (int Y = tid; Y <= RS; Y += kZThreads) segoff[Y] = Y == 0 ? 0 : ((Y - 1) / seg) * (RC + 1);
   if (tid < 8) mask[tid] = 0;
   __syncthreads();
   // the wave's levels in registers as byte offsets into the slab values, two
@@ -761,10 +775,6 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
     const uint32_t b = (i < nrows && x + 1 < RC) ? lv[y * RC + x + 1] : 256u;
     zq[i] = (a * 8u) | ((b * 8u) << 16);
   }
-  __syncthreads();  // lv is dead: its bytes now hold the level lists
-  for (int i = tid; i < 257 + 256; i += kZThreads) start[i] = 0;  // start and cursor
-  for (int Y = tid; Y <= RS; Y += kZThreads) segoff[Y] = Y == 0 ? 0 : ((Y - 1) / seg) * (RC + 1);
-  __syncthreads();
   int zp[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
@@ -776,20 +786,25 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
       atomicAdd(&cursor[zp[i]], 1);
     }
   }
-  __syncthreads();
-  if (wave == 0) {  // exclusive prefix of the level counts: four levels per lane
-    int c[4], t = 0;
+  __syncthreads();  // the staged levels are in registers: the table rows may be cleared
+  for (int x = tid; x < P; x += kZThreads) sat[x] = make_int2(0, 0);  // table row 0 and column 0 stay zero
+  for (int y = tid; y <= RS; y += kZThreads) sat[y * P] = make_int2(0, 0);
+  if (wave == 0) {  // exclusive prefix of the level counts and the list of levels: four per lane
+    int c[4], t = 0, np = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       c[k] = cursor[4 * lane + k];
       t += c[k];
+      np += c[k] > 0;
     }
     int e = (int)wave_inclusive_scan((uint32_t)t) - t;
+    int el = (int)wave_inclusive_scan((uint32_t)np) - np;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       start[4 * lane + k] = e;
       cursor[4 * lane + k] = e;
       e += c[k];
+      if (c[k] > 0) levels[el++] = 4 * lane + k;
     }
     if (lane == 63) start[256] = e;
   }
@@ -797,29 +812,35 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
 #pragma unroll
   for (int i = 0; i < PPT; ++i)
     if (zp[i] >= 0) list[atomicAdd(&cursor[zp[i]], 1)] = (uint16_t)(tid + kZThreads * i);
+  int nlev = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) nlev += __builtin_popcount(mask[k]);
+  nlev = __builtin_amdgcn_readfirstlane(nlev);
 
+  // slab values of level L into buffer b, by the threads 0 .. 256
+  auto fill_lut = [&](int L, int b) {
+    int2 *lut = luts + 264 * b;
+    if (tid < 256) {
+      const int z = tid;
+      const double w = tab->box_w[L - z + 255];  // zero outside the window
+      lut[z] = make_int2(__double2int_rn(w * (z * (1.0 / 255.0)) * scale), __double2int_rn(w * scale));
+    } else if (tid == 256) {
+      lut[256] = make_int2(0, 0);
+    }
+  };
+  fill_lut(__builtin_amdgcn_readfirstlane(levels[0]), 0);
   const int nq = tab->n_quads;
-  for (int wd = 0; wd < 8; ++wd) {
-    __syncthreads();  // the mask and the lists are complete
-    uint32_t bits = (uint32_t)__builtin_amdgcn_readfirstlane((int)mask[wd]);
-    while (bits) {
-      const int L = wd * 32 + __builtin_ctz(bits);
-      bits &= bits - 1;
-      if (tid < 256) {  // slab values of level L at source level z = tid
-        const int z = tid;
-        const double w = tab->box_w[L - z + 255];  // zero outside the window
-        lut[z] = make_int2(__double2int_rn(w * (z * (1.0 / 255.0)) * scale), __double2int_rn(w * scale));
-      } else if (tid == 256) {
-        lut[256] = make_int2(0, 0);
-      }
-      __syncthreads();
-      // column sums down the wave's rows in registers, a row scan across the
-      // lanes per row: the table of the segment, restarted at its first row
+  for (int li = 0; li < nlev; ++li) {
+    __syncthreads();  // the lists, the level's slab values and the cleared tables are ready
+    const int L = __builtin_amdgcn_readfirstlane(levels[li]);
+    // column sums down the wave's rows in registers, a row scan across the
+    // lanes per row: the table of the segment, restarted at its first row
+    {
+      const char *lb = reinterpret_cast<const char *>(luts + 264 * (li & 1));
       uint32_t c0n = 0, c0d = 0, c1n = 0, c1d = 0;
 #pragma unroll
       for (int i = 0; i < kZSeg; ++i) {
         if (i >= nrows) break;
-        const char *lb = reinterpret_cast<const char *>(lut);
         const int2 va = *reinterpret_cast<const int2 *>(lb + (zq[i] & 0xffffu));
         const int2 vb = *reinterpret_cast<const int2 *>(lb + (zq[i] >> 16));
         c0n += (uint32_t)va.x;
@@ -832,49 +853,47 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
         row[0] = make_int2((int)(en + c0n), (int)(ed + c0d));
         row[1] = make_int2((int)(en + tn), (int)(ed + td));
       }
-      __syncthreads();
-      // carries: totals of the segments above, per table column
-      for (int X = tid; X <= RC; X += kZThreads) {
-        uint32_t rn = 0, rd = 0;
-        for (int w = 0; w < kZWaves; ++w) {
-          carry[w * (RC + 1) + X] = make_int2((int)rn, (int)rd);
-          const int last = min((w + 1) * seg, RS);  // table row of the segment's last region row
-          if (w * seg < RS) {
-            const int2 v = sat[last * P + X];
-            rn += (uint32_t)v.x;
-            rd += (uint32_t)v.y;
-          }
-        }
+    }
+    __syncthreads();
+    // carries: exclusive sums over the segments above, one 16-lane row per
+    // table column (lane w of the row: segment w); the next level's slab
+    // values go to the other buffer meanwhile
+    for (int t0 = wave * 64; t0 < 16 * (RC + 1); t0 += kZThreads) {
+      const int X = (t0 + lane) >> 4, w = lane & 15;
+      const bool ok = X <= RC && w < kZWaves;
+      int2 v = make_int2(0, 0);
+      if (ok && w * seg < RS) v = sat[min((w + 1) * seg, RS) * P + X];
+      const uint32_t in_ = row16_inclusive_scan((uint32_t)v.x), id = row16_inclusive_scan((uint32_t)v.y);
+      if (ok) carry[w * (RC + 1) + X] = make_int2((int)(in_ - (uint32_t)v.x), (int)(id - (uint32_t)v.y));
+    }
+    if (li + 1 < nlev) fill_lut(__builtin_amdgcn_readfirstlane(levels[li + 1]), (li + 1) & 1);
+    __syncthreads();
+    auto corner = [&](int Y, int X) -> int2 {  // table entry (Y, X) of level L's slabs (row 0: zero)
+      const int2 v = sat[Y * P + X], c = carry[segoff[Y] + X];
+      return make_int2((int)((uint32_t)v.x + (uint32_t)c.x), (int)((uint32_t)v.y + (uint32_t)c.y));
+    };
+    // the pixels of level L, one per thread
+    const int s0 = start[L], cnt = start[L + 1] - s0;
+    for (int j = tid; j < cnt; j += kZThreads) {
+      const int pi = list[s0 + j];
+      const int py = ty0 + pi / kZTile, px = tx0 + pi % kZTile;
+      double num = 0.0, den = 0.0;
+      for (int q = 0; q < nq; ++q) {
+        const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
+        const int Ya = min(max(py + dy, 0), H) - cy0, Yb = min(max(py + 1 - dy, 0), H) - cy0;
+        const int Xa = min(max(px + dx, 0), W) - cx0, Xb = min(max(px + 1 - dx, 0), W) - cx0;
+        const int2 a = corner(Ya, Xa), b = corner(Yb, Xa), c = corner(Ya, Xb), d = corner(Yb, Xb);
+        const double w = tab->quad_w[q];
+        num = __builtin_fma(w, (double)box_of(a.x, b.x, c.x, d.x), num);
+        den = __builtin_fma(w, (double)box_of(a.y, b.y, c.y, d.y), den);
       }
-      __syncthreads();
-      auto corner = [&](int Y, int X) -> int2 {  // table entry (Y, X) of level L's slabs (row 0: zero)
-        const int2 v = sat[Y * P + X], c = carry[segoff[Y] + X];
-        return make_int2((int)((uint32_t)v.x + (uint32_t)c.x), (int)((uint32_t)v.y + (uint32_t)c.y));
-      };
-      // the pixels of level L, one per thread
-      const int s0 = start[L], cnt = start[L + 1] - s0;
-      for (int j = tid; j < cnt; j += kZThreads) {
-        const int pi = list[s0 + j];
-        const int py = ty0 + pi / kZTile, px = tx0 + pi % kZTile;
-        double num = 0.0, den = 0.0;
-        for (int q = 0; q < nq; ++q) {
-          const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
-          const int Ya = min(max(py + dy, 0), H) - cy0, Yb = min(max(py + 1 - dy, 0), H) - cy0;
-          const int Xa = min(max(px + dx, 0), W) - cx0, Xb = min(max(px + 1 - dx, 0), W) - cx0;
-          const int2 a = corner(Ya, Xa), b = corner(Yb, Xa), c = corner(Ya, Xb), d = corner(Yb, Xb);
-          const double w = tab->quad_w[q];
-          num = __builtin_fma(w, (double)box_of(a.x, b.x, c.x, d.x), num);
-          den = __builtin_fma(w, (double)box_of(a.y, b.y, c.y, d.y), den);
-        }
-        const double inv = 1.0 / scale;
-        num *= inv;
-        den *= inv;
-        const long long idx = (long long)py * W + px;
-        out[idx] = den > tab->den_floor ? (float)(num / den) : (float)L * (1.0f / 255.0f);
-        if (num_out) num_out[idx] = (float)num;
-        if (den_out) den_out[idx] = (float)den;
-      }
-      __syncthreads();  // before the next level overwrites the tables
+      const double inv = 1.0 / scale;
+      num *= inv;
+      den *= inv;
+      const long long idx = (long long)py * W + px;
+      out[idx] = den > tab->den_floor ? (float)(num / den) : (float)L * (1.0f / 255.0f);
+      if (num_out) num_out[idx] = (float)num;
+      if (den_out) den_out[idx] = (float)den;
     }
   }
 }
@@ -885,8 +904,9 @@ static size_t rangebox_lds(const DevTables &host) {
   const int RC = TE - 1 + host.tap_dx_max - host.tap_dx_min;
   if (RS > kZMaxRegion || RC > kZMaxRegion) return (size_t)-1;
   const int P = kZPitch;
-  const size_t lists = (257 + 256 + 129) * 4 + TE * TE * 2;  // share the bytes of the staged levels
-  return 264 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)(NT / 64) * (RC + 1) * 8 + std::max((size_t)RS * RC, lists);
+  const size_t lists = (257 + 256 + 129 + 256) * 4 + TE * TE * 2;
+  // the staged levels (RS x RC bytes) share the bytes of the tables
+  return 2 * 264 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)(NT / 64) * (RC + 1) * 8 + lists;
 }
 
 constexpr size_t kLdsLimit = 160 * 1024;
