@@ -235,9 +235,9 @@ def one_core_baseline(workload, n):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def slab_table_adds(Z, plan_info, tile=32):
+def slab_table_adds(Z, plan_info, tile):
     """Algorithmic integer adds of the range-box kernel on image Z: for every
-    32 x 32 output tile, two slab tables (numerator, denominator) per distinct
+    tile x tile output tile, two slab tables (numerator, denominator) per distinct
     output level, each (region rows + 1) x (region columns + 1) entries built
     with two adds (row and column recurrences of Eq. sum_sat_recurrence_2D)."""
     H, W = Z.shape
@@ -297,7 +297,7 @@ def range_box(args):
     bf.profile_enable(False)
     k_ms = kms[1] / max(1, kl[1])
     mpix = H * W / (ms_per_step * 1e-3) / 1e6
-    adds = slab_table_adds(Z, taps)
+    adds = slab_table_adds(Z, taps, info.box_tile)
     tops = adds / (k_ms * 1e-3) / 1e12
     log("[bench] %.4f ms/step  %.1f Mpix/s  kz_rangebox %.4f ms, %.3g table adds (%.2f TOP/s)"
         % (ms_per_step, mpix, k_ms, adds, tops))
@@ -310,7 +310,8 @@ def range_box(args):
                                "T = T_r with the range box (level window +-%d)"
                                % (w, W, H, c["sigma_s"], c["radius"], c["sigma_r"], c["n_range"],
                                   c["n_spatial"], info.box_levels),
-                   "H": H, "W": W, "box_levels": info.box_levels, "sat_shift": info.sat_shift},
+                   "H": H, "W": W, "box_levels": info.box_levels, "sat_shift": info.sat_shift,
+                   "output_tile": info.box_tile},
         "plan_ms": round(plan_ms, 2),
         "kernel_ms": {"kz_rangebox": round(k_ms, 5)},
         "roofline": {"bound": "alu", "achieved": tops, "peak": INT32_PEAK_TOPS, "unit": "TOP/s",

@@ -191,6 +191,7 @@ typedef struct {
   int direct;         /* 1: filters by direct summation (BF_FLAG_DIRECT / _AUTO) */
   int range_box;      /* 1: the 8-bit range-box regime (BF_FLAG_RANGE_BOX) */
   int box_levels;     /* its level window half-width floor(255 T_r); -1 otherwise */
+  int box_tile;       /* its output tile edge (64, or 32 where a 64 tile's region exceeds LDS) */
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);

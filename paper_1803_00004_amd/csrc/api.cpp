@@ -603,6 +603,7 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   info->direct = plan->host_tables.direct;
   info->range_box = plan->host_tables.range_box;
   info->box_levels = plan->host_tables.range_box ? plan->host_tables.box_zr : -1;
+  info->box_tile = plan->host_tables.range_box ? bf::rangebox_tile(plan->host_tables) : 0;
   info->n_single = plan->host_tables.n_single;
   if (plan->host_tables.range_box) {
     info->sat_shift = (int)std::lround(std::log2(plan->host_tables.box_scale));

@@ -127,6 +127,7 @@ int lds_pitch_for(int width);
 bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const void *I, float *out, float *num,
                             float *den, int H, int W, void *stream);
 size_t rangebox_lds_bytes(const DevTables &host);
+int rangebox_tile(const DevTables &host);  // output tile edge of the range-box kernel (0: does not fit)
 constexpr int kMaxRangeBoxRadius = 48;
 
 // Direct summation of Eq. BF for a plan with host.direct set.

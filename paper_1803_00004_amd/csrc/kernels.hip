@@ -916,6 +916,11 @@ size_t rangebox_lds_bytes(const DevTables &host) {
   return a <= kLdsLimit ? a : rangebox_lds<32, 512>(host);
 }
 
+int rangebox_tile(const DevTables &host) {
+  if (rangebox_lds<64, 1024>(host) <= kLdsLimit) return 64;
+  return rangebox_lds<32, 512>(host) <= kLdsLimit ? 32 : 0;
+}
+
 bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const void *I, float *out, float *num,
                             float *den, int H, int W, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);

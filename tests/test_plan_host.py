@@ -258,6 +258,8 @@ def test_range_box_plan_rules():
     assert p.info.range_box == 1 and abs(p.info.T - p.info.T_r) < 1e-15
     assert p.info.box_levels == int(np.floor(255 * 0.1 * np.sqrt(2 * np.log(100))))
     assert p.workspace_size(1080, 1920) == 0
+    assert p.info.box_tile == 64
+    assert bf.Plan(16.0, 0.1, 48, 5, 4, dtype="u8", range_box=True, host_only=True).info.box_tile == 32
     wide = bf.Plan(3.0, 0.5, 9, 5, 4, dtype="u8", range_box=True, host_only=True)
     assert wide.info.box_levels == 255
     with pytest.raises(bf.BFError) as e:
