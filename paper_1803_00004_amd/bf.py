@@ -91,6 +91,20 @@ def lib():
         L.bf_plan_spatial_kernel.argtypes = [vp, dp, i]
         L.bf_plan_taps.argtypes = [vp, ip, ip, dp, i]
         L.bf_plan_spatial_groups.argtypes = [vp, ip, ip, i]
+        L.bf_autotune.argtypes = [vp, i, i, i, vp, ip]
+        L.bf_tuning_set.argtypes = [vp, i, i, i, i, i]
+        L.bf_autotune_clear.argtypes = []
+        L.bf_precompute_size.argtypes = [vp, i, i, ctypes.POINTER(sz)]
+        L.bf_precompute.argtypes = [vp, vp, i, i, vp, sz, vp]
+        L.bf_precomputed_compatible.argtypes = [vp, vp]
+        L.bf_filter_precomputed.argtypes = [vp, vp, vp, vp, i, i, vp, sz, vp]
+        L.bf_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_ServerOpts)]
+        L.bf_server_destroy.argtypes = [vp]
+        L.bf_server_submit.argtypes = [vp, vp, vp, vp, i, i, ctypes.c_ulonglong, d]
+        L.bf_server_poll.argtypes = [vp, d, ctypes.POINTER(Completion), i, ip]
+        L.bf_server_pending.argtypes = [vp, ip, ip]
+        L.bf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.bf_version.argtypes = []
         L.bf_profile_enable.argtypes = [i]
         L.bf_profile_read.argtypes = [dp, ip]
         L.bf_status_string.argtypes = [i]

@@ -27,6 +27,19 @@ def test_library_exports_every_declared_symbol():
     assert bf.lib().bf_version().decode().startswith("bf-mi355x")
 
 
+def test_binding_declares_every_argument_type():
+    """Every entry point has its ctypes argument types: a size_t passed as a
+    plain Python int would be cut to a C int (workspaces above 2 GiB)."""
+    L = bf.lib()
+    missing = [n for n in bf.EXPORTED if getattr(L, n).argtypes is None]
+    assert not missing, missing
+    # a size above 2^32 reaches the library intact: the bound check sees it
+    p = bf.Plan(3.0, 0.1, 9, 8, 4, host_only=True)
+    big = (1 << 33) + 5
+    assert L.bf_filter_precomputed(p.handle, p.handle, ctypes.c_void_p(0x10000), ctypes.c_void_p(0x90000), 16, 16,
+                                   ctypes.c_void_p(1 << 40), big, None) == bf.BF_ERR_INVALID_ARG  # host-only plan
+
+
 @pytest.mark.parametrize("ss,r,ns,sr,nr", CONFIGS)
 def test_plan_tables_match_oracle(ss, r, ns, sr, nr):
     p = bf.Plan(ss, sr, r, nr, ns, host_only=True)
