@@ -553,3 +553,46 @@ def test_range_box_in_batches(torch_dev):
     torch.cuda.synchronize()
     for o, s in zip(outs, singles):
         assert torch.equal(o, s)
+
+
+def test_served_mixed_plan_kinds(torch_dev):
+    """The request loop with every kind of plan in one queue: Gaussian and
+    exponential expansions, direct summation (both range kinds) and the 8-bit
+    range-box regime, on 8-bit images of mixed sizes.  Each result is bitwise
+    the single-image result."""
+    import torch
+    bf = _bf()
+    plans = [bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8"),
+             bf.Plan(3.0, 0.1, 14, 12, 6, dtype="u8", kernel_s="exponential", kernel_r="exponential"),
+             bf.Plan(2.0, 0.1, 6, 8, 4, dtype="u8", direct=True),
+             bf.Plan(2.0, 0.1, 9, 8, 4, dtype="u8", direct=True, kernel_s="exponential", kernel_r="exponential"),
+             bf.Plan(8.0, 0.1, 24, 5, 6, dtype="u8", range_box=True),
+             bf.Plan(3.0, 0.1, 9, 5, 4, dtype="u8", range_box=True)]
+    rng = np.random.default_rng(31)
+    sizes = [(int(rng.integers(40, 300)), int(rng.integers(40, 300))) for _ in range(24)]
+    imgs = [torch.from_numpy(synth.gen_image_u8(h, w, 4, 0.03, 100 + i)).cuda() for i, (h, w) in enumerate(sizes)]
+    which = [i % len(plans) for i in range(len(imgs))]
+    outs = [torch.full(I.shape, -1.0, device="cuda") for I in imgs]
+    srv = bf.Server(hbm_budget=1 << 30, max_batch=5, n_streams=2)
+    for i, I in enumerate(imgs):
+        srv.submit(plans[which[i]], I, outs[i], tag=i, now=0.0)
+    import time
+    done = {}
+    t0 = time.perf_counter()
+    while len(done) < len(imgs) and time.perf_counter() - t0 < 60.0:
+        for c in srv.poll(time.perf_counter() - t0):
+            done[c.tag] = c
+    srv.close()
+    assert len(done) == len(imgs)
+    assert all(c.status == bf.BF_OK for c in done.values())
+    for i, I in enumerate(imgs):
+        alone = bf.filter(plans[which[i]], I)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], alone), (i, which[i])
+    # one request of each kind against its oracle
+    Z = imgs[4].cpu().numpy()
+    ref = oracle.expanded_rangebox(Z, oracle.make_plan(8.0, 24, 6, 0.1, 5, span=0.0))
+    assert np.abs(outs[4].cpu().numpy() - ref).max() <= TIGHT
+    Z = imgs[1].cpu().numpy()
+    ref = oracle.expanded_box(Z, oracle.make_plan(3.0, 14, 6, 0.1, 12, kind_s="exponential", kind_r="exponential"))
+    assert np.abs(outs[1].cpu().numpy() - ref).max() <= TIGHT
