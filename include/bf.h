@@ -75,8 +75,15 @@ typedef struct {
 typedef enum { BF_IN_F32 = 0, BF_IN_U8 = 1 } bf_dtype_t;
 
 /* PLAIN: int32 summed-area tables (exact), FP64 tap sums; max-abs error
- * against the FP64 expanded form about 1e-6.  REDUCED: reserved for the
- * reduced-precision path (BF_ERR_UNSUPPORTED when not built). */
+ * against the FP64 expanded form about 1e-6.  REDUCED: the term images are
+ * stored once in FP16 (2 bytes per pixel and table, no halo copies) and the
+ * lookup kernel builds each table of its output tile in LDS from them (exact
+ * int32 sums of the FP16 values); the error is the FP16 rounding of the term
+ * values, a few 1e-5.  REDUCED needs every tap in a symmetric quadruplet
+ * (at most 12) and a region of at most 128 x 128 for its 32 x 32 output
+ * tiles (radius <= 48), and neither DIRECT nor RANGE_BOX (BF_ERR_INVALID_ARG);
+ * else BF_ERR_UNSUPPORTED.  Workspace: n_images H W 2 bytes; no pre-computed
+ * tables, no autotuning. */
 typedef enum { BF_PREC_PLAIN = 0, BF_PREC_REDUCED = 1 } bf_precision_t;
 
 #define BF_FLAG_HOST_ONLY 0x1u /* fit tables on the host only; no device work, no filtering */
@@ -192,6 +199,7 @@ typedef struct {
   int range_box;      /* 1: the 8-bit range-box regime (BF_FLAG_RANGE_BOX) */
   int box_levels;     /* its level window half-width floor(255 T_r); -1 otherwise */
   int box_tile;       /* its output tile edge (64, or 32 where a 64 tile's region exceeds LDS) */
+  int reduced;        /* 1: BF_PREC_REDUCED (FP16 term images, tables built in LDS) */
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);

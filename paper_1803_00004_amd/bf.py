@@ -57,7 +57,7 @@ class PlanInfo(ctypes.Structure):
                 ("T_s", ctypes.c_double), ("T_r", ctypes.c_double), ("T", ctypes.c_double),
                 ("den_floor", ctypes.c_double), ("n_quads", ctypes.c_int), ("n_single", ctypes.c_int),
                 ("lookup_kernel", ctypes.c_int), ("direct", ctypes.c_int), ("range_box", ctypes.c_int),
-                ("box_levels", ctypes.c_int), ("box_tile", ctypes.c_int)]
+                ("box_levels", ctypes.c_int), ("box_tile", ctypes.c_int), ("reduced", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

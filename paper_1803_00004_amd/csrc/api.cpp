@@ -46,7 +46,8 @@ TuneKey tune_key(const bf_plan_s *p, int H, int W) {
 }
 
 bool tunable(const bf_plan_s *p) {
-  return p->tile == 0 && p->host_tables.n_single == 0 && !p->host_tables.direct && !p->host_tables.range_box;
+  return p->tile == 0 && p->host_tables.n_single == 0 && !p->host_tables.direct && !p->host_tables.range_box &&
+         !p->host_tables.reduced;
 }
 
 bf::Geometry geometry_with(const bf_plan_s *p, int H, int W, int tile_override, int kb_single,
@@ -56,8 +57,9 @@ bf::Geometry geometry_with(const bf_plan_s *p, int H, int W, int tile_override, 
   bf::choose_tiling(H, W, p->fit.radius, p->host_tables.n_terms, tile_override ? tile_override : p->tile,
                     p->gmax, box_edge, &tile, &q);
   // a direct plan keeps no tables: an empty workspace
-  const bool no_tables = p->host_tables.direct || p->host_tables.range_box;
+  const bool no_tables = p->host_tables.direct || p->host_tables.range_box || p->host_tables.reduced;
   bf::Geometry g = bf::make_geometry(H, W, tile, p->fit.radius, no_tables ? 0 : p->host_tables.n_images, q);
+  if (p->host_tables.reduced) g.bytes = bf::reduced_workspace_bytes(p->host_tables, H, W);  // FP16 term images
   g.kb_single = kb_single;
   g.ka_one = ka_one;
   return g;
@@ -100,7 +102,6 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   if (opts) o = *opts;
   if (o.in_dtype != BF_IN_F32 && o.in_dtype != BF_IN_U8) return BF_ERR_INVALID_ARG;
   if (o.precision != BF_PREC_PLAIN && o.precision != BF_PREC_REDUCED) return BF_ERR_INVALID_ARG;
-  if (o.precision == BF_PREC_REDUCED) return BF_ERR_UNSUPPORTED;
   const double eps = o.eps == 0.0 ? 0.01 : o.eps;
   const double span = o.span == 0.0 ? 1.0 : o.span;
   if (!(span > 0) || !std::isfinite(span) || radius < 0) return BF_ERR_INVALID_ARG;
@@ -117,6 +118,11 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   if (range_box && o.in_dtype != BF_IN_U8) {
     delete p;
     return BF_ERR_UNSUPPORTED;
+  }
+  const bool reduced = o.precision == BF_PREC_REDUCED;
+  if (reduced && (o.flags & (BF_FLAG_DIRECT | BF_FLAG_DIRECT_AUTO | BF_FLAG_RANGE_BOX))) {
+    delete p;
+    return BF_ERR_INVALID_ARG;
   }
   bf_status_t st = bf::fit_plan((int)K_s, (int)K_r, sigma_s, sigma_r, radius, N, eps, range_box ? 0.0 : span, &p->fit);
   if (st != BF_OK) {
@@ -237,6 +243,13 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   // Cost model in vector operations per pixel, fitted to MI355X timings of
   // both paths at 1920 x 1080: direct 8.5 (2r + 1)^2; expansion
   // (1700 + n_images (85 + 10 quadruplets)) (1 + r / 120).
+  if (reduced) {
+    t.reduced = 1;
+    if (bf::reduced_tile(t) == 0 || t.n_quads > 12 || t.n_single != 0) {
+      delete p;
+      return BF_ERR_UNSUPPORTED;
+    }
+  }
   if (range_box) {
     if (f.radius > bf::kMaxRangeBoxRadius || t.n_single != 0) {
       delete p;
@@ -549,7 +562,8 @@ bf_status_t bf_precompute_size(bf_plan_t tables_plan, int H, int W, size_t *byte
 bf_status_t bf_precompute(bf_plan_t tables_plan, const void *I, int H, int W, void *ws, size_t ws_bytes,
                           void *stream) {
   if (!tables_plan || !I || !ws || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
-  if (tables_plan->host_tables.direct || tables_plan->host_tables.range_box) return BF_ERR_UNSUPPORTED;
+  if (tables_plan->host_tables.direct || tables_plan->host_tables.range_box || tables_plan->host_tables.reduced)
+    return BF_ERR_UNSUPPORTED;
   if (tables_plan->flags & BF_FLAG_HOST_ONLY) return BF_ERR_INVALID_ARG;
   const bf::Geometry g = precompute_geometry(tables_plan, H, W);
   const size_t in_bytes = (size_t)H * W * (tables_plan->in_dtype == BF_IN_U8 ? 1 : 4);
@@ -561,7 +575,7 @@ bf_status_t bf_precompute(bf_plan_t tables_plan, const void *I, int H, int W, vo
 bf_status_t bf_precomputed_compatible(bf_plan_t tables_plan, bf_plan_t plan) {
   if (!tables_plan || !plan) return BF_ERR_INVALID_ARG;
   if (tables_plan->host_tables.direct || plan->host_tables.direct || tables_plan->host_tables.range_box ||
-      plan->host_tables.range_box)
+      plan->host_tables.range_box || tables_plan->host_tables.reduced || plan->host_tables.reduced)
     return BF_ERR_UNSUPPORTED;
   const bf::DevTables &a = tables_plan->host_tables, &b = plan->host_tables;
   if (tables_plan->in_dtype != plan->in_dtype) return BF_ERR_INVALID_ARG;
@@ -604,6 +618,7 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   info->range_box = plan->host_tables.range_box;
   info->box_levels = plan->host_tables.range_box ? plan->host_tables.box_zr : -1;
   info->box_tile = plan->host_tables.range_box ? bf::rangebox_tile(plan->host_tables) : 0;
+  info->reduced = plan->host_tables.reduced;
   info->n_single = plan->host_tables.n_single;
   if (plan->host_tables.range_box) {
     info->sat_shift = (int)std::lround(std::log2(plan->host_tables.box_scale));

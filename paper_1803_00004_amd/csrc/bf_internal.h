@@ -87,6 +87,7 @@ struct DevTables {
   int box_zr;                          // level window half-width floor(255 T_r), <= 255
   double box_scale;                    // 2^q of the slab tables
   double box_w[511];                   // W(d) = sum_k a_k cos(omega_k d / 255) [|d| <= zr] at d + 255
+  int reduced;                         // FP16 term images, tables built in LDS (BF_PREC_REDUCED)
 };
 
 // Geometry of one image under a plan: tiles of `tile` outputs with their
@@ -129,6 +130,14 @@ bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const v
 size_t rangebox_lds_bytes(const DevTables &host);
 int rangebox_tile(const DevTables &host);  // output tile edge of the range-box kernel (0: does not fit)
 constexpr int kMaxRangeBoxRadius = 48;
+
+// Reduced precision (host.reduced): FP16 term images in ws ([table][H][W]),
+// then the lookup kernel with tables built in LDS.  Output tile edge 64 or 32
+// (0: the region does not fit); workspace bytes for an H x W image.
+bf_status_t launch_reduced(const DevTables *dev, const DevTables &host, const Geometry &g, const void *I,
+                           float *out, float *num, float *den, void *ws, void *stream);
+int reduced_tile(const DevTables &host);
+size_t reduced_workspace_bytes(const DevTables &host, int H, int W);
 
 // Direct summation of Eq. BF for a plan with host.direct set.
 bf_status_t launch_direct(const DevTables &host, const void *I, float *out, float *num, float *den,

@@ -946,6 +946,269 @@ bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const v
 }
 
 // ---------------------------------------------------------------------------
+// Reduced precision: the term images C I, S I, C, S (I alone for k = 0; the
+// byte itself for 8-bit input, exact in FP16) are stored once in FP16,
+// [table][H][W] with no halo copies, half the bytes of an int32 value.  The
+// lookup kernel then builds each table of its output tile in LDS from them:
+// the region's values, rounded to round(v 2^q) in int32, summed by column
+// in registers down each wave's row segment with one DPP row scan per row,
+// segment carries added in place per column, and the box sums and fold of
+// the plain lookup.  The next table's values are loaded while the current one
+// is read.  Out-of-image values are zero, so the table's corners need no clamp.
+// ---------------------------------------------------------------------------
+template <bool U8>
+__global__ __launch_bounds__(256) void kr_modulate(const void *__restrict__ I, int H, int W,
+                                                   const DevTables *__restrict__ tab,
+                                                   _Float16 *__restrict__ img) {
+  const long long n = (long long)H * W;
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n) return;
+  float px, v;
+  load_pixel<U8>(I, idx, &px, &v);
+  for (int t = 0; t < tab->n_terms; ++t) {
+    _Float16 *dst = img + (long long)tab->slot[t] * n + idx;
+    if (tab->k_is_zero[t]) {
+      dst[0] = (_Float16)(U8 ? px : v);
+      continue;
+    }
+    const float fr = phase_rev(tab->f_hi[t], tab->f_lo[t], px);
+    const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
+    dst[0] = (_Float16)(C * v);
+    dst[n] = (_Float16)(S * v);
+    dst[2 * n] = (_Float16)C;
+    dst[3 * n] = (_Float16)S;
+  }
+}
+
+template <int TE, int NT, int NQ, bool U8>
+__global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H, int W,
+                                              const DevTables *__restrict__ tab,
+                                              const _Float16 *__restrict__ img, float scale, double inv_scale,
+                                              float *__restrict__ out, float *__restrict__ num_out,
+                                              float *__restrict__ den_out) {
+  constexpr int NW = NT / 64;              // waves: one row segment each
+  static_assert(NW <= 16, "segment carries are scanned in 16-lane rows");
+  constexpr int SEGMAX = kZMaxRegion / NW;  // rows per segment
+  constexpr int PPT = TE * TE / NT;        // pixels per thread
+  constexpr int RSTEP = NT / TE;           // tile rows between a thread's pixels
+  constexpr int P = kZPitch;               // table pitch (int32): every lane's two columns fit
+  extern __shared__ int kr_lds[];
+  int *sat = kr_lds;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tiles_x = (W + TE - 1) / TE;
+  const int ty0 = (blockIdx.x / tiles_x) * TE, tx0 = (blockIdx.x % tiles_x) * TE;
+  const int dy0 = tab->tap_dy_min, dx0 = tab->tap_dx_min;
+  const int Y0 = ty0 + dy0, X0 = tx0 + dx0;  // image position of table corner (0, 0)
+  const int RS = TE - 1 + tab->tap_dy_max - dy0, RC = TE - 1 + tab->tap_dx_max - dx0;  // <= 128 each
+  const long long npx = (long long)H * W;
+  const int seg = (RS + NW - 1) / NW;
+  const int ry0 = wave * seg, nrows = max(0, min(seg, RS - ry0));
+  const int xs0 = X0 + 2 * lane, xs1 = xs0 + 1;  // this lane's source columns
+  const bool c0ok = 2 * lane < RC && xs0 >= 0 && xs0 < W;
+  const bool c1ok = 2 * lane + 1 < RC && xs1 >= 0 && xs1 < W;
+
+  for (int x = tid; x < P; x += NT) sat[x] = 0;  // table row 0 and column 0 stay zero
+  for (int y = tid; y <= RS; y += NT) sat[y * P] = 0;
+
+  _Float16 h0[SEGMAX], h1[SEGMAX];
+  auto load = [&](int m) {
+    const _Float16 *base = img + (long long)m * npx;
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i) {
+      const int y = Y0 + ry0 + i;
+      const bool rok = i < nrows && y >= 0 && y < H;
+      h0[i] = (rok && c0ok) ? base[(long long)y * W + xs0] : (_Float16)0.0f;
+      h1[i] = (rok && c1ok) ? base[(long long)y * W + xs1] : (_Float16)0.0f;
+    }
+  };
+
+  // the thread's pixels: tile row prow + RSTEP i, column pcol; table corner
+  // (y + dy - Y0, x + dx - X0) of tap (dy, dx)
+  const int prow = tid / TE, pcol = tid % TE;
+  const uint32_t lb = (uint32_t)(prow * P + pcol);
+  const int nq = tab->n_quads;
+  uint32_t qa[NQ][4];
+  double qw[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q < nq) {
+      const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
+      const int ra = dy - dy0, rb = 1 - dy - dy0, ca = dx - dx0, cb = 1 - dx - dx0;
+      qa[q][0] = (lb + (uint32_t)(ra * P + ca)) * 4u;
+      qa[q][1] = (lb + (uint32_t)(rb * P + ca)) * 4u;
+      qa[q][2] = (lb + (uint32_t)(ra * P + cb)) * 4u;
+      qa[q][3] = (lb + (uint32_t)(rb * P + cb)) * 4u;
+      qw[q] = tab->quad_w[q];
+    } else {
+      qa[q][0] = qa[q][1] = qa[q][2] = qa[q][3] = lb * 4u;
+      qw[q] = 0.0;
+    }
+  }
+  float pxv[PPT], cs[PPT], sn[PPT];
+  double num[PPT], den[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int y = ty0 + prow + RSTEP * i, x = tx0 + pcol;
+    pxv[i] = 0.0f;
+    if (y < H && x < W) {
+      float px, v;
+      load_pixel<U8>(I, (long long)y * W + x, &px, &v);
+      pxv[i] = px;
+    }
+    num[i] = 0.0;
+    den[i] = 0.0;
+    cs[i] = sn[i] = 0.0f;
+  }
+
+  const int n = tab->n_images;
+  load(0);
+  for (int m = 0; m < n; ++m) {
+    const int t = tab->slot_term[m], part = tab->slot_part[m];
+    const float sc = (U8 && part == 4) ? 1.0f : scale;  // 8-bit k = 0: exact byte sums
+    __syncthreads();  // the previous table's reads are done
+    {
+      uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+      for (int i = 0; i < SEGMAX; ++i) {
+        if (i >= nrows) break;
+        c0 += (uint32_t)__float2int_rn((float)h0[i] * sc);
+        c1 += (uint32_t)__float2int_rn((float)h1[i] * sc);
+        const uint32_t tt = c0 + c1;
+        const uint32_t e = wave_inclusive_scan(tt) - tt;
+        int *row = sat + (ry0 + i + 1) * P + 2 * lane + 1;  // columns past the region: padding
+        row[0] = (int)(e + c0);
+        row[1] = (int)(e + tt);
+      }
+    }
+    if (m + 1 < n) load(m + 1);  // in flight during the carries and the lookups
+    __syncthreads();
+    // carries: column X by one 16-lane row, lane w holding segment w: the
+    // exclusive sum of the segments above is added to the segment's entries
+    for (int t0 = wave * 64; t0 < 16 * (RC + 1); t0 += NT) {
+      const int X = (t0 + lane) >> 4, w = lane & 15;
+      const bool ok = X >= 1 && X <= RC && w < NW && w * seg < RS;
+      const int last = min((w + 1) * seg, RS);
+      const uint32_t v = ok ? (uint32_t)sat[last * P + X] : 0u;
+      const uint32_t c = row16_inclusive_scan(v) - v;
+      if (ok && c != 0)
+        for (int r = w * seg + 1; r <= last; ++r) sat[r * P + X] = (int)((uint32_t)sat[r * P + X] + c);
+    }
+    __syncthreads();
+    if (part == 0) {
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        const float fr = phase_rev(tab->f_hi[t], tab->f_lo[t], pxv[i]);
+        cs[i] = __builtin_amdgcn_cosf(fr);
+        sn[i] = __builtin_amdgcn_sinf(fr);
+      }
+    }
+    double sv[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) sv[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        const uint32_t o = i * RSTEP * P * 4u;
+        const int box = box_of(lds_ld(sat, qa[q][0] + o), lds_ld(sat, qa[q][1] + o),
+                               lds_ld(sat, qa[q][2] + o), lds_ld(sat, qa[q][3] + o));
+        sv[i] = __builtin_fma(qw[q], (double)box, sv[i]);
+      }
+    }
+    const double ai = tab->a[t] * (U8 && part == 4 ? 1.0 / 255.0 : inv_scale);
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      if (part == 4) {
+        num[i] = __builtin_fma(ai, sv[i], num[i]);
+        // denominator of the k = 0 term from the clamped corners (table of ones)
+        const int y = ty0 + prow + RSTEP * i, x = tx0 + pcol;
+        double d0 = 0.0;
+        for (int k = 0; k < tab->n_taps4; ++k) {
+          const int Yc = min(max(y + tab->tap_dy[k], 0), H), Xc = min(max(x + tab->tap_dx[k], 0), W);
+          d0 = __builtin_fma(tab->tap_w[k], (double)Yc * (double)Xc, d0);
+        }
+        den[i] = __builtin_fma(tab->a[t], d0, den[i]);
+      } else if (part == 0) {
+        num[i] = __builtin_fma(ai * cs[i], sv[i], num[i]);
+      } else if (part == 1) {
+        num[i] = __builtin_fma(ai * sn[i], sv[i], num[i]);
+      } else if (part == 2) {
+        den[i] = __builtin_fma(ai * cs[i], sv[i], den[i]);
+      } else {
+        den[i] = __builtin_fma(ai * sn[i], sv[i], den[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int y = ty0 + prow + RSTEP * i, x = tx0 + pcol;
+    if (y >= H || x >= W) continue;
+    const long long idx = (long long)y * W + x;
+    const float xv = U8 ? pxv[i] * (1.0f / 255.0f) : pxv[i];
+    out[idx] = den[i] > tab->den_floor ? (float)(num[i] / den[i]) : xv;
+    if (num_out) num_out[idx] = (float)num[i];
+    if (den_out) den_out[idx] = (float)den[i];
+  }
+}
+
+// 32 x 32 output tiles (512 threads, two pixels each): 64 x 64 tiles with four
+// pixels per thread exceed 128 registers and spill.
+int reduced_tile(const DevTables &host) {
+  if (31 + host.tap_dy_max - host.tap_dy_min <= kZMaxRegion && 31 + host.tap_dx_max - host.tap_dx_min <= kZMaxRegion)
+    return 32;
+  return 0;
+}
+
+size_t reduced_workspace_bytes(const DevTables &host, int H, int W) {
+  return ((size_t)host.n_images * H * W * sizeof(_Float16) + 255) / 256 * 256;
+}
+
+template <int TE, int NT, bool U8>
+static hipError_t launch_kr_nq(int nq, dim3 grid, size_t lds, hipStream_t s, const void *I, int H, int W,
+                               const DevTables *dev, const _Float16 *img, float scale, double inv, float *out,
+                               float *num, float *den) {
+  auto go = [&](auto k) {
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, grid, dim3(NT), lds, s, I, H, W, dev, img, scale, inv, out, num, den);
+    return hipGetLastError();
+  };
+  if (nq <= 4) return go(kr_tile<TE, NT, 4, U8>);
+  if (nq <= 8) return go(kr_tile<TE, NT, 8, U8>);
+  return go(kr_tile<TE, NT, 12, U8>);
+}
+
+bf_status_t launch_reduced(const DevTables *dev, const DevTables &host, const Geometry &g, const void *I,
+                           float *out, float *num, float *den, void *ws, void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int te = reduced_tile(host);
+  if (te == 0 || host.n_quads > 12 || host.n_single != 0) return BF_ERR_UNSUPPORTED;
+  const int RS = te - 1 + host.tap_dy_max - host.tap_dy_min;
+  const size_t lds = (size_t)(RS + 1) * kZPitch * 4;
+  _Float16 *img = static_cast<_Float16 *>(ws);
+  const long long npx = (long long)g.H * g.W;
+  profile_mark(0, 1, stream);
+  hipError_t e;
+  const unsigned blocks_m = (unsigned)((npx + 255) / 256);
+  if (host.in_u8)
+    hipLaunchKernelGGL((kr_modulate<true>), dim3(blocks_m), dim3(256), 0, s, I, g.H, g.W, dev, img);
+  else
+    hipLaunchKernelGGL((kr_modulate<false>), dim3(blocks_m), dim3(256), 0, s, I, g.H, g.W, dev, img);
+  e = hipGetLastError();
+  profile_mark(0, 0, stream);
+  if (e != hipSuccess) return BF_ERR_DEVICE;
+  const float scale = std::ldexp(1.0f, g.sat_shift);
+  const double inv = std::ldexp(1.0, -g.sat_shift);
+  const dim3 grid(((g.W + te - 1) / te) * ((g.H + te - 1) / te));
+  profile_mark(1, 1, stream);
+  e = host.in_u8 ? launch_kr_nq<32, 512, true>(host.n_quads, grid, lds, s, I, g.H, g.W, dev, img, scale, inv, out, num, den)
+                 : launch_kr_nq<32, 512, false>(host.n_quads, grid, lds, s, I, g.H, g.W, dev, img, scale, inv, out, num, den);
+  profile_mark(1, 0, stream);
+  return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
+}
+
+// ---------------------------------------------------------------------------
 // Batches: every image of a batch runs in one launch per kernel.  The
 // per-image descriptors travel by value in the kernel arguments (nothing to
 // allocate, copy or keep alive, so a batch can be captured in a graph).
@@ -1214,6 +1477,7 @@ bf_status_t launch_filter(const DevTables *dev, const DevTables &host, const Geo
                           void *stream) {
   if (host.direct) return launch_direct(host, I, out, num, den, g.H, g.W, stream);
   if (host.range_box) return launch_rangebox(dev, host, I, out, num, den, g.H, g.W, stream);
+  if (host.reduced) return launch_reduced(dev, host, g, I, out, num, den, ws, stream);
   bf_status_t st = launch_tables(dev, host, g, I, ws, stream);
   if (st != BF_OK) return st;
   return launch_lookup(dev, host, g, I, out, num, den, ws, stream);
@@ -1364,6 +1628,9 @@ bf_status_t launch_batch(const BatchItem *items_all, int n_all, uint32_t *heads,
       if (st != BF_OK) return st;
     } else if (it.host->range_box) {
       bf_status_t st = launch_rangebox(it.dev, *it.host, it.I, it.out, nullptr, nullptr, it.g.H, it.g.W, stream);
+      if (st != BF_OK) return st;
+    } else if (it.host->reduced) {
+      bf_status_t st = launch_reduced(it.dev, *it.host, it.g, it.I, it.out, nullptr, nullptr, it.ws, stream);
       if (st != BF_OK) return st;
     } else {
       kept.push_back(it);

@@ -596,3 +596,40 @@ def test_served_mixed_plan_kinds(torch_dev):
     Z = imgs[1].cpu().numpy()
     ref = oracle.expanded_box(Z, oracle.make_plan(3.0, 14, 6, 0.1, 12, kind_s="exponential", kind_r="exponential"))
     assert np.abs(outs[1].cpu().numpy() - ref).max() <= TIGHT
+
+
+@pytest.mark.parametrize("H,W,ss,r,ns,sr,nr,dtype", [
+    (300, 517, 3.0, 9, 4, 0.1, 8, "f32"),     # several tiles, ragged tails
+    (197, 263, 4.0, 12, 6, 0.2, 8, "u8"),
+    (1080 // 4, 1920 // 4, 8.0, 24, 6, 0.1, 16, "f32"),
+    (130, 129, 16.0, 48, 8, 0.05, 32, "f32"),  # the largest region of the path (12 quadruplets)
+    (7, 13, 3.0, 9, 4, 0.1, 8, "f32"),         # image smaller than the window
+    (1, 1, 3.0, 9, 4, 0.1, 8, "u8"),
+])
+def test_reduced_precision_vs_oracle(torch_dev, H, W, ss, r, ns, sr, nr, dtype):
+    """FP16 term images, tables built in LDS: within the reduced bar 1e-3 of
+    the oracle's T3 (FP16 rounding of the term values, a few 1e-5)."""
+    bf = _bf()
+    I = synth.gen_image_u8(H, W, 5, 0.03, H + W) if dtype == "u8" else synth.gen_image(H, W, 5, 0.03, H + W)
+    p = bf.Plan(ss, sr, r, nr, ns, dtype=dtype, precision="reduced")
+    assert p.info.reduced == 1
+    out = _run(torch_dev, p, I)
+    ref = oracle.expanded_box(I, oracle.make_plan(ss, r, ns, sr, nr))
+    err = np.abs(out - ref).max()
+    _report("reduced %dx%d r %d N %d %s vs T3" % (H, W, r, nr, dtype), err)
+    assert err <= 1e-3
+    assert err <= 2e-4  # the FP16 bound in practice; the 1e-3 bar leaves room
+
+
+def test_reduced_precision_in_batches(torch_dev):
+    import torch
+    bf = _bf()
+    pr = bf.Plan(3.0, 0.1, 9, 8, 4, precision="reduced")
+    pe = bf.Plan(3.0, 0.1, 9, 8, 4)
+    imgs = [torch.from_numpy(synth.gen_image(h, w, 4, 0.03, h * w)).cuda() for h, w in ((120, 333), (77, 64), (256, 256))]
+    plans = [pr, pe, pr]
+    singles = [bf.filter(p, I).clone() for p, I in zip(plans, imgs)]
+    outs = bf.filter_batch(plans, imgs)
+    torch.cuda.synchronize()
+    for o, s in zip(outs, singles):
+        assert torch.equal(o, s)

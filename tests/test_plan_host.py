@@ -287,3 +287,21 @@ def test_range_box_plan_rules():
     o = oracle.make_plan(3.0, 9, 4, 0.1, 5, span=0.0)
     k, a, w = p.range_terms()
     assert k.tolist() == o.range.k.tolist() and np.abs(a - o.a).max() < 1e-13
+
+
+def test_reduced_precision_plan_rules():
+    """BF_PREC_REDUCED: FP16 term images as workspace (n_images H W 2 bytes),
+    not with the direct or range-box flags, radius <= 48."""
+    p = bf.Plan(3.0, 0.1, 9, 8, 4, precision="reduced", host_only=True)
+    assert p.info.reduced == 1
+    assert p.workspace_size(1080, 1920) == (p.info.n_images * 1080 * 1920 * 2 + 255) // 256 * 256
+    assert bf.Plan(3.0, 0.1, 9, 8, 4, host_only=True).info.reduced == 0
+    with pytest.raises(bf.BFError) as e:
+        bf.Plan(3.0, 0.1, 9, 8, 4, precision="reduced", direct=True, host_only=True)
+    assert e.value.status == bf.BF_ERR_INVALID_ARG
+    with pytest.raises(bf.BFError) as e:
+        bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8", precision="reduced", range_box=True, host_only=True)
+    assert e.value.status == bf.BF_ERR_INVALID_ARG
+    with pytest.raises(bf.BFError) as e:
+        bf.Plan(20.0, 0.1, 60, 8, 4, precision="reduced", host_only=True)
+    assert e.value.status == bf.BF_ERR_UNSUPPORTED
