@@ -63,10 +63,10 @@ def recorded_traffic(workload, kernel):
     return None
 
 
-def kb_roofline(kms, klaunch, ka_bytes, kb_bytes, kb_flops, kb_name):
+def kb_roofline(kms, klaunch, ka_bytes, kb_bytes, kb_flops, kb_name, ka_name="ka_sat"):
     """Roofline of the dominant kernel from per-kernel times (ms summed over
     the timed launches) and algorithmic work summed over the same launches."""
-    names = ["ka_sat", kb_name]
+    names = [ka_name, kb_name]
     dom = 0 if kms[0] >= kms[1] else 1
     t = kms[dom] * 1e-3
     if dom == 0:
@@ -359,6 +359,8 @@ def main():
                              "cfg6_1080p_u8_box"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (no error check)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (heuristic tiling)")
+    ap.add_argument("--precision", choices=["plain", "reduced"], default="plain",
+                    help="reduced: FP16 term images, tables built in LDS (single-image workloads)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run one device copy of MIB MiB (a reference kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -391,8 +393,9 @@ def main():
         one_core = one_core_baseline(args.workload, n1)
 
     t0 = time.perf_counter()
+    reduced = args.precision == "reduced"
     plan = bf.Plan(c["sigma_s"], c["sigma_r"], c["radius"], c["n_range"], c["n_spatial"],
-                   dtype=c["dtype"])
+                   dtype=c["dtype"], precision=args.precision)
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info
     log("[bench] plan %.1f ms: %s" % (plan_ms, info.as_dict()))
@@ -402,7 +405,7 @@ def main():
     out = torch.empty((H, W), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
     tuned = None
-    if not args.no_tune:
+    if not args.no_tune and not reduced:
         t0 = time.perf_counter()
         tuned = plan.autotune(H, W, reps=5, stream=stream)
         log("[bench] autotuner: table tile %d (%.0f ms)" % (tuned, (time.perf_counter() - t0) * 1e3))
@@ -441,50 +444,56 @@ def main():
         % (ms_per_step, mpix, k_avg[0], k_avg[1]))
 
     # re-filtering the same image from tables pre-computed once (lookup only)
-    tables = bf.precompute(plan, I, stream=stream)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(args.steps):
-        bf.filter_precomputed(plan, plan, I, tables, out=out, stream=stream)
-    end.record(stream)
-    torch.cuda.synchronize()
-    refilter_ms = start.elapsed_time(end) / args.steps
-    del tables
-    log("[bench] re-filter from pre-computed tables: %.4f ms (%.1f Mpix/s)"
-        % (refilter_ms, H * W / (refilter_ms * 1e-3) / 1e6))
+    refilter_ms = None
+    if not reduced:
+        tables = bf.precompute(plan, I, stream=stream)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(args.steps):
+            bf.filter_precomputed(plan, plan, I, tables, out=out, stream=stream)
+        end.record(stream)
+        torch.cuda.synchronize()
+        refilter_ms = start.elapsed_time(end) / args.steps
+        del tables
+        log("[bench] re-filter from pre-computed tables: %.4f ms (%.1f Mpix/s)"
+            % (refilter_ms, H * W / (refilter_ms * 1e-3) / 1e6))
 
     # roofline of the dominant kernel, from algorithmic work per launch
     px = H * W
     in_b = 1 if c["dtype"] == "u8" else 4
     n_img = info.n_images
-    ka_bytes = px * (4 * n_img + in_b)             # write every table once, read I
-    kb_bytes = px * (4 * n_img + in_b + 4)         # read every table once, read I, write out
+    vb = 2 if reduced else 4                       # bytes per stored term value (FP16 images / int32 tables)
+    ka_bytes = px * (vb * n_img + in_b)            # write every term image or table once, read I
+    kb_bytes = px * (vb * n_img + in_b + 4)        # read every one once, read I, write out
     kb_flops = px * 2.0 * n_img * info.n_taps      # one FP64 FMA per tap per table
-    kb_name = "kb_tile" if info.lookup_kernel == 1 else "kb_lookup"
-    roof, dom = kb_roofline(k_avg, [1, 1], ka_bytes, kb_bytes, kb_flops, kb_name)
+    kb_name = "kr_tile" if reduced else ("kb_tile" if info.lookup_kernel == 1 else "kb_lookup")
+    roof_names = ["kr_modulate" if reduced else "ka_sat", kb_name]
+    roof, dom = kb_roofline(k_avg, [1, 1], ka_bytes, kb_bytes, kb_flops, kb_name, roof_names[0])
     roof["traffic"] = recorded_traffic(args.workload, roof["kernel"])
     # the whole path against HBM: every table written once and read once, I
     # read twice, out written once (8 n_img + 2 in_b + 4 bytes per pixel)
-    path_bytes = px * (8 * n_img + 2 * in_b + 4)
+    path_bytes = px * (2 * vb * n_img + 2 * in_b + 4)
     path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
 
     result = {
         "metric": METRIC, "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "i32+f64", "data": "synthetic (seeded gradient noise + step edges + Gaussian noise)",
-        "config": {"workload": "%s: %dx%d %s, Gaussian sigma_s=%g r=%d, sigma_r=%g, N_r=%d, N_s=%d"
+        "dtype": "f16+i32+f64" if reduced else "i32+f64",
+        "data": "synthetic (seeded gradient noise + step edges + Gaussian noise)",
+        "config": {"workload": "%s: %dx%d %s, Gaussian sigma_s=%g r=%d, sigma_r=%g, N_r=%d, N_s=%d%s"
                    % (args.workload, W, H, c["dtype"], c["sigma_s"], c["radius"], c["sigma_r"],
-                      c["n_range"], c["n_spatial"]),
+                      c["n_range"], c["n_spatial"], ", reduced precision (FP16 term images)" if reduced else ""),
+                   "precision": args.precision,
                    "H": H, "W": W, "table_tile": tile, "autotuned": tuned is not None, "sat_shift": q,
                    "n_images": n_img, "n_taps": info.n_taps, "workspace_bytes": ws_bytes},
         "plan_ms": round(plan_ms, 2),
-        "kernel_ms": {"ka_sat": round(k_avg[0], 5), kb_name: round(k_avg[1], 5)},
+        "kernel_ms": {roof_names[0]: round(k_avg[0], 5), kb_name: round(k_avg[1], 5)},
         "roofline": roof,
-        "path_hbm": {"algorithmic_bytes_per_px": 8 * n_img + 2 * in_b + 4, "achieved_gbs": round(path_gbs, 1),
+        "path_hbm": {"algorithmic_bytes_per_px": 2 * vb * n_img + 2 * in_b + 4, "achieved_gbs": round(path_gbs, 1),
                      "frac_of_peak": round(path_gbs / HBM_PEAK_GBS, 4)},
-        "refilter_from_precomputed": {"ms": round(refilter_ms, 5),
-                                      "mpix_s": round(H * W / (refilter_ms * 1e-3) / 1e6, 2)},
+        "refilter_from_precomputed": None if refilter_ms is None else {
+            "ms": round(refilter_ms, 5), "mpix_s": round(H * W / (refilter_ms * 1e-3) / 1e6, 2)},
     }
 
     if not args.no_cpu:
