@@ -633,3 +633,26 @@ def test_reduced_precision_in_batches(torch_dev):
     torch.cuda.synchronize()
     for o, s in zip(outs, singles):
         assert torch.equal(o, s)
+
+
+@pytest.mark.parametrize("mode", ["range_box", "reduced"])
+def test_exponential_kernels_in_the_other_paths(torch_dev, mode):
+    """The exponential kernel pair through the range-box regime (against T4)
+    and the reduced-precision path (against T3)."""
+    bf = _bf()
+    H, W = 150, 211
+    Z = synth.gen_image_u8(H, W, 5, 0.03, 41)
+    kw = dict(kind_s="exponential", kind_r="exponential")
+    if mode == "range_box":
+        p = bf.Plan(3.0, 0.1, 14, 6, 6, dtype="u8", range_box=True, kernel_s="exponential", kernel_r="exponential")
+        ref = oracle.expanded_rangebox(Z, oracle.make_plan(3.0, 14, 6, 0.1, 6, span=0.0, **kw))
+        bar = TIGHT
+    else:
+        p = bf.Plan(3.0, 0.1, 14, 12, 6, dtype="u8", precision="reduced", kernel_s="exponential",
+                    kernel_r="exponential")
+        ref = oracle.expanded_box(Z, oracle.make_plan(3.0, 14, 6, 0.1, 12, **kw))
+        bar = 1e-3
+    out = _run(torch_dev, p, Z)
+    err = np.abs(out - ref).max()
+    _report("exponential kernels, %s, %dx%d" % (mode, H, W), err)
+    assert err <= bar
