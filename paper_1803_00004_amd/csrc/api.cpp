@@ -75,6 +75,10 @@ bf::Geometry geometry_of(const bf_plan_s *p, int H, int W) {
   return geometry_with(p, H, W, 0, 0, 0);
 }
 
+// Pre-computed tables are laid out by the untuned heuristic tiling of the
+// plan that builds them, so a later call finds them where they were written.
+bf::Geometry precompute_geometry(const bf_plan_s *p, int H, int W) { return geometry_with(p, H, W, 0, 0, 0); }
+
 bf_status_t check_image(const bf_plan_s *p, const void *I, const float *out, int H, int W) {
   if (!p || !I || !out) return BF_ERR_INVALID_ARG;
   if (p->flags & BF_FLAG_HOST_ONLY) return BF_ERR_INVALID_ARG;
@@ -547,11 +551,6 @@ bf_status_t bf_autotune_clear(void) {
 // Pre-computed tables (Case 1 of Sec. V-C): the term tables of an image built
 // once under one plan serve later plans whose terms they contain.
 // ---------------------------------------------------------------------------
-namespace {
-// Tables are laid out by the untuned heuristic tiling of the plan that
-// builds them, so a later call finds them where they were written.
-bf::Geometry precompute_geometry(const bf_plan_s *p, int H, int W) { return geometry_with(p, H, W, 0, 0, 0); }
-}  // namespace
 
 bf_status_t bf_precompute_size(bf_plan_t tables_plan, int H, int W, size_t *bytes) {
   if (!tables_plan || !bytes || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;

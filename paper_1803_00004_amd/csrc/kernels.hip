@@ -840,18 +840,19 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
       uint32_t c0n = 0, c0d = 0, c1n = 0, c1d = 0;
 #pragma unroll
       for (int i = 0; i < kZSeg; ++i) {
-        if (i >= nrows) break;
-        const int2 va = *reinterpret_cast<const int2 *>(lb + (zq[i] & 0xffffu));
-        const int2 vb = *reinterpret_cast<const int2 *>(lb + (zq[i] >> 16));
-        c0n += (uint32_t)va.x;
-        c0d += (uint32_t)va.y;
-        c1n += (uint32_t)vb.x;
-        c1d += (uint32_t)vb.y;
-        const uint32_t tn = c0n + c1n, td = c0d + c1d;
-        const uint32_t en = wave_inclusive_scan(tn) - tn, ed = wave_inclusive_scan(td) - td;
-        int2 *row = sat + (ry0 + i + 1) * P + 2 * lane + 1;  // columns past the region: padding
-        row[0] = make_int2((int)(en + c0n), (int)(ed + c0d));
-        row[1] = make_int2((int)(en + tn), (int)(ed + td));
+        if (i < nrows) {  // wave-uniform
+          const int2 va = *reinterpret_cast<const int2 *>(lb + (zq[i] & 0xffffu));
+          const int2 vb = *reinterpret_cast<const int2 *>(lb + (zq[i] >> 16));
+          c0n += (uint32_t)va.x;
+          c0d += (uint32_t)va.y;
+          c1n += (uint32_t)vb.x;
+          c1d += (uint32_t)vb.y;
+          const uint32_t tn = c0n + c1n, td = c0d + c1d;
+          const uint32_t en = wave_inclusive_scan(tn) - tn, ed = wave_inclusive_scan(td) - td;
+          int2 *row = sat + (ry0 + i + 1) * P + 2 * lane + 1;  // columns past the region: padding
+          row[0] = make_int2((int)(en + c0n), (int)(ed + c0d));
+          row[1] = make_int2((int)(en + tn), (int)(ed + td));
+        }
       }
     }
     __syncthreads();
@@ -1071,14 +1072,15 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
       uint32_t c0 = 0, c1 = 0;
 #pragma unroll
       for (int i = 0; i < SEGMAX; ++i) {
-        if (i >= nrows) break;
-        c0 += (uint32_t)__float2int_rn((float)h0[i] * sc);
-        c1 += (uint32_t)__float2int_rn((float)h1[i] * sc);
-        const uint32_t tt = c0 + c1;
-        const uint32_t e = wave_inclusive_scan(tt) - tt;
-        int *row = sat + (ry0 + i + 1) * P + 2 * lane + 1;  // columns past the region: padding
-        row[0] = (int)(e + c0);
-        row[1] = (int)(e + tt);
+        if (i < nrows) {  // wave-uniform
+          c0 += (uint32_t)__float2int_rn((float)h0[i] * sc);
+          c1 += (uint32_t)__float2int_rn((float)h1[i] * sc);
+          const uint32_t tt = c0 + c1;
+          const uint32_t e = wave_inclusive_scan(tt) - tt;
+          int *row = sat + (ry0 + i + 1) * P + 2 * lane + 1;  // columns past the region: padding
+          row[0] = (int)(e + c0);
+          row[1] = (int)(e + tt);
+        }
       }
     }
     if (m + 1 < n) load(m + 1);  // in flight during the carries and the lookups
