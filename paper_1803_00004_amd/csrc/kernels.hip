@@ -953,8 +953,8 @@ bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const v
 // lookup kernel then builds each table of its output tile in LDS from them:
 // the region's values, rounded to round(v 2^q) in int32, summed by column
 // in registers down each wave's row segment with one DPP row scan per row,
-// segment carries added in place per column, and the box sums and fold of
-// the plain lookup.  The next table's values are loaded while the current one
+// each segment starting from the column totals of the segments above (two
+// barriers per table), and the box sums and fold of the plain lookup.  The next table's values are loaded while the current one
 // is read.  Out-of-image values are zero, so the table's corners need no clamp.
 // ---------------------------------------------------------------------------
 template <bool U8>
@@ -994,7 +994,8 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
   constexpr int RSTEP = NT / TE;           // tile rows between a thread's pixels
   constexpr int P = kZPitch;               // table pitch (int32): every lane's two columns fit
   extern __shared__ int kr_lds[];
-  int *sat = kr_lds;
+  uint32_t *tot = reinterpret_cast<uint32_t *>(kr_lds);  // [NW][P]: column totals of each wave's segment
+  int *sat = kr_lds + NW * P;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tiles_x = (W + TE - 1) / TE;
@@ -1067,14 +1068,30 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
   for (int m = 0; m < n; ++m) {
     const int t = tab->slot_term[m], part = tab->slot_part[m];
     const float sc = (U8 && part == 4) ? 1.0f : scale;  // 8-bit k = 0: exact byte sums
-    __syncthreads();  // the previous table's reads are done
+    // the segment's fixed-point values and their column totals; the totals of
+    // the segments above are the columns' carry into this segment
+    uint32_t v0[SEGMAX], v1[SEGMAX], s0 = 0, s1 = 0;
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i) {
+      v0[i] = (uint32_t)__float2int_rn((float)h0[i] * sc);  // zero outside the segment and the image
+      v1[i] = (uint32_t)__float2int_rn((float)h1[i] * sc);
+      s0 += v0[i];
+      s1 += v1[i];
+    }
+    tot[wave * P + 2 * lane] = s0;
+    tot[wave * P + 2 * lane + 1] = s1;
+    __syncthreads();  // the totals are in, and the previous table's reads are done
     {
       uint32_t c0 = 0, c1 = 0;
+      for (int w = 0; w < wave; ++w) {
+        c0 += tot[w * P + 2 * lane];
+        c1 += tot[w * P + 2 * lane + 1];
+      }
 #pragma unroll
       for (int i = 0; i < SEGMAX; ++i) {
         if (i < nrows) {  // wave-uniform
-          c0 += (uint32_t)__float2int_rn((float)h0[i] * sc);
-          c1 += (uint32_t)__float2int_rn((float)h1[i] * sc);
+          c0 += v0[i];
+          c1 += v1[i];
           const uint32_t tt = c0 + c1;
           const uint32_t e = wave_inclusive_scan(tt) - tt;
           int *row = sat + (ry0 + i + 1) * P + 2 * lane + 1;  // columns past the region: padding
@@ -1083,19 +1100,7 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
         }
       }
     }
-    if (m + 1 < n) load(m + 1);  // in flight during the carries and the lookups
-    __syncthreads();
-    // carries: column X by one 16-lane row, lane w holding segment w: the
-    // exclusive sum of the segments above is added to the segment's entries
-    for (int t0 = wave * 64; t0 < 16 * (RC + 1); t0 += NT) {
-      const int X = (t0 + lane) >> 4, w = lane & 15;
-      const bool ok = X >= 1 && X <= RC && w < NW && w * seg < RS;
-      const int last = min((w + 1) * seg, RS);
-      const uint32_t v = ok ? (uint32_t)sat[last * P + X] : 0u;
-      const uint32_t c = row16_inclusive_scan(v) - v;
-      if (ok && c != 0)
-        for (int r = w * seg + 1; r <= last; ++r) sat[r * P + X] = (int)((uint32_t)sat[r * P + X] + c);
-    }
+    if (m + 1 < n) load(m + 1);  // in flight during the lookups
     __syncthreads();
     if (part == 0) {
 #pragma unroll
@@ -1187,7 +1192,7 @@ bf_status_t launch_reduced(const DevTables *dev, const DevTables &host, const Ge
   const int te = reduced_tile(host);
   if (te == 0 || host.n_quads > 12 || host.n_single != 0) return BF_ERR_UNSUPPORTED;
   const int RS = te - 1 + host.tap_dy_max - host.tap_dy_min;
-  const size_t lds = (size_t)(RS + 1) * kZPitch * 4;
+  const size_t lds = (size_t)(RS + 1 + 512 / 64) * kZPitch * 4;  // table and the waves' column totals
   _Float16 *img = static_cast<_Float16 *>(ws);
   const long long npx = (long long)g.H * g.W;
   profile_mark(0, 1, stream);
