@@ -744,11 +744,10 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   const int cx0 = min(max(tx0 + tab->tap_dx_min, 0), W), cx1 = min(max(tx0 + kZTile - 1 + tab->tap_dx_max, 0), W);
   const int RS = cy1 - cy0, RC = cx1 - cx0;  // source rows / columns of the region (<= 128 each)
   const int P = kZPitch;                     // table pitch in int2: every lane's two columns fit
-  int2 *carry = sat + (RS + 1) * P;          // [kZWaves][RC + 1]: table totals of the segments above
-  int *start = reinterpret_cast<int *>(carry + kZWaves * (RC + 1));  // [257]: first list slot per level
-  int *cursor = start + 257;                                          // [256]
-  int *segoff = cursor + 256;                                         // [129]: carry row of table row Y
-  int *levels = segoff + 129;                                         // [256]: the output levels present
+  int2 *tot = sat + (RS + 1) * P;            // [kZWaves][P]: column totals of each wave's segment
+  int *start = reinterpret_cast<int *>(tot + kZWaves * P);  // [257]: first list slot per level
+  int *cursor = start + 257;                                 // [256]
+  int *levels = cursor + 256;                                // [256]: the output levels present
   uint16_t *list = reinterpret_cast<uint16_t *>(levels + 256);        // [kZTile^2]: tile pixels by level
   uint8_t *lv = reinterpret_cast<uint8_t *>(sat);  // the region's levels, staged before the tables exist
   const double scale = tab->box_scale;
@@ -762,7 +761,6 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
     lv[i] = I[(long long)(cy0 + y) * W + cx0 + x];
   }
   for (int i = tid; i < 257 + 256; i += kZThreads) start[i] = 0;  // start and cursor
-  for (int Y = tid; Y <= RS; Y += kZThreads) segoff[Y] = Y == 0 ? 0 : ((Y - 1) / seg) * (RC + 1);
   if (tid < 8) mask[tid] = 0;
   __syncthreads();
   // the wave's levels in registers as byte offsets into the slab values, two
@@ -831,22 +829,49 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   fill_lut(__builtin_amdgcn_readfirstlane(levels[0]), 0);
   const int nq = tab->n_quads;
   for (int li = 0; li < nlev; ++li) {
-    __syncthreads();  // the lists, the level's slab values and the cleared tables are ready
+    __syncthreads();  // the lists, the level's slab values, the cleared tables; the last level's reads are done
     const int L = __builtin_amdgcn_readfirstlane(levels[li]);
-    // column sums down the wave's rows in registers, a row scan across the
-    // lanes per row: the table of the segment, restarted at its first row
+    // the segment's slab values in registers and their column totals; each
+    // segment's table starts from the totals of the segments above, so the
+    // column sums run down the wave's rows and one row scan per row across
+    // the lanes gives the table itself
+    uint32_t an[kZSeg], ad[kZSeg], bn[kZSeg], bd[kZSeg];
     {
       const char *lb = reinterpret_cast<const char *>(luts + 264 * (li & 1));
+      uint32_t s0n = 0, s0d = 0, s1n = 0, s1d = 0;
+#pragma unroll
+      for (int i = 0; i < kZSeg; ++i) {  // rows past the segment read the zero entry 256
+        const int2 va = *reinterpret_cast<const int2 *>(lb + (zq[i] & 0xffffu));
+        const int2 vb = *reinterpret_cast<const int2 *>(lb + (zq[i] >> 16));
+        an[i] = (uint32_t)va.x;
+        ad[i] = (uint32_t)va.y;
+        bn[i] = (uint32_t)vb.x;
+        bd[i] = (uint32_t)vb.y;
+        s0n += an[i];
+        s0d += ad[i];
+        s1n += bn[i];
+        s1d += bd[i];
+      }
+      tot[wave * P + 2 * lane] = make_int2((int)s0n, (int)s0d);
+      tot[wave * P + 2 * lane + 1] = make_int2((int)s1n, (int)s1d);
+    }
+    __syncthreads();  // the totals are in
+    {
       uint32_t c0n = 0, c0d = 0, c1n = 0, c1d = 0;
+      for (int w = 0; w < wave; ++w) {
+        const int2 ta = tot[w * P + 2 * lane], tb = tot[w * P + 2 * lane + 1];
+        c0n += (uint32_t)ta.x;
+        c0d += (uint32_t)ta.y;
+        c1n += (uint32_t)tb.x;
+        c1d += (uint32_t)tb.y;
+      }
 #pragma unroll
       for (int i = 0; i < kZSeg; ++i) {
         if (i < nrows) {  // wave-uniform
-          const int2 va = *reinterpret_cast<const int2 *>(lb + (zq[i] & 0xffffu));
-          const int2 vb = *reinterpret_cast<const int2 *>(lb + (zq[i] >> 16));
-          c0n += (uint32_t)va.x;
-          c0d += (uint32_t)va.y;
-          c1n += (uint32_t)vb.x;
-          c1d += (uint32_t)vb.y;
+          c0n += an[i];
+          c0d += ad[i];
+          c1n += bn[i];
+          c1d += bd[i];
           const uint32_t tn = c0n + c1n, td = c0d + c1d;
           const uint32_t en = wave_inclusive_scan(tn) - tn, ed = wave_inclusive_scan(td) - td;
           int2 *row = sat + (ry0 + i + 1) * P + 2 * lane + 1;  // columns past the region: padding
@@ -855,24 +880,10 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
         }
       }
     }
-    __syncthreads();
-    // carries: exclusive sums over the segments above, one 16-lane row per
-    // table column (lane w of the row: segment w); the next level's slab
-    // values go to the other buffer meanwhile
-    for (int t0 = wave * 64; t0 < 16 * (RC + 1); t0 += kZThreads) {
-      const int X = (t0 + lane) >> 4, w = lane & 15;
-      const bool ok = X <= RC && w < kZWaves;
-      int2 v = make_int2(0, 0);
-      if (ok && w * seg < RS) v = sat[min((w + 1) * seg, RS) * P + X];
-      const uint32_t in_ = row16_inclusive_scan((uint32_t)v.x), id = row16_inclusive_scan((uint32_t)v.y);
-      if (ok) carry[w * (RC + 1) + X] = make_int2((int)(in_ - (uint32_t)v.x), (int)(id - (uint32_t)v.y));
-    }
+    // the next level's slab values go to the other buffer meanwhile
     if (li + 1 < nlev) fill_lut(__builtin_amdgcn_readfirstlane(levels[li + 1]), (li + 1) & 1);
     __syncthreads();
-    auto corner = [&](int Y, int X) -> int2 {  // table entry (Y, X) of level L's slabs (row 0: zero)
-      const int2 v = sat[Y * P + X], c = carry[segoff[Y] + X];
-      return make_int2((int)((uint32_t)v.x + (uint32_t)c.x), (int)((uint32_t)v.y + (uint32_t)c.y));
-    };
+    auto corner = [&](int Y, int X) -> int2 { return sat[Y * P + X]; };  // table entry (Y, X) of level L
     // the pixels of level L, one per thread
     const int s0 = start[L], cnt = start[L + 1] - s0;
     for (int j = tid; j < cnt; j += kZThreads) {
@@ -905,9 +916,9 @@ static size_t rangebox_lds(const DevTables &host) {
   const int RC = TE - 1 + host.tap_dx_max - host.tap_dx_min;
   if (RS > kZMaxRegion || RC > kZMaxRegion) return (size_t)-1;
   const int P = kZPitch;
-  const size_t lists = (257 + 256 + 129 + 256) * 4 + TE * TE * 2;
+  const size_t lists = (257 + 256 + 256) * 4 + TE * TE * 2;
   // the staged levels (RS x RC bytes) share the bytes of the tables
-  return 2 * 264 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)(NT / 64) * (RC + 1) * 8 + lists;
+  return 2 * 264 * 8 + 32 + (size_t)(RS + 1) * P * 8 + (size_t)(NT / 64) * P * 8 + lists;
 }
 
 constexpr size_t kLdsLimit = 160 * 1024;
