@@ -16,9 +16,18 @@
 //   normalisation.
 // Batches (ka_batch, kb_batch) run the same per-image bodies over many
 //   images in one launch per kernel.
+// Other plan kinds, each one launch per image (their own launches in batches):
+//   direct_bf    Eq. BF summed directly over the window (the brute-force
+//                baseline, for small windows);
+//   kz_rangebox  the paper's own 8-bit regime: range series on [-T_r, T_r]
+//                with the range box, cube sums over the promoted intensity
+//                axis as per-level slab tables built in LDS;
+//   kr_modulate, kr_tile  reduced precision: FP16 term images, tables built
+//                in LDS per output tile.
 //
 // Layout in HBM: one workspace of int32 tables, [tile][image][row][pitch],
-// each table (tile + 2r + 1) x pitch with pitch a multiple of 64 elements.
+// each table (tile + 2r + 1) x pitch with pitch a multiple of 64 elements
+// (reduced precision: FP16 term images [table][H][W]).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
