@@ -656,3 +656,24 @@ def test_exponential_kernels_in_the_other_paths(torch_dev, mode):
     err = np.abs(out - ref).max()
     _report("exponential kernels, %s, %dx%d" % (mode, H, W), err)
     assert err <= bar
+
+
+@pytest.mark.parametrize("name", ["cfg2_1080p", "cfg3_4096", "cfg5_4096_u8"])
+def test_reduced_precision_full_size(torch_dev, name):
+    """The reduced-precision path at the workloads' own sizes: 1080p against
+    T3 on the whole image, 4096^2 against T2 on sampled pixels (borders, tile
+    seams), within the reduced bar 1e-3."""
+    bf = _bf()
+    c = CONFIGS[name]
+    I = synth.config_image(name)
+    p = bf.Plan(c["sigma_s"], c["sigma_r"], c["radius"], c["n_range"], c["n_spatial"], dtype=c["dtype"],
+                precision="reduced")
+    out = _run(torch_dev, p, I)
+    op = oracle.make_plan(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"])
+    if c["H"] * c["W"] <= 4 * 1024 * 1024:
+        err = np.abs(out - oracle.expanded_box(I, op)).max()
+    else:
+        ys, xs = _sample_pixels(c["H"], c["W"], 1500, 9)
+        err = np.abs(out[ys, xs] - oracle.expanded_brute(I, op, ys, xs)).max()
+    _report("reduced %s vs oracle" % name, err)
+    assert err <= 1e-3
