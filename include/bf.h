@@ -14,6 +14,12 @@
  * evaluated as a sum of 2-D box sums read from summed-area tables (Sec.
  * III-D, Eqs. sum_sat_2D .. sum_sat_sum_region_2D).
  *
+ * A plan selects the kernels (Gaussian or exponential, bf_kernel_t) and the
+ * way the filter is computed: the N-term expansion above (default); Eq. BF
+ * summed directly (BF_FLAG_DIRECT / _AUTO); the paper's own 8-bit regime
+ * with the range box over the 256 intensity levels (BF_FLAG_RANGE_BOX); or
+ * the expansion with FP16 term images (BF_PREC_REDUCED).
+ *
  * Conventions (all functions):
  *  - Images are row-major and contiguous (pitch = W elements), H x W, with
  *    1 <= H, W <= 32768.  Pointers named I/out/ws are DEVICE pointers.
