@@ -677,3 +677,42 @@ def test_reduced_precision_full_size(torch_dev, name):
         err = np.abs(out[ys, xs] - oracle.expanded_brute(I, op, ys, xs)).max()
     _report("reduced %s vs oracle" % name, err)
     assert err <= 1e-3
+
+
+def test_graph_replays_of_every_plan_kind(torch_dev):
+    """A batch holding every plan kind (expansion, direct summation with the
+    exponential range kernel, range-box regime, reduced precision), captured
+    once in a graph and replayed on new inputs with eager work in between:
+    every replay equals the eager single-image calls."""
+    import torch
+    bf = _bf()
+    plans = [bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8"),
+             bf.Plan(2.0, 0.1, 9, 8, 4, dtype="u8", direct=True, kernel_r="exponential"),
+             bf.Plan(8.0, 0.1, 24, 5, 6, dtype="u8", range_box=True),
+             bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8", precision="reduced")]
+    shapes = [(97, 150), (64, 77), (130, 129), (111, 96)]
+    static_in = [torch.from_numpy(synth.gen_image_u8(h, w, 4, 0.03, 300 + i)).cuda() for i, (h, w) in enumerate(shapes)]
+    outs = [torch.empty(I.shape, dtype=torch.float32, device="cuda") for I in static_in]
+    ws = torch.empty(bf.batch_workspace_size(plans, shapes), dtype=torch.uint8, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bf.filter_batch(plans, static_in, outs=outs, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bf.filter_batch(plans, static_in, outs=outs, ws=ws)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for j, I in enumerate(static_in):
+            I.copy_(torch.from_numpy(synth.gen_image_u8(I.shape[0], I.shape[1], 4, 0.03, 700 + 10 * rep + j)))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        eager = [bf.filter(p, I) for p, I in zip(plans, static_in)]
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        for j in range(len(plans)):
+            assert torch.equal(outs[j], eager[j]), (rep, j)
+        assert torch.isfinite(junk)
