@@ -119,6 +119,17 @@ typedef enum { BF_PREC_PLAIN = 0, BF_PREC_REDUCED = 1 } bf_precision_t;
  * bf_plan_info_t.range_box and .box_levels (floor(255 T_r), at most 255)
  * describe it. */
 #define BF_FLAG_RANGE_BOX 0x8u
+/* 8-bit input in the default regime (T = max(T_r, span), no range box), with
+ * the range terms folded per output level: for an output of level L every
+ * source contributes K_s W(L - Z(q)) with W(d) = sum_k a_k cos(omega_k d/255),
+ * which is the same filter as the term-by-term expansion (Eq. 1D_N_terms;
+ * only the order of the sums over k and over the boxes changes), computed by
+ * the range-box kernel with its level window open to every difference.  Cost
+ * independent of N_r, proportional to the distinct levels per output tile:
+ * faster than the term tables where N_r is large.  BF_IN_U8 only
+ * (BF_ERR_UNSUPPORTED otherwise), radius <= 48, not with DIRECT, RANGE_BOX or
+ * REDUCED (BF_ERR_INVALID_ARG).  bf_plan_info_t.level_fold says so. */
+#define BF_FLAG_LEVEL_FOLD 0x10u
 
 typedef struct {
   bf_dtype_t in_dtype;      /* input element type, default BF_IN_F32 */
@@ -206,6 +217,7 @@ typedef struct {
   int box_levels;     /* its level window half-width floor(255 T_r); -1 otherwise */
   int box_tile;       /* its output tile edge (64, or 32 where a 64 tile's region exceeds LDS) */
   int reduced;        /* 1: BF_PREC_REDUCED (FP16 term images, tables built in LDS) */
+  int level_fold;     /* 1: BF_FLAG_LEVEL_FOLD (8-bit, range terms folded per output level) */
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);

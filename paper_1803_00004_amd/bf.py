@@ -23,6 +23,7 @@ BF_FLAG_HOST_ONLY = 0x1
 BF_FLAG_DIRECT = 0x2
 BF_FLAG_DIRECT_AUTO = 0x4
 BF_FLAG_RANGE_BOX = 0x8
+BF_FLAG_LEVEL_FOLD = 0x10
 
 EXPORTED = [
     "bf_plan_create", "bf_plan_destroy", "bf_workspace_size", "bf_filter", "bf_filter_ws",
@@ -57,7 +58,8 @@ class PlanInfo(ctypes.Structure):
                 ("T_s", ctypes.c_double), ("T_r", ctypes.c_double), ("T", ctypes.c_double),
                 ("den_floor", ctypes.c_double), ("n_quads", ctypes.c_int), ("n_single", ctypes.c_int),
                 ("lookup_kernel", ctypes.c_int), ("direct", ctypes.c_int), ("range_box", ctypes.c_int),
-                ("box_levels", ctypes.c_int), ("box_tile", ctypes.c_int), ("reduced", ctypes.c_int)]
+                ("box_levels", ctypes.c_int), ("box_tile", ctypes.c_int), ("reduced", ctypes.c_int),
+                ("level_fold", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -152,12 +154,14 @@ class Plan:
 
     def __init__(self, sigma_s, sigma_r, radius=0, n_range=8, n_spatial=4, dtype="f32",
                  precision="plain", eps=0.0, span=0.0, tile=0, host_only=False, direct=False,
-                 kernel_s="gaussian", kernel_r="gaussian", range_box=False):
+                 kernel_s="gaussian", kernel_r="gaussian", range_box=False, level_fold=False):
         """direct: False (N-term expansion), True (direct summation of Eq. BF,
         BF_FLAG_DIRECT) or "auto" (direct where its cost model is lower).
         kernel_s / kernel_r: "gaussian" or "exponential" (bf_kernel_t).
         range_box: the paper's own 8-bit regime, T = T_r with the range box
-        (BF_FLAG_RANGE_BOX; dtype "u8" only)."""
+        (BF_FLAG_RANGE_BOX; dtype "u8" only).
+        level_fold: 8-bit input, the default regime with the range terms folded
+        per output level (BF_FLAG_LEVEL_FOLD; dtype "u8" only)."""
         self._h = ctypes.c_void_p()
         flags = BF_FLAG_HOST_ONLY if host_only else 0
         if direct == "auto":
@@ -166,6 +170,8 @@ class Plan:
             flags |= BF_FLAG_DIRECT
         if range_box:
             flags |= BF_FLAG_RANGE_BOX
+        if level_fold:
+            flags |= BF_FLAG_LEVEL_FOLD
         opts = _Opts(BF_IN_U8 if dtype == "u8" else BF_IN_F32,
                      BF_PREC_REDUCED if precision == "reduced" else BF_PREC_PLAIN,
                      float(eps), float(span), int(tile), flags)

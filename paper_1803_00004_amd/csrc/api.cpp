@@ -115,16 +115,22 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   if (!p) return BF_ERR_OUT_OF_MEMORY;
   // the paper's own 8-bit regime: series on [-T_r, T_r] (span 0) and the range box
   const bool range_box = (o.flags & BF_FLAG_RANGE_BOX) != 0;
-  if (range_box && (o.flags & (BF_FLAG_DIRECT | BF_FLAG_DIRECT_AUTO))) {
+  // 8-bit input, the default regime with the range terms folded per output level
+  const bool level_fold = (o.flags & BF_FLAG_LEVEL_FOLD) != 0;
+  if ((range_box || level_fold) && (o.flags & (BF_FLAG_DIRECT | BF_FLAG_DIRECT_AUTO))) {
     delete p;
     return BF_ERR_INVALID_ARG;
   }
-  if (range_box && o.in_dtype != BF_IN_U8) {
+  if (range_box && level_fold) {
+    delete p;
+    return BF_ERR_INVALID_ARG;
+  }
+  if ((range_box || level_fold) && o.in_dtype != BF_IN_U8) {
     delete p;
     return BF_ERR_UNSUPPORTED;
   }
   const bool reduced = o.precision == BF_PREC_REDUCED;
-  if (reduced && (o.flags & (BF_FLAG_DIRECT | BF_FLAG_DIRECT_AUTO | BF_FLAG_RANGE_BOX))) {
+  if (reduced && (o.flags & (BF_FLAG_DIRECT | BF_FLAG_DIRECT_AUTO | BF_FLAG_RANGE_BOX | BF_FLAG_LEVEL_FOLD))) {
     delete p;
     return BF_ERR_INVALID_ARG;
   }
@@ -254,14 +260,17 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
       return BF_ERR_UNSUPPORTED;
     }
   }
-  if (range_box) {
+  if (range_box || level_fold) {
     if (f.radius > bf::kMaxRangeBoxRadius || t.n_single != 0) {
       delete p;
       return BF_ERR_UNSUPPORTED;
     }
+    // the same kernel: level_fold opens the level window to every difference,
+    // which is the default regime's filter (T = max(T_r, span))
     t.range_box = 1;
+    t.level_fold = level_fold;
     t.direct_r = f.radius;
-    t.box_zr = (int)std::min(255.0, std::floor(255.0 * f.T_r));
+    t.box_zr = level_fold ? 255 : (int)std::min(255.0, std::floor(255.0 * f.T_r));
     // the range terms folded per level difference d = L - z (8-bit input)
     double wmax = 0.0;
     for (int d = -255; d <= 255; ++d) {
@@ -614,7 +623,8 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   info->n_quads = plan->host_tables.n_quads;
   info->lookup_kernel = bf::lookup_kernel_kind(plan->host_tables);
   info->direct = plan->host_tables.direct;
-  info->range_box = plan->host_tables.range_box;
+  info->range_box = plan->host_tables.range_box && !plan->host_tables.level_fold;
+  info->level_fold = plan->host_tables.level_fold;
   info->box_levels = plan->host_tables.range_box ? plan->host_tables.box_zr : -1;
   info->box_tile = plan->host_tables.range_box ? bf::rangebox_tile(plan->host_tables) : 0;
   info->reduced = plan->host_tables.reduced;

@@ -88,6 +88,7 @@ struct DevTables {
   double box_scale;                    // 2^q of the slab tables
   double box_w[511];                   // W(d) = sum_k a_k cos(omega_k d / 255) [|d| <= zr] at d + 255
   int reduced;                         // FP16 term images, tables built in LDS (BF_PREC_REDUCED)
+  int level_fold;                      // range_box kernel with the window open (BF_FLAG_LEVEL_FOLD)
 };
 
 // Geometry of one image under a plan: tiles of `tile` outputs with their

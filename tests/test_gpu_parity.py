@@ -716,3 +716,37 @@ def test_graph_replays_of_every_plan_kind(torch_dev):
         for j in range(len(plans)):
             assert torch.equal(outs[j], eager[j]), (rep, j)
         assert torch.isfinite(junk)
+
+
+@pytest.mark.parametrize("H,W,ss,r,ns,sr,nr", [
+    (300, 517, 3.0, 9, 4, 0.1, 8),
+    (197, 263, 8.0, 24, 6, 0.1, 16),
+    (130, 129, 16.0, 48, 8, 0.05, 32),
+    (5, 40, 2.0, 6, 4, 0.1, 8),
+    (1, 1, 2.0, 6, 4, 0.1, 8),
+])
+def test_level_fold_vs_oracle(torch_dev, H, W, ss, r, ns, sr, nr):
+    """8-bit input with the range terms folded per output level: the default
+    regime's filter (T = max(T_r, span)), against the oracle's T3."""
+    bf = _bf()
+    Z = synth.gen_image_u8(H, W, 5, 0.03, 3 * H + W)
+    p = bf.Plan(ss, sr, r, nr, ns, dtype="u8", level_fold=True)
+    assert p.info.level_fold == 1 and p.info.range_box == 0
+    out = _run(torch_dev, p, Z)
+    ref = oracle.expanded_box(Z, oracle.make_plan(ss, r, ns, sr, nr))
+    err = np.abs(out - ref).max()
+    _report("level fold %dx%d r %d N %d vs T3" % (H, W, r, nr), err)
+    assert err <= TIGHT
+
+
+def test_level_fold_4096_sampled(torch_dev):
+    bf = _bf()
+    c = CONFIGS["cfg5_4096_u8"]
+    Z = synth.config_image("cfg5_4096_u8")
+    p = bf.Plan(c["sigma_s"], c["sigma_r"], c["radius"], c["n_range"], c["n_spatial"], dtype="u8", level_fold=True)
+    out = _run(torch_dev, p, Z)
+    op = oracle.make_plan(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"])
+    ys, xs = _sample_pixels(4096, 4096, 1500, 11)
+    err = np.abs(out[ys, xs] - oracle.expanded_brute(Z, op, ys, xs)).max()
+    _report("level fold cfg5 sampled vs T2", err)
+    assert err <= TIGHT

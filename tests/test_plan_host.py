@@ -305,3 +305,18 @@ def test_reduced_precision_plan_rules():
     with pytest.raises(bf.BFError) as e:
         bf.Plan(20.0, 0.1, 60, 8, 4, precision="reduced", host_only=True)
     assert e.value.status == bf.BF_ERR_UNSUPPORTED
+
+
+def test_level_fold_plan_rules():
+    """BF_FLAG_LEVEL_FOLD: 8-bit input only, the default regime's series
+    (T = max(T_r, span)), window open to every level difference."""
+    p = bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8", level_fold=True, host_only=True)
+    assert p.info.level_fold == 1 and p.info.range_box == 0 and p.info.box_levels == 255
+    assert abs(p.info.T - 1.0) < 1e-15 and p.workspace_size(1080, 1920) == 0
+    with pytest.raises(bf.BFError) as e:
+        bf.Plan(3.0, 0.1, 9, 8, 4, dtype="f32", level_fold=True, host_only=True)
+    assert e.value.status == bf.BF_ERR_UNSUPPORTED
+    for kw in (dict(range_box=True), dict(direct=True), dict(precision="reduced")):
+        with pytest.raises(bf.BFError) as e:
+            bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8", level_fold=True, host_only=True, **kw)
+        assert e.value.status == bf.BF_ERR_INVALID_ARG
