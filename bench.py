@@ -361,6 +361,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (heuristic tiling)")
     ap.add_argument("--precision", choices=["plain", "reduced"], default="plain",
                     help="reduced: FP16 term images, tables built in LDS (single-image workloads)")
+    ap.add_argument("--level-fold", action="store_true",
+                    help="8-bit workloads: range terms folded per output level (BF_FLAG_LEVEL_FOLD)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run one device copy of MIB MiB (a reference kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -394,8 +396,11 @@ def main():
 
     t0 = time.perf_counter()
     reduced = args.precision == "reduced"
+    fold = args.level_fold
+    if fold and c["dtype"] != "u8":
+        raise SystemExit("--level-fold needs an 8-bit workload")
     plan = bf.Plan(c["sigma_s"], c["sigma_r"], c["radius"], c["n_range"], c["n_spatial"],
-                   dtype=c["dtype"], precision=args.precision)
+                   dtype=c["dtype"], precision=args.precision, level_fold=fold)
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info
     log("[bench] plan %.1f ms: %s" % (plan_ms, info.as_dict()))
@@ -405,7 +410,7 @@ def main():
     out = torch.empty((H, W), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
     tuned = None
-    if not args.no_tune and not reduced:
+    if not args.no_tune and not reduced and not fold:
         t0 = time.perf_counter()
         tuned = plan.autotune(H, W, reps=5, stream=stream)
         log("[bench] autotuner: table tile %d (%.0f ms)" % (tuned, (time.perf_counter() - t0) * 1e3))
@@ -445,7 +450,7 @@ def main():
 
     # re-filtering the same image from tables pre-computed once (lookup only)
     refilter_ms = None
-    if not reduced:
+    if not reduced and not fold:
         tables = bf.precompute(plan, I, stream=stream)
         torch.cuda.synchronize()
         start.record(stream)
@@ -466,13 +471,24 @@ def main():
     ka_bytes = px * (vb * n_img + in_b)            # write every term image or table once, read I
     kb_bytes = px * (vb * n_img + in_b + 4)        # read every one once, read I, write out
     kb_flops = px * 2.0 * n_img * info.n_taps      # one FP64 FMA per tap per table
-    kb_name = "kr_tile" if reduced else ("kb_tile" if info.lookup_kernel == 1 else "kb_lookup")
+    kb_name = "kr_tile" if reduced else "kz_rangebox" if fold else (
+        "kb_tile" if info.lookup_kernel == 1 else "kb_lookup")
     roof_names = ["kr_modulate" if reduced else "ka_sat", kb_name]
-    roof, dom = kb_roofline(k_avg, [1, 1], ka_bytes, kb_bytes, kb_flops, kb_name, roof_names[0])
-    roof["traffic"] = recorded_traffic(args.workload, roof["kernel"])
+    if fold:
+        # one kernel: integer adds of the level-slab tables it builds
+        dy, dx, _ = plan.taps()
+        adds = slab_table_adds(I_host, {"tap_dy_min": int(dy.min()), "tap_dy_max": int(dy.max()),
+                                        "tap_dx_min": int(dx.min()), "tap_dx_max": int(dx.max())}, info.box_tile)
+        tops = adds / (k_avg[1] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": tops, "peak": INT32_PEAK_TOPS, "unit": "TOP/s",
+                "frac": tops / INT32_PEAK_TOPS, "kernel": "kz_rangebox", "kernel_ms": k_avg[1],
+                "algorithmic_adds": adds, "traffic": None}
+    else:
+        roof, dom = kb_roofline(k_avg, [1, 1], ka_bytes, kb_bytes, kb_flops, kb_name, roof_names[0])
+        roof["traffic"] = recorded_traffic(args.workload, roof["kernel"])
     # the whole path against HBM: every table written once and read once, I
     # read twice, out written once (8 n_img + 2 in_b + 4 bytes per pixel)
-    path_bytes = px * (2 * vb * n_img + 2 * in_b + 4)
+    path_bytes = px * (in_b + 4) if fold else px * (2 * vb * n_img + 2 * in_b + 4)
     path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
 
     result = {
@@ -483,14 +499,16 @@ def main():
         "data": "synthetic (seeded gradient noise + step edges + Gaussian noise)",
         "config": {"workload": "%s: %dx%d %s, Gaussian sigma_s=%g r=%d, sigma_r=%g, N_r=%d, N_s=%d%s"
                    % (args.workload, W, H, c["dtype"], c["sigma_s"], c["radius"], c["sigma_r"],
-                      c["n_range"], c["n_spatial"], ", reduced precision (FP16 term images)" if reduced else ""),
-                   "precision": args.precision,
+                      c["n_range"], c["n_spatial"], ", reduced precision (FP16 term images)" if reduced else
+                      ", range terms folded per output level" if fold else ""),
+                   "precision": args.precision, "level_fold": fold,
                    "H": H, "W": W, "table_tile": tile, "autotuned": tuned is not None, "sat_shift": q,
                    "n_images": n_img, "n_taps": info.n_taps, "workspace_bytes": ws_bytes},
         "plan_ms": round(plan_ms, 2),
-        "kernel_ms": {roof_names[0]: round(k_avg[0], 5), kb_name: round(k_avg[1], 5)},
+        "kernel_ms": {kb_name: round(k_avg[1], 5)} if fold else {roof_names[0]: round(k_avg[0], 5),
+                                                                 kb_name: round(k_avg[1], 5)},
         "roofline": roof,
-        "path_hbm": {"algorithmic_bytes_per_px": 2 * vb * n_img + 2 * in_b + 4, "achieved_gbs": round(path_gbs, 1),
+        "path_hbm": {"algorithmic_bytes_per_px": path_bytes // px, "achieved_gbs": round(path_gbs, 1),
                      "frac_of_peak": round(path_gbs / HBM_PEAK_GBS, 4)},
         "refilter_from_precomputed": None if refilter_ms is None else {
             "ms": round(refilter_ms, 5), "mpix_s": round(H * W / (refilter_ms * 1e-3) / 1e6, 2)},
