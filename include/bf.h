@@ -17,8 +17,10 @@
  * A plan selects the kernels (Gaussian or exponential, bf_kernel_t) and the
  * way the filter is computed: the N-term expansion above (default); Eq. BF
  * summed directly (BF_FLAG_DIRECT / _AUTO); the paper's own 8-bit regime
- * with the range box over the 256 intensity levels (BF_FLAG_RANGE_BOX); or
- * the expansion with FP16 term images (BF_PREC_REDUCED).
+ * with the range box over the 256 intensity levels (BF_FLAG_RANGE_BOX); the
+ * expansion for 8-bit input with its range terms folded per output level
+ * (BF_FLAG_LEVEL_FOLD); or the expansion with FP16 term images
+ * (BF_PREC_REDUCED).
  *
  * Conventions (all functions):
  *  - Images are row-major and contiguous (pitch = W elements), H x W, with
