@@ -731,7 +731,7 @@ __device__ __forceinline__ uint32_t row16_inclusive_scan(uint32_t v) {
 
 template <int kZTile, int kZThreads>
 __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restrict__ I, int H, int W,
-                                                         const DevTables *__restrict__ tab,
+                                                         const DevTables *__restrict__ tab, int nsplit,
                                                          float *__restrict__ out, float *__restrict__ num_out,
                                                          float *__restrict__ den_out) {
   constexpr int kZWaves = kZThreads / 64;
@@ -748,7 +748,10 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tiles_x = (W + kZTile - 1) / kZTile;
-  const int ty0 = (blockIdx.x / tiles_x) * kZTile, tx0 = (blockIdx.x % tiles_x) * kZTile;
+  // nsplit blocks share a tile (small images): block part takes the tile's
+  // levels part, part + nsplit, ...
+  const int tile = blockIdx.x / nsplit, part = blockIdx.x - tile * nsplit;
+  const int ty0 = (tile / tiles_x) * kZTile, tx0 = (tile % tiles_x) * kZTile;
   const int cy0 = min(max(ty0 + tab->tap_dy_min, 0), H), cy1 = min(max(ty0 + kZTile - 1 + tab->tap_dy_max, 0), H);
   const int cx0 = min(max(tx0 + tab->tap_dx_min, 0), W), cx1 = min(max(tx0 + kZTile - 1 + tab->tap_dx_max, 0), W);
   const int RS = cy1 - cy0, RC = cx1 - cx0;  // source rows / columns of the region (<= 128 each)
@@ -835,9 +838,9 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
       lut[256] = make_int2(0, 0);
     }
   };
-  fill_lut(__builtin_amdgcn_readfirstlane(levels[0]), 0);
+  if (part < nlev) fill_lut(__builtin_amdgcn_readfirstlane(levels[part]), 0);
   const int nq = tab->n_quads;
-  for (int li = 0; li < nlev; ++li) {
+  for (int li = part, it = 0; li < nlev; li += nsplit, ++it) {
     __syncthreads();  // the lists, the level's slab values, the cleared tables; the last level's reads are done
     const int L = __builtin_amdgcn_readfirstlane(levels[li]);
     // the segment's slab values in registers and their column totals; each
@@ -846,7 +849,7 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
     // the lanes gives the table itself
     uint32_t an[kZSeg], ad[kZSeg], bn[kZSeg], bd[kZSeg];
     {
-      const char *lb = reinterpret_cast<const char *>(luts + 264 * (li & 1));
+      const char *lb = reinterpret_cast<const char *>(luts + 264 * (it & 1));
       uint32_t s0n = 0, s0d = 0, s1n = 0, s1d = 0;
 #pragma unroll
       for (int i = 0; i < kZSeg; ++i) {  // rows past the segment read the zero entry 256
@@ -890,7 +893,7 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
       }
     }
     // the next level's slab values go to the other buffer meanwhile
-    if (li + 1 < nlev) fill_lut(__builtin_amdgcn_readfirstlane(levels[li + 1]), (li + 1) & 1);
+    if (li + nsplit < nlev) fill_lut(__builtin_amdgcn_readfirstlane(levels[li + nsplit]), (it + 1) & 1);
     __syncthreads();
     auto corner = [&](int Y, int X) -> int2 { return sat[Y * P + X]; };  // table entry (Y, X) of level L
     // the pixels of level L, one per thread
@@ -950,17 +953,19 @@ bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const v
   const size_t lds = big ? l64 : l32;
   if (lds > kLdsLimit) return BF_ERR_UNSUPPORTED;
   const int te = big ? 64 : 32;
-  const int blocks = ((W + te - 1) / te) * ((H + te - 1) / te);
+  const int tiles = ((W + te - 1) / te) * ((H + te - 1) / te);
+  const int nsplit = std::max(1, std::min(8, 512 / tiles));  // small images: several blocks per tile
+  const int blocks = tiles * nsplit;
   const void *fn = big ? (const void *)kz_rangebox<64, 1024> : (const void *)kz_rangebox<32, 512>;
   profile_mark(1, 1, stream);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return BF_ERR_DEVICE;
   if (big)
     hipLaunchKernelGGL((kz_rangebox<64, 1024>), dim3(blocks), dim3(1024), lds, s, static_cast<const uint8_t *>(I),
-                       H, W, dev, out, num, den);
+                       H, W, dev, nsplit, out, num, den);
   else
     hipLaunchKernelGGL((kz_rangebox<32, 512>), dim3(blocks), dim3(512), lds, s, static_cast<const uint8_t *>(I),
-                       H, W, dev, out, num, den);
+                       H, W, dev, nsplit, out, num, den);
   const hipError_t e = hipGetLastError();
   profile_mark(1, 0, stream);
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
