@@ -69,6 +69,41 @@ void ref_true_bf(const double *I, int H, int W, int r, double sigma_s, double si
   }
 }
 
+/* T1 with tabulated kernels: ks holds (2r+1)^2 spatial weights,
+ * ks[(dy + r)(2r+1) + dx + r]; the range weight of a difference t is the
+ * linear interpolant of kr[i] at |t| = i step, zero past (n - 1) step. */
+static inline double kr_table(const double *kr, int n, double step, double t) {
+  const double u = fabs(t) / step;
+  if (u > (double)(n - 1)) return 0.0;
+  int i = (int)floor(u);
+  if (i >= n - 1) return kr[n - 1];
+  return kr[i] + (u - i) * (kr[i + 1] - kr[i]);
+}
+
+void ref_true_bf_tab(const double *I, int H, int W, int r, const double *ks, const double *kr, int kr_n,
+                     double kr_step, const int *ys, const int *xs, long npix, double den_floor, double *out) {
+  long n = ys ? npix : (long)H * W;
+  const int K = 2 * r + 1;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (long i = 0; i < n; ++i) {
+    int py = ys ? ys[i] : (int)(i / W), px = ys ? xs[i] : (int)(i % W);
+    double Ip = I[(long)py * W + px], num = 0.0, den = 0.0;
+    for (int dy = -r; dy <= r; ++dy) {
+      int qy = py - dy;
+      if (qy < 0 || qy >= H) continue;
+      for (int dx = -r; dx <= r; ++dx) {
+        int qx = px - dx;
+        if (qx < 0 || qx >= W) continue;
+        double Iq = I[(long)qy * W + qx];
+        double w = ks[(dy + r) * K + dx + r] * kr_table(kr, kr_n, kr_step, Ip - Iq);
+        num += w * Iq;
+        den += w;
+      }
+    }
+    out[i] = den > den_floor ? num / den : Ip;
+  }
+}
+
 /* T2: expanded form by brute force.  Ks is the (2r+1)^2 sampled spatial
  * expansion, Ks[(dy + r)(2r+1) + dx + r] = K~_s(dy, dx); the range expansion is
  * K~_r(t) = sum_k a[k] cos(omega[k] t).  num/den may be NULL. */

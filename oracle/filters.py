@@ -1,7 +1,7 @@
 """Python front end of the FP64 oracle filters (TEST INFRASTRUCTURE ONLY).
 
 T1 true_bf         : Eq. BF with the exact kernels (Gaussian or exponential),
-                     square window [-r, r]^2.
+                     square window [-r, r]^2; true_bf_tab with tabulated kernels.
 T2 expanded_brute  : Eq. BF with the N-term expansions of both kernels, direct sum.
 T3 expanded_box    : the same through the cosine shift identity (Eq. 1D_N_terms)
                      and FP64 summed-area-table box sums of the Haar rectangles
@@ -22,7 +22,8 @@ import os
 import numpy as np
 
 from . import build as _build
-from .fit import spatial_fit, spatial_fit_2d, spatial_kernel_2d, spatial_rectangles, range_fit
+from .fit import (spatial_fit, spatial_fit_2d, spatial_fit_table, spatial_kernel_2d, spatial_rectangles,
+                  range_fit, range_fit_table)
 
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -38,6 +39,8 @@ def _load():
         lib.ref_true_bf.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _ip, ctypes.c_long,
                                     ctypes.c_double, _dp]
+        lib.ref_true_bf_tab.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                                        ctypes.c_double, _ip, _ip, ctypes.c_long, ctypes.c_double, _dp]
         lib.ref_expanded_rangebox.argtypes = [ctypes.POINTER(ctypes.c_uint8), ctypes.c_int, ctypes.c_int,
                                               ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_double,
                                               _ip, _ip, ctypes.c_long, ctypes.c_double, _dp, _dp, _dp]
@@ -69,14 +72,25 @@ class Plan:
     """Both kernel expansions for one parameter set."""
 
     def __init__(self, sigma_s, radius, n_spatial, sigma_r, n_range, eps=0.01, span=1.0,
-                 kind_s="gaussian", kind_r="gaussian"):
+                 kind_s="gaussian", kind_r="gaussian", tables=None):
+        """tables = (spatial weights (2r+1) x (2r+1), range samples, range step):
+        both kernels tabulated (sigma_s, sigma_r, kind_s, kind_r, eps unused;
+        radius must match the spatial table)."""
         self.sigma_s, self.radius, self.sigma_r = sigma_s, radius, sigma_r
         self.kind_s, self.kind_r = kind_s, kind_r
-        if kind_s == "gaussian":
+        self.tables = tables
+        if tables is not None:
+            ks, kr, step = tables
+            self.kind_s = self.kind_r = "tabulated"
+            self.spatial = spatial_fit_table(ks, n_spatial)
+            assert self.spatial.radius == radius
+            self.range = range_fit_table(kr, step, n_range, span=span)
+        elif kind_s == "gaussian":
             self.spatial = spatial_fit(sigma_s, radius, n_spatial)
         else:
             self.spatial = spatial_fit_2d(spatial_kernel_2d(kind_s, sigma_s), radius, n_spatial)
-        self.range = range_fit(sigma_r, n_range, eps=eps, span=span, kernel=kind_r)
+        if tables is None:
+            self.range = range_fit(sigma_r, n_range, eps=eps, span=span, kernel=kind_r)
         self.Ks = np.ascontiguousarray(self.spatial.K, dtype=np.float64)
         self.rects = np.ascontiguousarray(spatial_rectangles(self.spatial), dtype=np.float64)
         self.a = np.ascontiguousarray(self.range.a, dtype=np.float64)
@@ -87,6 +101,12 @@ class Plan:
 
 def make_plan(sigma_s, radius, n_spatial, sigma_r, n_range, **kw):
     return Plan(sigma_s, radius, n_spatial, sigma_r, n_range, **kw)
+
+
+def make_table_plan(ks, kr, kr_step, n_spatial, n_range, span=1.0):
+    """Plan of two tabulated kernels (see Plan)."""
+    ks = np.asarray(ks, dtype=np.float64)
+    return Plan(None, (ks.shape[0] - 1) // 2, n_spatial, None, n_range, span=span, tables=(ks, kr, kr_step))
 
 
 def _pixels(H, W, ys, xs):
@@ -111,6 +131,21 @@ def true_bf(I, sigma_s, radius, sigma_r, ys=None, xs=None, den_floor=0.0, kind_s
     out = np.empty(n)
     _load().ref_true_bf(_p(I), H, W, int(radius), float(sigma_s), float(sigma_r), _KIND[kind_s],
                         _KIND[kind_r], _p(ys, _ip), _p(xs, _ip), n, float(den_floor), _p(out))
+    return out.reshape(H, W) if ys is None else out
+
+
+def true_bf_tab(I, ks, kr, kr_step, ys=None, xs=None, den_floor=0.0):
+    """T1 with tabulated kernels: spatial weights ks[dy + r, dx + r], range
+    weight the linear interpolant of kr[i] at |t| = i kr_step, zero past the
+    last sample."""
+    I = np.ascontiguousarray(to_unit(I))
+    H, W = I.shape
+    ks = np.ascontiguousarray(ks, dtype=np.float64)
+    kr = np.ascontiguousarray(kr, dtype=np.float64)
+    ys, xs, n = _pixels(H, W, ys, xs)
+    out = np.empty(n)
+    _load().ref_true_bf_tab(_p(I), H, W, (ks.shape[0] - 1) // 2, _p(ks), _p(kr), len(kr), float(kr_step),
+                            _p(ys, _ip), _p(xs, _ip), n, float(den_floor), _p(out))
     return out.reshape(H, W) if ys is None else out
 
 

@@ -13,6 +13,12 @@ It computes, in double precision and straight from the paper's definitions:
   each selected 2-D Haar function (App. A, Table VI);
 * for a kernel that is not separable (the radial exponential), the same 2-D
   coefficients from numerical integrals of K_s over the finest Haar cells;
+* tabulated kernels (the method takes arbitrary kernels, Secs. I, IV-B and VI):
+  a spatial table of weights on the integer offsets, taken as constant on the
+  unit square around each offset, whose cell integrals are exact overlap sums;
+  a range table of samples on a uniform grid, taken as linear between samples
+  and zero past the last, whose cosine coefficients are exact integrals of each
+  linear piece;
 * the truncated-cosine expansion of the range kernel (Sec. III-B, Eq.
   1D_truncated_cos; Sec. IV-C, Eq. trigonometric_N_terms) with its best N-term
   selection out of the first 20N coefficients (App. B, Table VII).
@@ -61,7 +67,7 @@ def truncation_radius(sigma, eps=0.01, kind="gaussian"):
 
 
 # ----------------------------------------------------------------------------
-# Other kernels (the method takes arbitrary kernels, Sec. I / Sec. V): the
+# Other kernels (the method takes arbitrary kernels, Secs. I, IV-B and VI): the
 # exponential exp(-|x| / sigma) in range and the radially symmetric, not
 # separable exp(-||(x, y)|| / sigma) in space.
 # ----------------------------------------------------------------------------
@@ -247,17 +253,36 @@ def cell_integrals(kernel2d, T, n_cells, sub=4, nodes=12, grading=24):
     return M
 
 
-def spatial_fit_2d(kernel2d, radius, n_spatial):
+def tabulated_cell_integrals(table, n_cells):
+    """Cell integrals (as cell_integrals) of the tabulated spatial kernel: the
+    weight table[dy + r, dx + r] on the unit square [dx - 1/2, dx + 1/2) x
+    [dy - 1/2, dy + 1/2) around each integer offset, zero outside [-T, T)^2
+    with T = r + 1/2.  A cell's integral is the sum of the weights times the
+    areas of overlap, A_y table A_x^T with A[i, d] the length of cell i's
+    interval inside offset d's."""
+    table = np.asarray(table, dtype=np.float64)
+    radius = (table.shape[0] - 1) // 2
+    T = radius + 0.5
+    h = 2.0 * T / n_cells
+    lo = -T + h * np.arange(n_cells)
+    d = np.arange(-radius, radius + 1)
+    A = np.clip(np.minimum(lo[:, None] + h, d[None, :] + 0.5) - np.maximum(lo[:, None], d[None, :] - 0.5),
+                0.0, None)
+    return A @ table @ A.T
+
+
+def spatial_fit_2d(kernel2d, radius, n_spatial, cells=None):
     """Best N_s-group Haar approximation of an arbitrary K_s on
     [-T_s, T_s)^2 (Eq. Haar_2D_coefficients without separability): every 2-D
     coefficient c_ab = <K, h_a(x) h_b(y)> / (||h_a||^2 ||h_b||^2) is a signed sum
     of integrals of K over the finest cells (every Haar function up to level J
-    is constant on them)."""
+    is constant on them).  cells: a function of the cell count giving those
+    integrals (default: quadrature of kernel2d)."""
     T = radius + 0.5
     J = max_level(T)
     fam = haar_family(T, J)
     n_cells = 2 ** (J + 1)
-    M = cell_integrals(kernel2d, T, n_cells)
+    M = cell_integrals(kernel2d, T, n_cells) if cells is None else cells(n_cells)
     centers = -T + (2.0 * T / n_cells) * (np.arange(n_cells) + 0.5)
     Hm = np.array([f.sample(centers) for f in fam])        # functions x cells, +-1 / 0
     norms = np.array([f.norm2() for f in fam])
@@ -292,6 +317,18 @@ def spatial_fit_2d(kernel2d, radius, n_spatial):
     out.selected = sel
     out.K = K
     return out
+
+
+def spatial_fit_table(table, n_spatial):
+    """spatial_fit_2d of a tabulated K_s, (2r + 1) x (2r + 1) weights indexed
+    [dy + r, dx + r]; the table must be even in dy and in dx."""
+    table = np.asarray(table, dtype=np.float64)
+    K = table.shape[0]
+    if table.ndim != 2 or table.shape[1] != K or K % 2 != 1 or K < 3:
+        raise ValueError("spatial table must be (2r + 1) x (2r + 1), r >= 1")
+    if not (np.array_equal(table, table[::-1, :]) and np.array_equal(table, table[:, ::-1])):
+        raise ValueError("spatial table must be even in dy and in dx")
+    return spatial_fit_2d(None, (K - 1) // 2, n_spatial, cells=lambda n: tabulated_cell_integrals(table, n))
 
 
 def spatial_rectangles(fit):
@@ -382,6 +419,51 @@ def range_fit(sigma_r, n_range, eps=0.01, span=1.0, kernel=None):
     ks = select_largest(a, n_range)
     out = RangeFit()
     out.sigma, out.T_r, out.T, out.M = sigma_r, T_r, T, M
+    out.a_all = a
+    out.k = np.array(ks, dtype=np.int64)
+    out.a = a[ks]
+    out.omega = np.pi * out.k / T
+    return out
+
+
+def piecewise_linear_cosine_coefficients(values, step, T, M):
+    """a_j (as cosine_coefficients) of the even function equal on [0, T] to the
+    linear interpolant of values[i] at t_i = i step and to zero past the last
+    sample (which must lie in [0, T]).  Exact per linear piece: with
+    f(t) = v0 + beta (t - t0) on [t0, t1],
+        int f(t) cos(w t) dt = [f(t) sin(w t) / w + beta cos(w t) / w^2]_{t0}^{t1},
+    the cosine difference written as -2 sin(w (t0 + t1) / 2) sin(w (t1 - t0) / 2)."""
+    v = np.asarray(values, dtype=np.float64)
+    n = len(v)
+    t0 = step * np.arange(n - 1)
+    t1 = step * np.arange(1, n)
+    v0, v1 = v[:-1], v[1:]
+    beta = (v1 - v0) / (t1 - t0)
+    a = np.empty(M)
+    a[0] = float(np.sum(0.5 * (v0 + v1) * (t1 - t0))) / T          # (1 / 2T) int_{-T}^{T} f
+    for j in range(1, M):
+        w = math.pi * j / T
+        seg = ((v1 * np.sin(w * t1) - v0 * np.sin(w * t0)) / w
+               - 2.0 * beta * np.sin(0.5 * w * (t0 + t1)) * np.sin(0.5 * w * (t1 - t0)) / (w * w))
+        a[j] = 2.0 * float(np.sum(seg)) / T                         # (1 / T) int_{-T}^{T} f cos
+    return a
+
+
+def range_fit_table(values, step, n_range, span=1.0):
+    """range_fit of a tabulated K_r: samples values[i] = K_r(i step), linear
+    between samples, zero past T_r = (n - 1) step; T = max(T_r, span)."""
+    v = np.asarray(values, dtype=np.float64)
+    if not (1 <= n_range <= 64):
+        raise ValueError("n_range must be in [1, 64]")
+    if v.ndim != 1 or len(v) < 2 or not step > 0:
+        raise ValueError("range table needs >= 2 samples and a positive step")
+    T_r = (len(v) - 1) * step
+    T = max(T_r, span)
+    M = max(20 * n_range, 2)
+    a = piecewise_linear_cosine_coefficients(v, step, T, M)
+    ks = select_largest(a, n_range)
+    out = RangeFit()
+    out.sigma, out.T_r, out.T, out.M = None, T_r, T, M
     out.a_all = a
     out.k = np.array(ks, dtype=np.int64)
     out.a = a[ks]

@@ -617,3 +617,180 @@ def test_rangebox_constant_image_is_unchanged():
     Z = np.full((9, 13), 77, dtype=np.uint8)
     p = oracle.make_plan(2.0, 6, 4, 0.1, 5, span=0.0)
     assert np.abs(oracle.expanded_rangebox(Z, p) - 77 / 255.0).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Tabulated kernels (arbitrary kernels, Secs. I, IV-B and VI): a spatial table
+# constant on unit squares, a range table linear between samples
+# ---------------------------------------------------------------------------
+def _even_table(r, seed):
+    g = np.random.default_rng(seed).uniform(0.05, 1.0, (r + 1, r + 1))
+    q = np.concatenate([g[:0:-1], g])              # rows -r .. r from |dy|
+    return np.concatenate([q[:, :0:-1], q], axis=1)
+
+
+def _fine_grid(table, n_cells, sub):
+    """The tabulated kernel sampled at the midpoints of a grid of step h / sub
+    (h = 2T / n_cells): every pixel edge and every cell edge is a grid line
+    when sub = 2r + 1, so midpoint sums of one cell are its exact integral."""
+    r = (table.shape[0] - 1) // 2
+    T = r + 0.5
+    step = 2.0 * T / (n_cells * sub)
+    mids = -T + step * (np.arange(n_cells * sub) + 0.5)
+    idx = np.floor(mids + 0.5).astype(int) + r      # the offset whose unit square holds the midpoint
+    return table[np.ix_(idx, idx)] * step * step
+
+
+@pytest.mark.parametrize("r,seed", [(1, 0), (5, 1), (9, 2), (12, 3)])
+def test_tabulated_cell_integrals_match_fine_grid(r, seed):
+    """Exact overlap sums against midpoint sums on a grid fine enough to be
+    exact for a function constant on unit squares."""
+    table = _even_table(r, seed)
+    n = 2 ** (F.max_level(r + 0.5) + 1)
+    sub = 2 * r + 1
+    fine = _fine_grid(table, n, sub).reshape(n, sub, n, sub).sum(axis=(1, 3))
+    M = F.tabulated_cell_integrals(table, n)
+    assert np.abs(M - fine).max() <= 1e-13 * table.sum()
+    assert abs(M.sum() - table.sum()) <= 1e-12 * table.sum()      # each unit square has area 1
+
+
+@pytest.mark.parametrize("r,seed", [(5, 4), (9, 5)])
+def test_tabulated_full_expansion_is_the_cell_average(r, seed):
+    """With every level group kept the Haar expansion is the projection onto
+    functions constant on the finest cells: K~_s at an offset is the mean of
+    the kernel over the cell holding it (half-open cells, by brute force)."""
+    table = _even_table(r, seed)
+    T = r + 0.5
+    J = F.max_level(T)
+    n = 2 ** (J + 1)
+    fit = F.spatial_fit_table(table, (J + 2) ** 2)
+    h = 2.0 * T / n
+    sub = 2 * r + 1
+    fine = _fine_grid(table, n, sub).reshape(n, sub, n, sub).sum(axis=(1, 3)) / (h * h)
+    cell = np.floor((np.arange(-r, r + 1) + T) / h).astype(int)
+    assert np.abs(fit.K - fine[np.ix_(cell, cell)]).max() <= 1e-12 * table.max()
+
+
+def test_tabulated_spatial_table_must_be_even():
+    t = _even_table(3, 6)
+    t[0, 1] += 0.1
+    with pytest.raises(ValueError):
+        F.spatial_fit_table(t, 4)
+
+
+@pytest.mark.parametrize("w,T", [(0.3, 1.0), (0.05, 1.0), (1.0, 1.0), (0.2, 2.5)])
+def test_piecewise_linear_coefficients_of_a_tent(w, T):
+    """Two samples (1, 0) at step w are the tent max(0, 1 - |t| / w), whose
+    Fourier cosine integral is 2 (1 - cos(omega w)) / (omega^2 w)."""
+    M = 200
+    a = F.piecewise_linear_cosine_coefficients([1.0, 0.0], w, T, M)
+    j = np.arange(1, M)
+    om = np.pi * j / T
+    ref = 2.0 * (1.0 - np.cos(om * w)) / (om * om * w) / T
+    assert abs(a[0] - 0.5 * w / T) <= 1e-15
+    assert np.abs(a[1:] - ref).max() <= 1e-14
+
+
+def test_piecewise_linear_coefficients_match_adaptive_quadrature():
+    """A random table against QUADPACK's cosine-weighted quadrature (QAWO) of
+    np.interp on each linear piece."""
+    rng = np.random.default_rng(7)
+    v = rng.uniform(0.0, 1.0, 13)
+    step, T, M = 0.06, 1.0, 60
+    a = F.piecewise_linear_cosine_coefficients(v, step, T, M)
+    tk = step * np.arange(len(v))
+    f = lambda t: np.interp(t, tk, v)
+    for j in range(M):
+        om = np.pi * j / T
+        s = sum(integrate.quad(f, tk[i], tk[i + 1], weight="cos", wvar=om, epsabs=1e-15, epsrel=1e-13)[0]
+                for i in range(len(v) - 1))
+        ref = s / T if j == 0 else 2.0 * s / T
+        assert abs(a[j] - ref) <= 1e-13, j
+
+
+def test_table_range_fit_converges_to_the_gaussian_fit():
+    """Samples of the Gaussian range kernel at step 1e-4 over [0, 1] give the
+    closed-form Gaussian fit's coefficients up to the interpolation error
+    (step^2 max|K''| / 8 = 5e-7 at sigma_r = 0.05)."""
+    sr = 0.05
+    step = 1e-4
+    t = step * np.arange(10001)
+    tab = F.range_fit_table(F.gaussian(t, sr), step, 16, span=1.0)
+    ref = F.range_fit(sr, 16, span=1.0)
+    assert tab.T == ref.T == 1.0
+    assert tab.k.tolist() == ref.k.tolist()
+    assert np.abs(tab.a - ref.a).max() <= 1e-6
+
+
+def test_tabulated_true_bf_equals_gaussian_true_bf_at_the_knots():
+    """On 8-bit images every intensity difference is a multiple of 1/255, so a
+    range table sampled at those levels and a spatial table sampled at the
+    integer offsets reproduce T1 with the Gaussian kernels."""
+    I = (synth.gen_image(23, 19, 4, 0.08, 11) * 255).round().clip(0, 255).astype(np.uint8)
+    r, ss, sr = 4, 2.0, 0.1
+    d = np.arange(-r, r + 1)
+    ks = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2 * ss * ss))
+    kr = np.exp(-(np.arange(256) / 255.0) ** 2 / (2 * sr * sr))
+    a = oracle.true_bf_tab(I, ks, kr, 1.0 / 255.0)
+    b = oracle.true_bf(I, ss, r, sr)
+    assert np.abs(a - b).max() <= 1e-12
+
+
+def test_tabulated_true_bf_interpolates_linearly():
+    """A tent range table (samples 1, 0.5, 0 at step w / 2) is linear on its
+    pieces, so T1 with it is Eq. BF with max(0, 1 - |t| / w), summed here by a
+    pure-Python double loop."""
+    I = synth.gen_image(9, 11, 3, 0.1, 12).astype(np.float64)
+    r, w = 2, 0.3
+    ks = _even_table(r, 8)
+    got = oracle.true_bf_tab(I, ks, [1.0, 0.5, 0.0], w / 2)
+    H, W = I.shape
+    for y in range(H):
+        for x in range(W):
+            num = den = 0.0
+            for dy in range(-r, r + 1):
+                for dx in range(-r, r + 1):
+                    qy, qx = y - dy, x - dx
+                    if 0 <= qy < H and 0 <= qx < W:
+                        wt = ks[dy + r, dx + r] * max(0.0, 1.0 - abs(I[y, x] - I[qy, qx]) / w)
+                        num += wt * I[qy, qx]
+                        den += wt
+            assert abs(got[y, x] - num / den) <= 1e-13
+
+
+def test_tabulated_plan_through_the_filters():
+    """A plan of two tables: T2 (direct sum) and T3 (box sums) agree, and with
+    every term kept the expansion approaches T1 with the tables."""
+    r = 6
+    ks = _even_table(r, 9)
+    kr = np.array([1.0, 0.9, 0.6, 0.35, 0.15, 0.05, 0.0])
+    I = synth.gen_image(30, 27, 4, 0.05, 13).astype(np.float64)
+    p = oracle.make_table_plan(ks, kr, 0.04, 4, 12)
+    t2 = oracle.expanded_brute(I, p)
+    t3 = oracle.expanded_box(I, p)
+    assert np.abs(t2 - t3).max() <= 1e-10
+    full = oracle.make_table_plan(ks, kr, 0.04, (F.max_level(r + 0.5) + 2) ** 2, 64)
+    t1 = oracle.true_bf_tab(I, ks, kr, 0.04)
+    # the full spatial expansion averages the table over cells of side h in [1, 2)
+    assert np.abs(oracle.expanded_box(I, full) - t1).max() < 0.05
+    # a box kernel is phi(x) phi(y) itself: one group reproduces it exactly,
+    # and what is left is the range series' truncation error
+    box = np.ones_like(ks)
+    p1 = oracle.make_table_plan(box, kr, 0.04, 1, 64)
+    assert p1.spatial.selected == [(F.PHI, F.PHI)] and np.abs(p1.Ks - 1.0).max() <= 1e-14
+    assert np.abs(oracle.expanded_box(I, p1) - oracle.true_bf_tab(I, box, kr, 0.04)).max() < 1e-3
+
+
+def test_planted_mistake_in_the_spatial_table_is_caught():
+    """Unit squares anchored at the offset instead of centred on it: the
+    fine-grid pin tells the two apart."""
+    r = 5
+    table = _even_table(r, 10)
+    n = 2 ** (F.max_level(r + 0.5) + 1)
+    T, h = r + 0.5, (2 * r + 1.0) / n
+    lo = -T + h * np.arange(n)
+    d = np.arange(-r, r + 1)
+    A = np.clip(np.minimum(lo[:, None] + h, d[None, :] + 1.0) - np.maximum(lo[:, None], d[None, :] * 1.0), 0, None)
+    shifted = A @ table @ A.T
+    fine = _fine_grid(table, n, 2 * r + 1).reshape(n, 2 * r + 1, n, 2 * r + 1).sum(axis=(1, 3))
+    assert np.abs(shifted - fine).max() > 1e-3
