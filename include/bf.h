@@ -14,7 +14,8 @@
  * evaluated as a sum of 2-D box sums read from summed-area tables (Sec.
  * III-D, Eqs. sum_sat_2D .. sum_sat_sum_region_2D).
  *
- * A plan selects the kernels (Gaussian or exponential, bf_kernel_t) and the
+ * A plan selects the kernels (Gaussian or exponential, bf_kernel_t, or
+ * tables of any symmetric kernels, bf_plan_create_tabulated) and the
  * way the filter is computed: the N-term expansion above (default); Eq. BF
  * summed directly (BF_FLAG_DIRECT / _AUTO); the paper's own 8-bit regime
  * with the range box over the 256 intensity levels (BF_FLAG_RANGE_BOX); the
@@ -68,7 +69,8 @@ typedef enum {
  *                exp(-sqrt(dx^2 + dy^2) / sigma_s), whose 2-D Haar
  *                coefficients are integrated numerically (radius <= 511);
  *                K^{-1}(eps) = sigma ln(1/eps).
- * K_s and K_r are chosen independently. */
+ * K_s and K_r are chosen independently.  Other kernels are given as tables
+ * (bf_plan_create_tabulated). */
 typedef enum { BF_KERNEL_GAUSSIAN = 0, BF_KERNEL_EXPONENTIAL = 1 } bf_kernel_t;
 
 /* Expansion sizes: n_range cosine terms (1..64) of K_r, n_spatial Haar level
@@ -155,6 +157,30 @@ typedef struct {
  * BF_ERR_DEVICE.  The plan owns its device tables until bf_plan_destroy. */
 bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, double sigma_s,
                            double sigma_r, int radius, bf_terms_t N, const bf_plan_opts_t *opts);
+
+/* Create a plan of two tabulated kernels (arbitrary kernels: Secs. I, IV-B
+ * and VI; the expansions and every kernel of the path are unchanged, only
+ * the coefficients come from the tables).  Host arrays, read during the
+ * call only (the caller keeps ownership):
+ *   K_s[(2 radius + 1)^2], row-major, K_s[(dy + radius)(2 radius + 1) + dx +
+ *     radius] = weight of offset (dy, dx); radius in [1, 511].  The kernel is
+ *     taken as constant on the unit square around each offset, so its Haar
+ *     coefficients are exact sums over the finest Haar cells.  Weights must be
+ *     finite and >= 0, the centre > 0, and the table even in dy and in dx
+ *     (bitwise equal mirrored entries).
+ *   K_r[n_r], n_r in [2, 16385]: K_r(i step_r), i = 0 .. n_r - 1, for
+ *     differences t >= 0 in the plan's intensity units ([0, 1] for uint8
+ *     input, where one level is 1/255); linear between samples, even in t,
+ *     zero past T_r = (n_r - 1) step_r.  Samples finite and >= 0, K_r(0) > 0.
+ *     The cosine coefficients are the exact integrals of the linear pieces.
+ *     The series lies on [-T, T], T = max(T_r, span) (RANGE_BOX: T = T_r).
+ * eps is not used (the tables fix both supports).  Every option and flag of
+ * bf_plan_create applies except DIRECT (BF_ERR_UNSUPPORTED: direct
+ * summation evaluates the analytic kernels only); DIRECT_AUTO never chooses
+ * it.  Errors as bf_plan_create; BF_ERR_INVALID_ARG for a NULL table or a
+ * table that breaks the rules above. */
+bf_status_t bf_plan_create_tabulated(bf_plan_t *plan, const double *K_s, int radius, const double *K_r,
+                                     int n_r, double step_r, bf_terms_t N, const bf_plan_opts_t *opts);
 
 /* Release a plan and everything it owns (waits for nothing; the caller must
  * not destroy a plan while work that uses it is in flight).  NULL is a no-op. */

@@ -26,7 +26,7 @@ BF_FLAG_RANGE_BOX = 0x8
 BF_FLAG_LEVEL_FOLD = 0x10
 
 EXPORTED = [
-    "bf_plan_create", "bf_plan_destroy", "bf_workspace_size", "bf_filter", "bf_filter_ws",
+    "bf_plan_create", "bf_plan_create_tabulated", "bf_plan_destroy", "bf_workspace_size", "bf_filter", "bf_filter_ws",
     "bf_filter_parts", "bf_batch_workspace_size", "bf_filter_batch", "bf_plan_query",
     "bf_image_geometry", "bf_plan_range_terms", "bf_plan_spatial_kernel", "bf_plan_taps", "bf_plan_spatial_groups",
     "bf_profile_enable", "bf_profile_read", "bf_status_string", "bf_version",
@@ -79,6 +79,7 @@ def lib():
         vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
         ip, dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
         L.bf_plan_create.argtypes = [ctypes.POINTER(vp), i, i, d, d, i, _Terms, ctypes.POINTER(_Opts)]
+        L.bf_plan_create_tabulated.argtypes = [ctypes.POINTER(vp), dp, i, dp, i, d, _Terms, ctypes.POINTER(_Opts)]
         L.bf_plan_destroy.argtypes = [vp]
         L.bf_workspace_size.argtypes = [vp, i, i, ctypes.POINTER(sz)]
         L.bf_filter.argtypes = [vp, vp, vp, i, i, vp]
@@ -154,10 +155,13 @@ class Plan:
 
     def __init__(self, sigma_s, sigma_r, radius=0, n_range=8, n_spatial=4, dtype="f32",
                  precision="plain", eps=0.0, span=0.0, tile=0, host_only=False, direct=False,
-                 kernel_s="gaussian", kernel_r="gaussian", range_box=False, level_fold=False):
+                 kernel_s="gaussian", kernel_r="gaussian", range_box=False, level_fold=False, tables=None):
         """direct: False (N-term expansion), True (direct summation of Eq. BF,
         BF_FLAG_DIRECT) or "auto" (direct where its cost model is lower).
         kernel_s / kernel_r: "gaussian" or "exponential" (bf_kernel_t).
+        tables: (K_s weights (2r+1) x (2r+1), K_r samples, sample step) for
+        bf_plan_create_tabulated (sigma_s, sigma_r, radius, kernel_s / _r and
+        eps are then unused); see Plan.tabulated.
         range_box: the paper's own 8-bit regime, T = T_r with the range box
         (BF_FLAG_RANGE_BOX; dtype "u8" only).
         level_fold: 8-bit input, the default regime with the range terms folded
@@ -175,12 +179,30 @@ class Plan:
         opts = _Opts(BF_IN_U8 if dtype == "u8" else BF_IN_F32,
                      BF_PREC_REDUCED if precision == "reduced" else BF_PREC_PLAIN,
                      float(eps), float(span), int(tile), flags)
-        st = lib().bf_plan_create(ctypes.byref(self._h), KERNELS[kernel_s], KERNELS[kernel_r],
-                                  float(sigma_s), float(sigma_r), int(radius),
-                                  _Terms(int(n_range), int(n_spatial)), ctypes.byref(opts))
-        _check(st, "bf_plan_create")
+        if tables is not None:
+            ks = np.ascontiguousarray(tables[0], dtype=np.float64)
+            kr = np.ascontiguousarray(tables[1], dtype=np.float64)
+            if ks.ndim != 2 or ks.shape[0] != ks.shape[1] or ks.shape[0] % 2 != 1 or kr.ndim != 1:
+                raise ValueError("tables: K_s must be (2r+1) x (2r+1), K_r one-dimensional")
+            dp = ctypes.POINTER(ctypes.c_double)
+            st = lib().bf_plan_create_tabulated(ctypes.byref(self._h), ks.ctypes.data_as(dp),
+                                                (ks.shape[0] - 1) // 2, kr.ctypes.data_as(dp), len(kr),
+                                                float(tables[2]), _Terms(int(n_range), int(n_spatial)),
+                                                ctypes.byref(opts))
+            _check(st, "bf_plan_create_tabulated")
+        else:
+            st = lib().bf_plan_create(ctypes.byref(self._h), KERNELS[kernel_s], KERNELS[kernel_r],
+                                      float(sigma_s), float(sigma_r), int(radius),
+                                      _Terms(int(n_range), int(n_spatial)), ctypes.byref(opts))
+            _check(st, "bf_plan_create")
         self.dtype = dtype
         self.info = self.query()
+
+    @classmethod
+    def tabulated(cls, ks, kr, kr_step, n_range=8, n_spatial=4, **kw):
+        """A plan of two tabulated kernels (bf_plan_create_tabulated): K_s
+        weights on the integer offsets, K_r samples at multiples of kr_step."""
+        return cls(0.0, 0.0, n_range=n_range, n_spatial=n_spatial, tables=(ks, kr, kr_step), **kw)
 
     @property
     def handle(self):

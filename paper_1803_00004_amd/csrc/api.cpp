@@ -89,6 +89,10 @@ bf_status_t check_image(const bf_plan_s *p, const void *I, const float *out, int
   return BF_OK;
 }
 
+// Fit, compile and upload a plan of the given kernels (both creation calls).
+bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, const bf_plan_opts_t *opts,
+                        bf_plan_t *plan);
+
 }  // namespace
 
 extern "C" {
@@ -102,6 +106,33 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
     if ((int)K_s < 0 || (int)K_r < 0) return BF_ERR_INVALID_ARG;
     return BF_ERR_UNSUPPORTED;
   }
+  bf::KernelSpec kern;
+  kern.kind_s = (int)K_s;
+  kern.kind_r = (int)K_r;
+  kern.sigma_s = sigma_s;
+  kern.sigma_r = sigma_r;
+  return create_plan(kern, radius, N, opts, plan);
+}
+
+bf_status_t bf_plan_create_tabulated(bf_plan_t *plan, const double *K_s, int radius, const double *K_r,
+                                     int n_r, double step_r, bf_terms_t N, const bf_plan_opts_t *opts) {
+  if (!plan) return BF_ERR_INVALID_ARG;
+  *plan = nullptr;
+  if (!K_s || !K_r || radius < 1) return BF_ERR_INVALID_ARG;
+  bf::KernelSpec kern;
+  kern.ks = K_s;
+  kern.kr = K_r;
+  kern.kr_n = n_r;
+  kern.kr_step = step_r;
+  return create_plan(kern, radius, N, opts, plan);
+}
+
+}  // extern "C"
+
+namespace {
+
+bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, const bf_plan_opts_t *opts,
+                        bf_plan_t *plan) {
   bf_plan_opts_t o{};
   if (opts) o = *opts;
   if (o.in_dtype != BF_IN_F32 && o.in_dtype != BF_IN_U8) return BF_ERR_INVALID_ARG;
@@ -134,7 +165,12 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
     delete p;
     return BF_ERR_INVALID_ARG;
   }
-  bf_status_t st = bf::fit_plan((int)K_s, (int)K_r, sigma_s, sigma_r, radius, N, eps, range_box ? 0.0 : span, &p->fit);
+  const bool tabulated = kern.ks || kern.kr;
+  if (tabulated && (o.flags & BF_FLAG_DIRECT)) {  // direct summation evaluates analytic kernels only
+    delete p;
+    return BF_ERR_UNSUPPORTED;
+  }
+  bf_status_t st = bf::fit_plan(kern, radius, N, eps, range_box ? 0.0 : span, &p->fit);
   if (st != BF_OK) {
     delete p;
     return st;
@@ -289,7 +325,7 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
     t.box_scale = std::ldexp(1.0, q);
   }
   bool direct = (o.flags & BF_FLAG_DIRECT) != 0;
-  if (!direct && (o.flags & BF_FLAG_DIRECT_AUTO) && f.radius <= bf::kMaxDirectRadius) {
+  if (!direct && !tabulated && (o.flags & BF_FLAG_DIRECT_AUTO) && f.radius <= bf::kMaxDirectRadius) {
     const double e = (double)(2 * f.radius + 1) * (2 * f.radius + 1);
     const double expansion = (1700.0 + t.n_images * (85.0 + 10.0 * (t.n_quads + t.n_single))) * (1.0 + f.radius / 120.0);
     direct = 8.5 * e < expansion;
@@ -305,14 +341,16 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
     for (int dy = -r; dy <= r; ++dy)
       for (int dx = -r; dx <= r; ++dx)
         ks[(size_t)(dy + r) * K + dx + r] =
-            (float)(K_s == BF_KERNEL_EXPONENTIAL ? std::exp(-std::sqrt((double)(dx * dx + dy * dy)) / sigma_s)
-                                                 : std::exp(-(dx * dx + dy * dy) / (2.0 * sigma_s * sigma_s)));
+            (float)(kern.kind_s == BF_KERNEL_EXPONENTIAL
+                        ? std::exp(-std::sqrt((double)(dx * dx + dy * dy)) / kern.sigma_s)
+                        : std::exp(-(dx * dx + dy * dy) / (2.0 * kern.sigma_s * kern.sigma_s)));
     t.direct = 1;
     t.direct_r = r;
     // K_r(d) = 2^(c d^2) (Gaussian) or 2^(c |d|) (exponential)
     const double log2e = 1.4426950408889634;
-    t.direct_abs = K_r == BF_KERNEL_EXPONENTIAL;
-    double c = t.direct_abs ? -log2e / sigma_r : -log2e / (2.0 * sigma_r * sigma_r);
+    t.direct_abs = kern.kind_r == BF_KERNEL_EXPONENTIAL;
+    const double sr = kern.sigma_r;
+    double c = t.direct_abs ? -log2e / sr : -log2e / (2.0 * sr * sr);
     if (o.in_dtype == BF_IN_U8) c /= t.direct_abs ? 255.0 : 255.0 * 255.0;  // differences in bytes
     t.direct_c = (float)c;
   }
@@ -350,6 +388,10 @@ bf_status_t bf_plan_create(bf_plan_t *plan, bf_kernel_t K_s, bf_kernel_t K_r, do
   *plan = p;
   return BF_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 bf_status_t bf_plan_destroy(bf_plan_t plan) {
   if (!plan) return BF_OK;

@@ -39,9 +39,23 @@ struct Fit {
   std::vector<double> a, omega;
 };
 
-// Fit both expansions; returns BF_OK or BF_ERR_INVALID_ARG.
-bf_status_t fit_plan(int kind_s, int kind_r, double sigma_s, double sigma_r, int radius,
-                     bf_terms_t N, double eps, double span, Fit *out);
+// The two kernels of a plan: analytic kinds (bf_kernel_t) with their sigmas,
+// or tables.  A spatial table holds (2r + 1)^2 weights, ks[(dy + r)(2r + 1) +
+// dx + r], taken as constant on the unit square around each integer offset; a
+// range table holds kr_n samples K_r(i kr_step), taken as linear between
+// samples and zero past the last.
+struct KernelSpec {
+  int kind_s = BF_KERNEL_GAUSSIAN, kind_r = BF_KERNEL_GAUSSIAN;
+  double sigma_s = 0, sigma_r = 0;
+  const double *ks = nullptr;  // tabulated K_s, or null
+  const double *kr = nullptr;  // tabulated K_r, or null
+  int kr_n = 0;
+  double kr_step = 0;
+};
+constexpr int kMaxRangeSamples = 16385;
+
+// Fit both expansions; returns BF_OK, BF_ERR_INVALID_ARG or BF_ERR_UNSUPPORTED.
+bf_status_t fit_plan(const KernelSpec &kern, int radius, bf_terms_t N, double eps, double span, Fit *out);
 
 // Device-side constant tables of a plan (one upload per plan).
 struct DevTables {

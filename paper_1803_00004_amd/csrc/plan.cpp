@@ -10,12 +10,15 @@
 //  * Taps: the sampled kernel is piecewise constant on rectangles (App. A,
 //    Table VI); its mixed second differences give the corners at which the
 //    four-reference box sums of Eq. sum_sat_sum_region_2D read the table.
-//    Other kernels (Sec. I: the expansion takes any symmetric kernel): the
-//    radial exponential exp(-||d|| / sigma_s), which is not separable, gets
-//    its 2-D coefficients from integrals over the finest Haar cells.
+//    Other kernels (Secs. I, IV-B and VI: the expansion takes any symmetric
+//    kernel): the radial exponential exp(-||d|| / sigma_s), which is not
+//    separable, and tabulated kernels get their 2-D coefficients from
+//    integrals over the finest Haar cells -- by quadrature for the exponential,
+//    as exact overlap sums for a table (constant on unit squares).
 //  * Range: best N-term truncated cosine approximation (Sec. III-B, Eq.
 //    1D_truncated_cos; Sec. IV-C, Eq. trigonometric_N_terms), coefficients by
-//    composite Gauss-Legendre quadrature, the N largest |a_k| among the first
+//    composite Gauss-Legendre quadrature (in closed form for a table, linear
+//    between samples), the N largest |a_k| among the first
 //    20N (App. B), on [-T, T] with T = max(T_r, span) so that every intensity
 //    difference lies inside the series interval.
 #include <algorithm>
@@ -162,17 +165,122 @@ void quadrant_cell_integrals(int kind, double sigma, double h, int n, std::vecto
   (*Q)[0] = s;
 }
 
+// Cells of the quadrant (as above) for a tabulated K_s: weight ks(dy, dx) on
+// the unit square [dx - 1/2, dx + 1/2) x [dy - 1/2, dy + 1/2).  A cell's
+// integral is the sum over the squares it meets of weight times overlap
+// area; the cell side h = (2r + 1) / 2^(J+1) and the square edges are exact
+// binary fractions, so every overlap length is exact.
+void tabulated_quadrant_cells(const double *ks, int r, double h, int n, std::vector<double> *Q) {
+  const int K = 2 * r + 1;
+  struct Span { int d; double len; };
+  std::vector<std::vector<Span>> ov(n);  // per cell: offsets d >= 0 met, with the overlap length
+  for (int i = 0; i < n; ++i) {
+    const double lo = i * h, hi = (i + 1) * h;
+    for (int d = std::max(0, (int)std::floor(lo - 0.5)); d <= r && d - 0.5 < hi; ++d) {
+      const double len = std::min(hi, d + 0.5) - std::max(lo, d - 0.5);
+      if (len > 0) ov[i].push_back({d, len});
+    }
+  }
+  Q->assign((size_t)n * n, 0.0);
+  for (int jy = 0; jy < n; ++jy)
+    for (int ix = 0; ix < n; ++ix) {
+      double s = 0.0;
+      for (const Span &a : ov[jy]) {
+        double row = 0.0;
+        for (const Span &b : ov[ix]) row += b.len * ks[(size_t)(a.d + r) * K + b.d + r];
+        s += a.len * row;
+      }
+      (*Q)[(size_t)jy * n + ix] = s;
+    }
+}
+
+// Checks of a tabulated kernel: finite, non-negative weights, a positive
+// centre, and a spatial table even in dy and in dx (bitwise).
+bool valid_tables(const KernelSpec &k, int radius) {
+  if (k.ks) {
+    const int K = 2 * radius + 1;
+    const double *t = k.ks;
+    for (int i = 0; i < K * K; ++i)
+      if (!std::isfinite(t[i]) || t[i] < 0) return false;
+    if (!(t[(size_t)radius * K + radius] > 0)) return false;
+    for (int y = 0; y < K; ++y)
+      for (int x = 0; x < K; ++x) {
+        const double v = t[(size_t)y * K + x];
+        if (v != t[(size_t)(K - 1 - y) * K + x] || v != t[(size_t)y * K + K - 1 - x]) return false;
+      }
+  }
+  if (k.kr) {
+    if (k.kr_n < 2 || k.kr_n > kMaxRangeSamples || !(k.kr_step > 0) || !std::isfinite(k.kr_step)) return false;
+    for (int i = 0; i < k.kr_n; ++i)
+      if (!std::isfinite(k.kr[i]) || k.kr[i] < 0) return false;
+    if (!(k.kr[0] > 0)) return false;
+  }
+  return true;
+}
+
+// a_j (j < M) of the even function equal on [0, T] to the linear interpolant
+// of v_i = K_r(i s) and zero past t_{n-1} <= T.  On a piece [t_i, t_i + s]
+// with slope beta_i, integration by parts gives
+// [f sin(w t) / w + beta_i cos(w t) / w^2]; the first part telescopes over the
+// pieces to v_{n-1} sin(w t_{n-1}) / w (sin 0 = 0), and each cosine
+// difference is -2 sin(w (t_i + s/2)) sin(w s / 2).
+void table_cosine_coefficients(const double *v, int n, double s, double T, int M, std::vector<double> *a) {
+  a->assign(M, 0.0);
+  double area = 0.0;
+  for (int i = 0; i + 1 < n; ++i) area += 0.5 * (v[i] + v[i + 1]) * s;
+  (*a)[0] = area / T;
+  const double tl = (n - 1) * s;
+  for (int j = 1; j < M; ++j) {
+    const double w = kPi * j / T;
+    double acc = 0.0;
+    for (int i = 0; i + 1 < n; ++i) acc += (v[i + 1] - v[i]) / s * std::sin(w * (i * s + 0.5 * s));
+    const double integral = v[n - 1] * std::sin(w * tl) / w - 2.0 * std::sin(0.5 * w * s) * acc / (w * w);
+    (*a)[j] = 2.0 * integral / T;
+  }
+}
+
+// a_j (j < M) of an analytic K_r on [-T, T] by composite 16-point
+// Gauss-Legendre quadrature: 4 panels per period of the highest frequency, at
+// least 256.
+void kernel_cosine_coefficients(int kind, double sigma, double T, int M, std::vector<double> *a) {
+  const int panels = std::max(256, 4 * M);
+  std::vector<double> gx, gw;
+  gauss_legendre(16, &gx, &gw);
+  std::vector<double> t, fw;
+  t.reserve((size_t)panels * 16);
+  fw.reserve((size_t)panels * 16);
+  const double h = 2.0 * T / panels;
+  for (int p = 0; p < panels; ++p) {
+    const double lo = -T + p * h;
+    for (int i = 0; i < 16; ++i) {
+      const double tt = lo + 0.5 * h * (gx[i] + 1.0);
+      t.push_back(tt);
+      fw.push_back(0.5 * h * gw[i] * range_profile(kind, tt, sigma));
+    }
+  }
+  a->assign(M, 0.0);
+  for (int j = 0; j < M; ++j) {
+    double s = 0.0;
+    const double w = kPi * j / T;
+    for (size_t i = 0; i < t.size(); ++i) s += std::cos(w * t[i]) * fw[i];
+    (*a)[j] = (j == 0 ? 0.5 : 1.0) * s / T;
+  }
+}
+
 }  // namespace
 
-bf_status_t fit_plan(int kind_s, int kind_r, double sigma_s, double sigma_r, int radius,
-                     bf_terms_t N, double eps, double span, Fit *out) {
-  if (!(sigma_s > 0) || !std::isfinite(sigma_s) || !(sigma_r > 0) || !std::isfinite(sigma_r) ||
-      !(eps > 0 && eps < 1) || !(span >= 0) || !std::isfinite(span))
+bf_status_t fit_plan(const KernelSpec &kern, int radius, bf_terms_t N, double eps, double span, Fit *out) {
+  const int kind_s = kern.ks ? -1 : kern.kind_s, kind_r = kern.kr ? -1 : kern.kind_r;
+  const double sigma_s = kern.sigma_s, sigma_r = kern.sigma_r;
+  if ((!kern.ks && (!(sigma_s > 0) || !std::isfinite(sigma_s))) ||
+      (!kern.kr && (!(sigma_r > 0) || !std::isfinite(sigma_r))) || !(eps > 0 && eps < 1) || !(span >= 0) ||
+      !std::isfinite(span))
     return BF_ERR_INVALID_ARG;
-  if (radius == 0) radius = (int)std::ceil(kernel_inverse(kind_s, sigma_s, eps));
+  if (radius == 0 && !kern.ks) radius = (int)std::ceil(kernel_inverse(kind_s, sigma_s, eps));
   if (radius < 1 || radius > 1024) return BF_ERR_INVALID_ARG;
   // the cell integrals of a non-separable kernel cost O((2^J)^2) evaluations
   if (kind_s != BF_KERNEL_GAUSSIAN && radius > kMaxCellFitRadius) return BF_ERR_UNSUPPORTED;
+  if (!valid_tables(kern, radius)) return BF_ERR_INVALID_ARG;
   if (N.n_range < 1 || N.n_range > kMaxTerms) return BF_ERR_INVALID_ARG;
 
   Fit f;
@@ -240,7 +348,10 @@ bf_status_t fit_plan(int kind_s, int kind_r, double sigma_s, double sigma_r, int
     const int n = 1 << (J + 1), n2 = n / 2, E = J + 2;  // block exponents e = 0 .. J + 1
     const double h = 2.0 * T / n;
     std::vector<double> Q;
-    quadrant_cell_integrals(kind_s, sigma_s, h, n2, &Q);  // kernel even in x and in y
+    if (kern.ks)  // kernel even in x and in y
+      tabulated_quadrant_cells(kern.ks, radius, h, n2, &Q);
+    else
+      quadrant_cell_integrals(kind_s, sigma_s, h, n2, &Q);
     // X[ex]: n rows x 2^ex column blocks; B[ex][ey]: 2^ey x 2^ex blocks
     std::vector<std::vector<double>> X(E);
     X[E - 1].resize((size_t)n * n);
@@ -369,31 +480,14 @@ bf_status_t fit_plan(int kind_s, int kind_r, double sigma_s, double sigma_r, int
   }
 
   // ---------------- range ----------------
-  f.T_r = kernel_inverse(kind_r, sigma_r, eps);
+  f.T_r = kern.kr ? (kern.kr_n - 1) * kern.kr_step : kernel_inverse(kind_r, sigma_r, eps);
   f.T = std::max(f.T_r, span);
   const int M = std::max(20 * N.n_range, 2);
-  const int panels = std::max(256, 4 * M);
-  std::vector<double> gx, gw;
-  gauss_legendre(16, &gx, &gw);
-  std::vector<double> t, fw;
-  t.reserve((size_t)panels * 16);
-  fw.reserve((size_t)panels * 16);
-  const double h = 2.0 * f.T / panels;
-  for (int p = 0; p < panels; ++p) {
-    const double lo = -f.T + p * h;
-    for (int i = 0; i < 16; ++i) {
-      const double tt = lo + 0.5 * h * (gx[i] + 1.0);
-      t.push_back(tt);
-      fw.push_back(0.5 * h * gw[i] * range_profile(kind_r, tt, sigma_r));
-    }
-  }
-  std::vector<double> a(M);
-  for (int j = 0; j < M; ++j) {
-    double s = 0.0;
-    const double w = kPi * j / f.T;
-    for (size_t i = 0; i < t.size(); ++i) s += std::cos(w * t[i]) * fw[i];
-    a[j] = (j == 0 ? 0.5 : 1.0) * s / f.T;
-  }
+  std::vector<double> a;
+  if (kern.kr)
+    table_cosine_coefficients(kern.kr, kern.kr_n, kern.kr_step, f.T, M, &a);
+  else
+    kernel_cosine_coefficients(kind_r, sigma_r, f.T, M, &a);
   double amax = 0;
   for (double v : a) amax = std::max(amax, std::fabs(v));
   std::vector<double> q(M);

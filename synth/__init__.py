@@ -5,9 +5,11 @@ This module holds no arithmetic of the filtering method: it only draws images
 natural photographs (Lena, Barbara, Boat, an HDR scene) that are not available
 here; these fields stand in for them: smooth multi-octave gradient noise for
 the low-frequency content, straight step edges for the structures a bilateral
-filter must preserve, and Gaussian sensor noise.
+filter must preserve, and Gaussian sensor noise.  kernels.py holds sampled
+kernel shapes for the plans of tabulated kernels.
 """
 from .images import gen_image, gen_image_u8, config_image
 from .stream import gen_stream
+from . import kernels
 
-__all__ = ["gen_image", "gen_image_u8", "config_image", "gen_stream"]
+__all__ = ["gen_image", "gen_image_u8", "config_image", "gen_stream", "kernels"]

@@ -750,3 +750,73 @@ def test_level_fold_4096_sampled(torch_dev):
     err = np.abs(out[ys, xs] - oracle.expanded_brute(Z, op, ys, xs)).max()
     _report("level fold cfg5 sampled vs T2", err)
     assert err <= TIGHT
+
+
+def _table_cases():
+    K = synth.kernels
+    return {
+        "cauchy r9 tukey u8": (300, 517, K.cauchy_spatial(9, 3.0), K.tukey_range(0.2, 1 / 255.0), 1 / 255.0, 6, 8, "u8"),
+        "gauss r24 cauchy f32": (197, 263, K.gaussian_spatial(24, 8.0), K.cauchy_range(0.05, 0.005, 201), 0.005, 6,
+                                 16, "f32"),
+        "cauchy r48 tukey f32": (130, 129, K.cauchy_spatial(48, 10.0), K.tukey_range(0.3, 0.01), 0.01, 8, 32, "f32"),
+        "cauchy r3 cauchy f32": (5, 33, K.cauchy_spatial(3, 1.0), K.cauchy_range(0.1, 0.01, 101), 0.01, 4, 8, "f32"),
+    }
+
+
+@pytest.mark.parametrize("name", ["cauchy r9 tukey u8", "gauss r24 cauchy f32", "cauchy r48 tukey f32",
+                                  "cauchy r3 cauchy f32"])
+def test_tabulated_kernels_vs_oracle(torch_dev, name):
+    """Tabulated kernels change only the fitted coefficients: the same kernels
+    filter them, against the oracle's T3 for the same tables."""
+    bf = _bf()
+    H, W, ks, kr, step, ns, nr, dtype = _table_cases()[name]
+    I = synth.gen_image_u8(H, W, 5, 0.03, H + 5 * W) if dtype == "u8" else synth.gen_image(H, W, 5, 0.03, H + 5 * W)
+    p = bf.Plan.tabulated(ks, kr, step, n_range=nr, n_spatial=ns, dtype=dtype)
+    o = oracle.make_table_plan(ks, kr, step, ns, nr)
+    out = _run(torch_dev, p, I)
+    err = np.abs(out - oracle.expanded_box(I, o)).max()
+    _report("tabulated %s %dx%d vs T3" % (name, H, W), err)
+    _report("  same vs true BF with the tables (reported)",
+            np.abs(out - oracle.true_bf_tab(I, ks, kr, step)).max())
+    assert err <= TIGHT
+
+
+@pytest.mark.parametrize("mode", ["range_box", "level_fold", "reduced", "batch"])
+def test_tabulated_kernels_in_the_other_paths(torch_dev, mode):
+    """A tabulated kernel pair through the range-box regime (against T4), the
+    level fold and the reduced-precision path (against T3), and a batch mixed
+    with Gaussian plans (bitwise the single-image results)."""
+    import torch
+    bf = _bf()
+    K = synth.kernels
+    H, W = 150, 211
+    Z = synth.gen_image_u8(H, W, 5, 0.03, 43)
+    ks, kr, step = K.cauchy_spatial(12, 4.0), K.tukey_range(0.2, 1 / 255.0), 1 / 255.0
+    if mode == "batch":
+        pt = bf.Plan.tabulated(ks, kr, step, n_range=12, n_spatial=6, dtype="u8")
+        pg = bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8")
+        imgs = [torch.from_numpy(synth.gen_image_u8(h, w, 4, 0.03, h * w)).cuda() for h, w in ((120, 333), (77, 64),
+                                                                                               (256, 256))]
+        plans = [pt, pg, pt]
+        singles = [bf.filter(p, I).clone() for p, I in zip(plans, imgs)]
+        outs = bf.filter_batch(plans, imgs)
+        torch.cuda.synchronize()
+        for o, s in zip(outs, singles):
+            assert torch.equal(o, s)
+        return
+    if mode == "range_box":
+        p = bf.Plan.tabulated(ks, kr, step, n_range=5, n_spatial=6, dtype="u8", range_box=True)
+        ref = oracle.expanded_rangebox(Z, oracle.make_table_plan(ks, kr, step, 6, 5, span=0.0))
+        bar = TIGHT
+    elif mode == "level_fold":
+        p = bf.Plan.tabulated(ks, kr, step, n_range=12, n_spatial=6, dtype="u8", level_fold=True)
+        ref = oracle.expanded_box(Z, oracle.make_table_plan(ks, kr, step, 6, 12))
+        bar = TIGHT
+    else:
+        p = bf.Plan.tabulated(ks, kr, step, n_range=12, n_spatial=6, dtype="u8", precision="reduced")
+        ref = oracle.expanded_box(Z, oracle.make_table_plan(ks, kr, step, 6, 12))
+        bar = 1e-3
+    out = _run(torch_dev, p, Z)
+    err = np.abs(out - ref).max()
+    _report("tabulated kernels, %s, %dx%d" % (mode, H, W), err)
+    assert err <= bar

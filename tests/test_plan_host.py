@@ -320,3 +320,100 @@ def test_level_fold_plan_rules():
         with pytest.raises(bf.BFError) as e:
             bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8", level_fold=True, host_only=True, **kw)
         assert e.value.status == bf.BF_ERR_INVALID_ARG
+
+
+def _table_cases():
+    K = synth.kernels
+    return [
+        (K.cauchy_spatial(9, 3.0), K.tukey_range(0.2, 1 / 255.0), 1 / 255.0, 6, 8),
+        (K.gaussian_spatial(24, 8.0), K.cauchy_range(0.05, 0.005, 201), 0.005, 6, 16),
+        (K.cauchy_spatial(48, 10.0), K.tukey_range(0.3, 0.01), 0.01, 8, 32),
+        (K.cauchy_spatial(3, 1.0), K.cauchy_range(0.1, 0.01, 101), 0.01, 4, 8),
+    ]
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_tabulated_kernels_match_oracle(case):
+    """Tabulated kernels: the library's exact cell sums and closed-form cosine
+    coefficients against the oracle's (exact overlap matrices, per-piece
+    integrals), and the compiled taps against the oracle's rectangles."""
+    ks, kr, step, ns, nr = _table_cases()[case]
+    p = bf.Plan.tabulated(ks, kr, step, n_range=nr, n_spatial=ns, host_only=True)
+    o = oracle.make_table_plan(ks, kr, step, ns, nr)
+    assert p.spatial_groups() == o.spatial.selected
+    assert np.abs(p.spatial_kernel() - o.Ks).max() <= 1e-13 * np.abs(o.Ks).max()
+    k, a, w = p.range_terms()
+    assert k.tolist() == o.range.k.tolist()
+    assert np.abs(a - o.a).max() <= 1e-13
+    assert np.abs(w - o.omega).max() <= 1e-12
+    info = p.info
+    assert info.T_r == o.range.T_r and info.T == o.range.T
+    assert info.radius == (ks.shape[0] - 1) // 2
+    assert info.n_single == 0 and 4 * info.n_quads == info.n_taps
+    dy, dx, tw = p.taps()
+    g = synth.gen_image(40, 37, 4, 0.05, 3).astype(np.float64) - 0.3
+    S = _excl_sat(g)
+    ys, xs = np.mgrid[0:40, 0:37]
+    corr = np.zeros(g.shape)
+    for a_, b_, c_ in zip(dy, dx, tw):
+        corr += c_ * S[np.clip(ys + a_, 0, 40), np.clip(xs + b_, 0, 37)]
+    assert np.abs(corr - oracle.correlate_rects(g, o.rects)).max() < 1e-7
+
+
+def test_tabulated_plan_rules():
+    """Table checks, and which flags a tabulated plan takes."""
+    K = synth.kernels
+    ks, kr = K.cauchy_spatial(6, 2.0), K.tukey_range(0.2, 0.01)
+    L = bf.lib()
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def create(ks_, kr_, step, flags=bf.BF_FLAG_HOST_ONLY, dtype=0, precision=0, n=(8, 4)):
+        h = ctypes.c_void_p()
+        ks_ = np.ascontiguousarray(ks_, dtype=np.float64)
+        kr_ = np.ascontiguousarray(kr_, dtype=np.float64)
+        opts = bf._Opts(dtype, precision, 0.0, 0.0, 0, flags)
+        st = L.bf_plan_create_tabulated(ctypes.byref(h), ks_.ctypes.data_as(dp), (ks_.shape[0] - 1) // 2,
+                                        kr_.ctypes.data_as(dp), len(kr_), step, bf._Terms(*n), ctypes.byref(opts))
+        if st == bf.BF_OK:
+            L.bf_plan_destroy(h)
+        return st
+
+    assert create(ks, kr, 0.01) == bf.BF_OK
+    bad = ks.copy()
+    bad[0, 1] *= 1.5                                   # not even in dx
+    assert create(bad, kr, 0.01) == bf.BF_ERR_INVALID_ARG
+    bad = ks.copy()
+    bad[0, 0] = bad[0, -1] = bad[-1, 0] = bad[-1, -1] = -0.1
+    assert create(bad, kr, 0.01) == bf.BF_ERR_INVALID_ARG
+    bad = ks.copy()
+    bad[6, 6] = 0.0                                    # centre
+    assert create(bad, kr, 0.01) == bf.BF_ERR_INVALID_ARG
+    bad = ks.copy()
+    bad[3, 3] = bad[3, 9] = bad[9, 3] = bad[9, 9] = np.nan
+    assert create(bad, kr, 0.01) == bf.BF_ERR_INVALID_ARG
+    assert create(ks, kr[:1], 0.01) == bf.BF_ERR_INVALID_ARG
+    assert create(ks, kr, 0.0) == bf.BF_ERR_INVALID_ARG
+    assert create(ks, kr, np.inf) == bf.BF_ERR_INVALID_ARG
+    assert create(ks, np.concatenate([[0.0], kr[1:]]), 0.01) == bf.BF_ERR_INVALID_ARG
+    assert create(ks, np.full(20000, 0.5), 1e-4) == bf.BF_ERR_INVALID_ARG   # above 16385 samples
+    assert create(ks, kr, 0.01, n=(0, 4)) == bf.BF_ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    assert L.bf_plan_create_tabulated(ctypes.byref(h), None, 6, kr.ctypes.data_as(dp), len(kr), 0.01,
+                                      bf._Terms(8, 4), None) == bf.BF_ERR_INVALID_ARG
+    # direct summation evaluates analytic kernels only; the automatic choice never takes it
+    assert create(ks, kr, 0.01, flags=bf.BF_FLAG_HOST_ONLY | bf.BF_FLAG_DIRECT) == bf.BF_ERR_UNSUPPORTED
+    p = bf.Plan.tabulated(ks, kr, 0.01, n_range=32, n_spatial=4, host_only=True, direct="auto")
+    assert p.info.direct == 0
+    # a rough table keeps energy in fine Haar levels: more tap offsets per axis than the kernels take
+    rough = np.random.default_rng(1).uniform(0.1, 1.0, (10, 10))
+    rough = np.concatenate([rough[:0:-1], rough])
+    rough = np.concatenate([rough[:, :0:-1], rough], axis=1)
+    assert create(rough, kr, 0.01, n=(8, 6)) == bf.BF_ERR_UNSUPPORTED
+    # the other regimes take tables
+    p = bf.Plan.tabulated(ks, K.tukey_range(0.2, 1 / 255.0), 1 / 255.0, n_range=5, n_spatial=4, dtype="u8",
+                          range_box=True, host_only=True)
+    assert p.info.range_box == 1 and p.info.T == p.info.T_r == 51 / 255.0
+    p = bf.Plan.tabulated(ks, kr, 0.01, n_range=8, n_spatial=4, dtype="u8", level_fold=True, host_only=True)
+    assert p.info.level_fold == 1 and p.info.T == 1.0
+    p = bf.Plan.tabulated(ks, kr, 0.01, n_range=8, n_spatial=4, precision="reduced", host_only=True)
+    assert p.info.reduced == 1
