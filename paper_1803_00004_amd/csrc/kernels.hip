@@ -240,8 +240,11 @@ __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageP
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[m][g][c] += v[m][c] + excl;
         if (j0 < p.pitch)
-          *reinterpret_cast<int4 *>(row + m * te + j0) =
-              make_int4((int)acc[m][g][0], (int)acc[m][g][1], (int)acc[m][g][2], (int)acc[m][g][3]);
+        {
+          typedef int v4i __attribute__((ext_vector_type(4)));
+          const v4i val = {(int)acc[m][g][0], (int)acc[m][g][1], (int)acc[m][g][2], (int)acc[m][g][3]};
+          __builtin_nontemporal_store(val, reinterpret_cast<v4i *>(row + m * te + j0));
+        }
       }
     }
   }
