@@ -277,6 +277,9 @@ bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, co
     for (int q = 0; q < nparts; ++q) {
       t.slot_term[slot + q] = i;
       t.slot_part[slot + q] = f.k[i] == 0 ? 4 : q;
+      t.slot_fhi[slot + q] = t.f_hi[i];
+      t.slot_flo[slot + q] = t.f_lo[i];
+      t.slot_a[slot + q] = t.a[i];
     }
     slot += nparts;
   }

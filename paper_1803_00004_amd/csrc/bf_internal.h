@@ -85,6 +85,10 @@ struct DevTables {
   int slot[kMaxTerms];                 // first table of the term
   // table -> (term, part); part 0: C*I, 1: S*I, 2: C, 3: S, 4: I (k = 0)
   int slot_term[kMaxImages], slot_part[kMaxImages];
+  // the slot's term values again, indexed by slot, so that a lookup kernel
+  // fetches them without first fetching the slot's term
+  float slot_fhi[kMaxImages], slot_flo[kMaxImages];
+  double slot_a[kMaxImages];
   float gmax;                          // bound of |term value| for [0, span] input
   double den_floor;
   int in_u8;

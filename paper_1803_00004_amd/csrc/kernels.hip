@@ -491,11 +491,13 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
   // Eq. 1D_N_terms into the numerator / denominator
   auto body = [&](int m, auto BUF) {
     constexpr uint32_t bo = decltype(BUF)::value * BSTEP;
-    const int t = tab->slot_term[m], part = tab->slot_part[m];
+    const int part = tab->slot_part[m];
+    const float fhi = tab->slot_fhi[m], flo = tab->slot_flo[m];
+    const double at = tab->slot_a[m];
     if (part == 0) {
 #pragma unroll
       for (int i = 0; i < PX; ++i) {
-        const float fr = phase_rev(tab->f_hi[t], tab->f_lo[t], pxv[i]);
+        const float fr = phase_rev(fhi, flo, pxv[i]);
         cs[i] = __builtin_amdgcn_cosf(fr);
         sn[i] = __builtin_amdgcn_sinf(fr);
       }
@@ -530,7 +532,7 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
       for (int i = 0; i < PX; ++i) s[i] = __builtin_fma(w, (double)lds_ld(lds, a + i * PSTEP), s[i]);
     }
     // the k = 0 table of 8-bit input holds bytes: scale 1/255 instead of 2^-q
-    const double ai = tab->a[t] * (U8 && part == 4 ? 1.0 / 255.0 : inv);
+    const double ai = at * (U8 && part == 4 ? 1.0 / 255.0 : inv);
 #pragma unroll
     for (int i = 0; i < PX; ++i) {
       if (part == 4) {
@@ -557,7 +559,7 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
           const int X = min(max(x + tab->tap_dx[q], 0), p.W) - ox;
           d0 = __builtin_fma(tab->tap_w[q], (double)(Y * X), d0);
         }
-        den[i] = __builtin_fma(tab->a[t], d0, den[i]);
+        den[i] = __builtin_fma(at, d0, den[i]);
       }
     }
   };
@@ -1094,7 +1096,9 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
   const int n = tab->n_images;
   load(0);
   for (int m = 0; m < n; ++m) {
-    const int t = tab->slot_term[m], part = tab->slot_part[m];
+    const int part = tab->slot_part[m];
+    const float fhi = tab->slot_fhi[m], flo = tab->slot_flo[m];
+    const double at = tab->slot_a[m];
     const float sc = (U8 && part == 4) ? 1.0f : scale;  // 8-bit k = 0: exact byte sums
     // the segment's fixed-point values and their column totals; the totals of
     // the segments above are the columns' carry into this segment
@@ -1133,7 +1137,7 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
     if (part == 0) {
 #pragma unroll
       for (int i = 0; i < PPT; ++i) {
-        const float fr = phase_rev(tab->f_hi[t], tab->f_lo[t], pxv[i]);
+        const float fr = phase_rev(fhi, flo, pxv[i]);
         cs[i] = __builtin_amdgcn_cosf(fr);
         sn[i] = __builtin_amdgcn_sinf(fr);
       }
@@ -1151,7 +1155,7 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
         sv[i] = __builtin_fma(qw[q], (double)box, sv[i]);
       }
     }
-    const double ai = tab->a[t] * (U8 && part == 4 ? 1.0 / 255.0 : inv_scale);
+    const double ai = at * (U8 && part == 4 ? 1.0 / 255.0 : inv_scale);
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
       if (part == 4) {
@@ -1163,7 +1167,7 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
           const int Yc = min(max(y + tab->tap_dy[k], 0), H), Xc = min(max(x + tab->tap_dx[k], 0), W);
           d0 = __builtin_fma(tab->tap_w[k], (double)Yc * (double)Xc, d0);
         }
-        den[i] = __builtin_fma(tab->a[t], d0, den[i]);
+        den[i] = __builtin_fma(at, d0, den[i]);
       } else if (part == 0) {
         num[i] = __builtin_fma(ai * cs[i], sv[i], num[i]);
       } else if (part == 1) {
