@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpix/s at fixed max-abs err vs FP64 oracle; served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
+CPU_SECONDS = 10.0         # oracle work timed for the CPU baseline (each leg)
 INT32_PEAK_TOPS = 39.3     # 256 CUs x 64 lanes x 2.4 GHz, one 32-bit add per lane per clock
 
 
@@ -214,12 +215,15 @@ def oracle_one_core(workload, n):
     op = oracle.make_plan(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"],
                           **({"span": 0.0} if box else {}))
     rng = np.random.default_rng(13)
-    ys = rng.integers(0, c["H"], n).astype(np.int32)
-    xs = rng.integers(0, c["W"], n).astype(np.int32)
-    t0 = time.perf_counter()
-    (oracle.expanded_rangebox if box else oracle.expanded_brute)(I_host, op, ys, xs)
-    dt = time.perf_counter() - t0
-    print(json.dumps({"mpix_s": n / dt / 1e6, "seconds": dt, "pixels": n}))
+    done, dt = 0, 0.0
+    while done == 0 or (dt < CPU_SECONDS and done < 64 * n):  # batches of n pixels for ~CPU_SECONDS
+        ys = rng.integers(0, c["H"], n).astype(np.int32)
+        xs = rng.integers(0, c["W"], n).astype(np.int32)
+        t0 = time.perf_counter()
+        (oracle.expanded_rangebox if box else oracle.expanded_brute)(I_host, op, ys, xs)
+        dt += time.perf_counter() - t0
+        done += n
+    print(json.dumps({"mpix_s": done / dt / 1e6, "seconds": dt, "pixels": done}))
 
 
 def one_core_baseline(workload, n):
@@ -322,15 +326,19 @@ def range_box(args):
         import oracle
         op = oracle.make_plan(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"], span=0.0)
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        n = 262144  # about 2 s of 16 host cores
+        n = 262144  # about 2 s of 16 host cores per batch; batches for ~CPU_SECONDS
         rng = np.random.default_rng(11)
-        ys, xs = rng.integers(0, H, n).astype(np.int32), rng.integers(0, W, n).astype(np.int32)
-        log("[bench] oracle T4 on %d sampled pixels (%d threads)" % (n, threads))
-        t0 = time.perf_counter()
-        ref = oracle.expanded_rangebox(Z, op, ys, xs)
-        cpu_s = time.perf_counter() - t0
+        log("[bench] oracle T4 on sampled pixels (%d threads), batches of %d for ~%.0f s" % (threads, n, CPU_SECONDS))
         out_host = out.cpu().numpy().astype(np.float64)
-        err = float(np.abs(out_host[ys, xs] - ref).max())
+        err, done, cpu_s = 0.0, 0, 0.0
+        while done == 0 or (cpu_s < CPU_SECONDS and done < 64 * n):
+            ys, xs = rng.integers(0, H, n).astype(np.int32), rng.integers(0, W, n).astype(np.int32)
+            t0 = time.perf_counter()
+            ref = oracle.expanded_rangebox(Z, op, ys, xs)
+            cpu_s += time.perf_counter() - t0
+            err = max(err, float(np.abs(out_host[ys, xs] - ref).max()))
+            done += n
+        n = done
         t1 = oracle.true_bf(Z, c["sigma_s"], c["radius"], c["sigma_r"], ys[:4096], xs[:4096])
         result["max_abs_err_vs_oracle"] = err
         result["max_abs_err_vs_true_bf_4096px"] = float(np.abs(out_host[ys[:4096], xs[:4096]] - t1).max())
@@ -519,25 +527,32 @@ def main():
         out_host = out.cpu().numpy().astype(np.float64)
         op = oracle.make_plan(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"])
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        # the oracle is run again until about CPU_SECONDS of work have been timed
         if px <= 4 * 1024 * 1024:
-            log("[bench] oracle T3 on the full image (%d threads)" % threads)
-            t0 = time.perf_counter()
-            ref = oracle.expanded_box(I_host, op)
-            cpu_s = time.perf_counter() - t0
+            log("[bench] oracle T3 on the full image (%d threads), repeated for ~%.0f s" % (threads, CPU_SECONDS))
+            reps, cpu_s = 0, 0.0
+            while reps == 0 or (cpu_s < CPU_SECONDS and reps < 64):
+                t0 = time.perf_counter()
+                ref = oracle.expanded_box(I_host, op)
+                cpu_s += time.perf_counter() - t0
+                reps += 1
             err = float(np.abs(out_host - ref).max())
-            sample = "full %dx%d image, oracle T3 (FP64 shift identity + box sums)" % (W, H)
-            cpu_mpix = px / cpu_s / 1e6
+            sample = "full %dx%d image x %d, oracle T3 (FP64 shift identity + box sums)" % (W, H, reps)
+            cpu_mpix = reps * px / cpu_s / 1e6
         else:
             n = 2048
             rng = np.random.default_rng(11)
-            ys, xs = rng.integers(0, H, n).astype(np.int32), rng.integers(0, W, n).astype(np.int32)
-            log("[bench] oracle T2 on %d sampled pixels (%d threads)" % (n, threads))
-            t0 = time.perf_counter()
-            ref = oracle.expanded_brute(I_host, op, ys, xs)
-            cpu_s = time.perf_counter() - t0
-            err = float(np.abs(out_host[ys, xs] - ref).max())
-            sample = "%d random pixels of the %dx%d image, oracle T2 (FP64 direct sum)" % (n, W, H)
-            cpu_mpix = n / cpu_s / 1e6
+            log("[bench] oracle T2 on sampled pixels (%d threads), batches of %d for ~%.0f s" % (threads, n, CPU_SECONDS))
+            err, done, cpu_s = 0.0, 0, 0.0
+            while done == 0 or (cpu_s < CPU_SECONDS and done < 64 * n):
+                ys, xs = rng.integers(0, H, n).astype(np.int32), rng.integers(0, W, n).astype(np.int32)
+                t0 = time.perf_counter()
+                ref = oracle.expanded_brute(I_host, op, ys, xs)
+                cpu_s += time.perf_counter() - t0
+                err = max(err, float(np.abs(out_host[ys, xs] - ref).max()))
+                done += n
+            sample = "%d random pixels of the %dx%d image, oracle T2 (FP64 direct sum)" % (done, W, H)
+            cpu_mpix = done / cpu_s / 1e6
         rng = np.random.default_rng(12)
         ys, xs = rng.integers(0, H, 4096).astype(np.int32), rng.integers(0, W, 4096).astype(np.int32)
         t1 = oracle.true_bf(I_host, c["sigma_s"], c["radius"], c["sigma_r"], ys, xs)
