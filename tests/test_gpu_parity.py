@@ -556,18 +556,22 @@ def test_range_box_in_batches(torch_dev):
 
 
 def test_served_mixed_plan_kinds(torch_dev):
-    """The request loop with every kind of plan in one queue: Gaussian and
-    exponential expansions, direct summation (both range kinds) and the 8-bit
-    range-box regime, on 8-bit images of mixed sizes.  Each result is bitwise
-    the single-image result."""
+    """The request loop with every kind of plan in one queue: Gaussian,
+    exponential and tabulated expansions, direct summation (both range kinds),
+    the 8-bit range-box regime and the level fold, on 8-bit images of mixed
+    sizes.  Each result is bitwise the single-image result."""
     import torch
     bf = _bf()
+    K = synth.kernels
+    tab = (K.cauchy_spatial(9, 3.0), K.tukey_range(0.2, 1 / 255.0), 1 / 255.0)
     plans = [bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8"),
              bf.Plan(3.0, 0.1, 14, 12, 6, dtype="u8", kernel_s="exponential", kernel_r="exponential"),
              bf.Plan(2.0, 0.1, 6, 8, 4, dtype="u8", direct=True),
              bf.Plan(2.0, 0.1, 9, 8, 4, dtype="u8", direct=True, kernel_s="exponential", kernel_r="exponential"),
              bf.Plan(8.0, 0.1, 24, 5, 6, dtype="u8", range_box=True),
-             bf.Plan(3.0, 0.1, 9, 5, 4, dtype="u8", range_box=True)]
+             bf.Plan(3.0, 0.1, 9, 5, 4, dtype="u8", range_box=True),
+             bf.Plan.tabulated(*tab, n_range=8, n_spatial=6, dtype="u8"),
+             bf.Plan(3.0, 0.1, 9, 16, 4, dtype="u8", level_fold=True)]
     rng = np.random.default_rng(31)
     sizes = [(int(rng.integers(40, 300)), int(rng.integers(40, 300))) for _ in range(24)]
     imgs = [torch.from_numpy(synth.gen_image_u8(h, w, 4, 0.03, 100 + i)).cuda() for i, (h, w) in enumerate(sizes)]
@@ -596,6 +600,12 @@ def test_served_mixed_plan_kinds(torch_dev):
     Z = imgs[1].cpu().numpy()
     ref = oracle.expanded_box(Z, oracle.make_plan(3.0, 14, 6, 0.1, 12, kind_s="exponential", kind_r="exponential"))
     assert np.abs(outs[1].cpu().numpy() - ref).max() <= TIGHT
+    Z = imgs[6].cpu().numpy()
+    ref = oracle.expanded_box(Z, oracle.make_table_plan(*tab, 6, 8))
+    assert np.abs(outs[6].cpu().numpy() - ref).max() <= TIGHT
+    Z = imgs[7].cpu().numpy()
+    ref = oracle.expanded_box(Z, oracle.make_plan(3.0, 9, 4, 0.1, 16))
+    assert np.abs(outs[7].cpu().numpy() - ref).max() <= TIGHT
 
 
 @pytest.mark.parametrize("H,W,ss,r,ns,sr,nr,dtype", [
@@ -681,16 +691,21 @@ def test_reduced_precision_full_size(torch_dev, name):
 
 def test_graph_replays_of_every_plan_kind(torch_dev):
     """A batch holding every plan kind (expansion, direct summation with the
-    exponential range kernel, range-box regime, reduced precision), captured
-    once in a graph and replayed on new inputs with eager work in between:
-    every replay equals the eager single-image calls."""
+    exponential range kernel, range-box regime, reduced precision, tabulated
+    kernels, level fold), captured once in a graph and replayed on new inputs
+    with eager work in between: every replay equals the eager single-image
+    calls."""
     import torch
     bf = _bf()
+    K = synth.kernels
     plans = [bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8"),
              bf.Plan(2.0, 0.1, 9, 8, 4, dtype="u8", direct=True, kernel_r="exponential"),
              bf.Plan(8.0, 0.1, 24, 5, 6, dtype="u8", range_box=True),
-             bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8", precision="reduced")]
-    shapes = [(97, 150), (64, 77), (130, 129), (111, 96)]
+             bf.Plan(3.0, 0.1, 9, 8, 4, dtype="u8", precision="reduced"),
+             bf.Plan.tabulated(K.cauchy_spatial(9, 3.0), K.tukey_range(0.2, 1 / 255.0), 1 / 255.0, n_range=8,
+                               n_spatial=6, dtype="u8"),
+             bf.Plan(3.0, 0.1, 9, 16, 4, dtype="u8", level_fold=True)]
+    shapes = [(97, 150), (64, 77), (130, 129), (111, 96), (80, 201), (150, 70)]
     static_in = [torch.from_numpy(synth.gen_image_u8(h, w, 4, 0.03, 300 + i)).cuda() for i, (h, w) in enumerate(shapes)]
     outs = [torch.empty(I.shape, dtype=torch.float32, device="cuda") for I in static_in]
     ws = torch.empty(bf.batch_workspace_size(plans, shapes), dtype=torch.uint8, device="cuda")
