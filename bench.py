@@ -376,8 +376,9 @@ def main():
                          "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the filter has no multi-GPU path in this build "
-              "(requests and image bands would shard without collectives).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (served requests "
+              "would shard across GPUs by request, and one large image into row bands with an r-row "
+              "halo, without collectives).", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "cfg4_served":

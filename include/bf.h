@@ -56,7 +56,7 @@ typedef enum {
   BF_ERR_INVALID_ARG = 1,   /* bad pointer, size, parameter, or workspace too small */
   BF_ERR_OUT_OF_MEMORY = 2, /* a device or host allocation failed */
   BF_ERR_DEVICE = 3,        /* a HIP call or kernel launch failed */
-  BF_ERR_UNSUPPORTED = 4    /* valid request this build does not implement */
+  BF_ERR_UNSUPPORTED = 4    /* valid request the library does not implement */
 } bf_status_t;
 
 /* Kernel shapes.  Eq. BF takes symmetric kernels decreasing on R+ and the

@@ -417,3 +417,15 @@ def test_tabulated_plan_rules():
     assert p.info.level_fold == 1 and p.info.T == 1.0
     p = bf.Plan.tabulated(ks, kr, 0.01, n_range=8, n_spatial=4, precision="reduced", host_only=True)
     assert p.info.reduced == 1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: a multi-GPU request exits with a message
+    before anything touches a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
