@@ -271,6 +271,30 @@ def test_4096_sampled(torch_dev, name):
     assert err <= TIGHT
 
 
+@pytest.mark.parametrize("H,W,dtype", [(64, 32768, "f32"), (32768, 64, "f32"), (48, 32768, "u8")])
+def test_maximum_sizes_sampled(torch_dev, H, W, dtype):
+    """The largest image side (32768) on thin images, both orientations and
+    both input types: sampled pixels, borders and tile seams included, against
+    T2."""
+    bf = _bf()
+    ss, r, ns, sr, nr = (8.0, 24, 6, 0.1, 16) if dtype == "f32" else (16.0, 48, 8, 0.05, 32)
+    I = synth.gen_image_u8(H, W, 20, 0.03, 5) if dtype == "u8" else synth.gen_image(H, W, 20, 0.03, 5)
+    p = bf.Plan(ss, sr, r, nr, ns, dtype=dtype)
+    try:
+        out = _run(torch_dev, p, I)
+    finally:
+        p.close()  # the plan's workspace
+    rng = np.random.default_rng(17)
+    ys = np.concatenate([rng.integers(0, H, 1024), [0, H - 1, 0, H - 1, H // 2, min(H - 1, 511), min(H - 1, 512)]])
+    xs = np.concatenate([rng.integers(0, W, 1024), [0, W - 1, W - 1, 0, W // 2, min(W - 1, 512), min(W - 1, 511)]])
+    ys, xs = ys.astype(np.int32), xs.astype(np.int32)
+    ref = oracle.expanded_brute(I, oracle.make_plan(ss, r, ns, sr, nr), ys, xs)
+    err = np.abs(out[ys, xs] - ref).max()
+    _report("%dx%d %s sampled vs T2" % (H, W, dtype), err)
+    assert np.isfinite(out).all()
+    assert err <= TIGHT
+
+
 def test_argument_errors_on_device(torch_dev):
     import ctypes
     import torch
