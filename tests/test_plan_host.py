@@ -429,3 +429,18 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_empty_batch_is_a_no_op():
+    """A batch of no images: the workspace is the queue heads alone and the
+    call succeeds without touching a device; a negative count is an error."""
+    L = bf.lib()
+    vp = ctypes.c_void_p
+    plans = (vp * 1)()
+    hw = (ctypes.c_int * 1)()
+    size = ctypes.c_size_t()
+    assert L.bf_batch_workspace_size(plans, 0, hw, hw, ctypes.byref(size)) == bf.BF_OK
+    assert size.value == 256
+    ptrs = (vp * 1)()
+    assert L.bf_filter_batch(plans, 0, ptrs, ptrs, hw, hw, None, 0, None) == bf.BF_OK
+    assert L.bf_filter_batch(plans, -1, ptrs, ptrs, hw, hw, None, 0, None) == bf.BF_ERR_INVALID_ARG
