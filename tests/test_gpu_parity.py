@@ -799,11 +799,13 @@ def _table_cases():
                                  16, "f32"),
         "cauchy r48 tukey f32": (130, 129, K.cauchy_spatial(48, 10.0), K.tukey_range(0.3, 0.01), 0.01, 8, 32, "f32"),
         "cauchy r3 cauchy f32": (5, 33, K.cauchy_spatial(3, 1.0), K.cauchy_range(0.1, 0.01, 101), 0.01, 4, 8, "f32"),
+        "cauchy r24 tukey 1080p f32": (1080, 1920, K.cauchy_spatial(24, 8.0), K.tukey_range(0.3, 0.005), 0.005, 6,
+                                       16, "f32"),
     }
 
 
 @pytest.mark.parametrize("name", ["cauchy r9 tukey u8", "gauss r24 cauchy f32", "cauchy r48 tukey f32",
-                                  "cauchy r3 cauchy f32"])
+                                  "cauchy r3 cauchy f32", "cauchy r24 tukey 1080p f32"])
 def test_tabulated_kernels_vs_oracle(torch_dev, name):
     """Tabulated kernels change only the fitted coefficients: the same kernels
     filter them, against the oracle's T3 for the same tables."""
