@@ -444,3 +444,19 @@ def test_empty_batch_is_a_no_op():
     ptrs = (vp * 1)()
     assert L.bf_filter_batch(plans, 0, ptrs, ptrs, hw, hw, None, 0, None) == bf.BF_OK
     assert L.bf_filter_batch(plans, -1, ptrs, ptrs, hw, hw, None, 0, None) == bf.BF_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("span,step,n", [(2.0, 0.01, 31), (5.0, 0.05, 61), (1.0, 1 / 255.0, 256)])
+def test_tabulated_range_fit_with_wider_series_interval(span, step, n):
+    """The range table's coefficients when the series interval T = max(T_r,
+    span) extends past the table (zero there) or the table covers every level
+    difference of 8-bit data: library against oracle."""
+    ks = synth.kernels.cauchy_spatial(6, 2.0)
+    kr = synth.kernels.cauchy_range(0.1, step, n)
+    p = bf.Plan.tabulated(ks, kr, step, n_range=24, n_spatial=4, span=span, host_only=True)
+    o = oracle.make_table_plan(ks, kr, step, 4, 24, span=span)
+    k, a, w = p.range_terms()
+    assert p.info.T == o.range.T == max((n - 1) * step, span)
+    assert k.tolist() == o.range.k.tolist()
+    assert np.abs(a - o.a).max() <= 1e-13
+    assert np.abs(w - o.omega).max() <= 1e-12
