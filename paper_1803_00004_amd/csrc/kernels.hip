@@ -959,7 +959,7 @@ bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const v
   if (lds > kLdsLimit) return BF_ERR_UNSUPPORTED;
   const int te = big ? 64 : 32;
   const int tiles = ((W + te - 1) / te) * ((H + te - 1) / te);
-  const int nsplit = std::max(1, std::min(8, 512 / tiles));  // small images: several blocks per tile
+  const int nsplit = std::max(1, std::min(8, 1024 / tiles));  // small images: several blocks per tile
   const int blocks = tiles * nsplit;
   const void *fn = big ? (const void *)kz_rangebox<64, 1024> : (const void *)kz_rangebox<32, 512>;
   profile_mark(1, 1, stream);
