@@ -84,8 +84,8 @@ typedef struct {
 
 typedef enum { BF_IN_F32 = 0, BF_IN_U8 = 1 } bf_dtype_t;
 
-/* PLAIN: int32 summed-area tables (exact), FP64 tap sums; max-abs error
- * against the FP64 expanded form about 1e-6.  REDUCED: the term images are
+/* PLAIN: int32 summed-area tables (exact box sums), FP32 tap sums and
+ * accumulation; max-abs error against the FP64 expanded form about 1e-6.  REDUCED: the term images are
  * stored once in FP16 (2 bytes per pixel and table, no halo copies) and the
  * lookup kernel builds each table of its output tile in LDS from them (exact
  * int32 sums of the FP16 values); the error is the FP16 rounding of the term
@@ -238,7 +238,8 @@ typedef struct {
   double T;           /* range series half-interval max(T_r, span) */
   double den_floor;   /* out = I where den <= den_floor (1e-7 sum |K~_s|) */
   int n_quads;        /* taps grouped in symmetric quadruplets (one box sum each) */
-  int n_single;       /* taps outside any quadruplet */
+  int n_single;       /* taps outside any quadruplet: always 0 (plans whose taps do not all pair
+                         into quadruplets are refused with BF_ERR_UNSUPPORTED) */
   int lookup_kernel;  /* 1: LDS tile lookup kernel, 0: per-pixel lookup kernel */
   int direct;         /* 1: filters by direct summation (BF_FLAG_DIRECT / _AUTO) */
   int range_box;      /* 1: the 8-bit range-box regime (BF_FLAG_RANGE_BOX) */
@@ -246,6 +247,9 @@ typedef struct {
   int box_tile;       /* its output tile edge (64, or 32 where a 64 tile's region exceeds LDS) */
   int reduced;        /* 1: BF_PREC_REDUCED (FP16 term images, tables built in LDS) */
   int level_fold;     /* 1: BF_FLAG_LEVEL_FOLD (8-bit, range terms folded per output level) */
+  int lds_pitch;      /* LDS tile lookup kernel: row pitch (int32) of its staged table region
+                         (128, 160, 176 or 192); 0 when the per-pixel kernel is used */
+  int lds_double_buffered; /* 1: two staged regions fit in LDS (pitch 128) */
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);
@@ -255,9 +259,8 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);
  * tables summed with wrapping 32-bit adds; the kernels use only box
  * differences of a table, exact modulo 2^32, so q is the largest shift with
  * (2r + 1)^2 (gmax 2^q + 1) <= 2^31 - 1 (at most 24) and does not depend on
- * the tile.  For a plan with lone taps (bf_plan_info_t.n_single > 0) raw table
- * values are read and q instead keeps (tile + 2r)^2 (gmax 2^q + 1) in range.
- * Any pointer may be NULL. */
+ * the tile (the FP32 rounding of the quantised products is allowed for by a
+ * factor 1 + 2^-20 on gmax).  Any pointer may be NULL. */
 bf_status_t bf_image_geometry(bf_plan_t plan, int H, int W, int *tile, int *sat_shift,
                               size_t *ws_bytes);
 
@@ -288,15 +291,14 @@ bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, i
  * it, so the workspace size of those images may change: size workspaces
  * after tuning.  Results do not change: only plans whose taps all belong to
  * quadruplets are tuned, and their outputs do not depend on the tiling.
- * Other plans (lone taps, or a tile fixed in the options) are left as they
- * are.  Allocates and frees device memory and synchronises `stream`; not for
+ * Other plans (a tile fixed in the options) are left as they are.  Allocates and frees device memory and synchronises `stream`; not for
  * use under graph capture.  *tile (may be NULL) receives the chosen tile. */
 bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, int *tile);
 /* Set the launch shape for this plan's shape class and H x W's size bucket
  * by hand, as bf_autotune would: table tile (a multiple of 64 with
  * tile + 2r + 1 <= 1024), kb_single (1: single-buffered lookup kernel),
  * ka_one (1: one table per table-kernel wave).  BF_ERR_UNSUPPORTED for plans
- * that are not tuned (lone taps or a fixed tile). */
+ * that are not tuned (a fixed tile, direct, range-box or reduced plans). */
 bf_status_t bf_tuning_set(bf_plan_t plan, int H, int W, int tile, int kb_single, int ka_one);
 /* Forget every tuned shape. */
 bf_status_t bf_autotune_clear(void);
@@ -307,7 +309,7 @@ bf_status_t bf_autotune_clear(void);
  * kernel or on sigma_r while T = max(T_r, span) stays the same), so tables
  * built once under `tables_plan` serve later filters of the same image under
  * any `plan` that is compatible: same input type, radius <= tables_plan's,
- * no lone taps, and range terms equal to the first terms of tables_plan's
+ * and range terms equal to the first terms of tables_plan's
  * (same k, same T).  Only the lookup kernel runs.  The result equals
  * bf_filter(plan) up to the fixed-point shift, which here is tables_plan's
  * (within 1e-6 of it; not bitwise).
@@ -318,7 +320,7 @@ bf_status_t bf_precompute_size(bf_plan_t tables_plan, int H, int W, size_t *byte
 bf_status_t bf_precompute(bf_plan_t tables_plan, const void *I, int H, int W, void *ws, size_t ws_bytes,
                           void *stream);
 /* BF_OK if tables built under tables_plan serve plan; else BF_ERR_INVALID_ARG
- * (or BF_ERR_UNSUPPORTED for a plan with lone taps). Host only. */
+ * (BF_ERR_UNSUPPORTED for direct, range-box or reduced plans). Host only. */
 bf_status_t bf_precomputed_compatible(bf_plan_t tables_plan, bf_plan_t plan);
 /* Filter I (the image the tables were built from) under plan, reading the
  * tables in ws; lookup kernel only. */
@@ -350,7 +352,10 @@ bf_status_t bf_profile_read(double ms[2], int launches[2]);
  *
  * The server owns its arena (one device allocation of hbm_budget bytes at
  * create) and its streams; the caller owns plans, images and outputs and
- * keeps them alive until the request completes.  Completions are found by
+ * keeps them alive until the request completes.  The server's streams do not
+ * wait for any other stream: a request's input must hold its final values,
+ * and no queued work may still write its output, when it is submitted (the
+ * caller synchronises the streams that produced them first).  Completions are found by
  * bf_server_poll, which never blocks; `now` is the caller's clock, recorded
  * as the completion time.  Not thread-safe: one thread drives a server.
  *

@@ -46,16 +46,14 @@ TuneKey tune_key(const bf_plan_s *p, int H, int W) {
 }
 
 bool tunable(const bf_plan_s *p) {
-  return p->tile == 0 && p->host_tables.n_single == 0 && !p->host_tables.direct && !p->host_tables.range_box &&
-         !p->host_tables.reduced;
+  return p->tile == 0 && !p->host_tables.direct && !p->host_tables.range_box && !p->host_tables.reduced;
 }
 
 bf::Geometry geometry_with(const bf_plan_s *p, int H, int W, int tile_override, int kb_single,
                            int ka_one) {
   int tile = 0, q = 0;
-  const int box_edge = p->host_tables.n_single == 0 ? 2 * p->fit.radius + 1 : 0;
   bf::choose_tiling(H, W, p->fit.radius, p->host_tables.n_terms, tile_override ? tile_override : p->tile,
-                    p->gmax, box_edge, &tile, &q);
+                    p->gmax, &tile, &q);
   // a direct plan keeps no tables: an empty workspace
   const bool no_tables = p->host_tables.direct || p->host_tables.range_box || p->host_tables.reduced;
   bf::Geometry g = bf::make_geometry(H, W, tile, p->fit.radius, no_tables ? 0 : p->host_tables.n_images, q);
@@ -194,34 +192,18 @@ bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, co
   bf::DevTables &t = p->host_tables;
   std::memset(&t, 0, sizeof t);
   t.n_terms = (int)f.k.size();
-  t.n_ty = (int)f.row_off.size();
-  t.n_tx = (int)f.col_off.size();
-  for (int i = 0; i < t.n_ty; ++i) t.ty[i] = f.row_off[i];
-  for (int j = 0; j < t.n_tx; ++j) t.tx[j] = f.col_off[j];
-  for (int i = 0; i < t.n_ty; ++i)
-    for (int j = 0; j < t.n_tx; ++j) t.w[i * bf::kMaxTapAxis + j] = f.tap_grid[(size_t)i * t.n_tx + j];
-  // compact tap list
   const int nt = (int)f.tap_w.size();
-  if (nt > bf::kMaxTaps - 3) {
+  if (nt > bf::kMaxTaps) {
     delete p;
     return BF_ERR_UNSUPPORTED;
   }
-  t.n_taps4 = (nt + 3) / 4 * 4;
   t.tap_dy_min = t.tap_dx_min = 1 << 30;
   t.tap_dy_max = t.tap_dx_max = -(1 << 30);
   for (int i = 0; i < nt; ++i) {
-    t.tap_dy[i] = f.tap_dy[i];
-    t.tap_dx[i] = f.tap_dx[i];
-    t.tap_w[i] = f.tap_w[i];
     t.tap_dy_min = std::min(t.tap_dy_min, f.tap_dy[i]);
     t.tap_dy_max = std::max(t.tap_dy_max, f.tap_dy[i]);
     t.tap_dx_min = std::min(t.tap_dx_min, f.tap_dx[i]);
     t.tap_dx_max = std::max(t.tap_dx_max, f.tap_dx[i]);
-  }
-  for (int i = nt; i < t.n_taps4; ++i) {  // padding: weight 0 at the first tap's position
-    t.tap_dy[i] = f.tap_dy[0];
-    t.tap_dx[i] = f.tap_dx[0];
-    t.tap_w[i] = 0.0;
   }
   // quadruplets for the LDS tile kernel: region of 64 + (dx_max - dx_min) columns
   t.lds_pitch = bf::lds_pitch_for(64 + t.tap_dx_max - t.tap_dx_min);
@@ -249,19 +231,21 @@ bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, co
         const int q = t.n_quads++;
         t.quad_dy[q] = dy;
         t.quad_dx[q] = dx;
-        t.quad_w[q] = 0.25 * ((wa + wd) - (wb + wc));
+        t.quad_w[q] = (float)(0.25 * ((wa + wd) - (wb + wc)));
         for (int j = 0; j < nt; ++j) {
           const int ey = f.tap_dy[j], ex = f.tap_dx[j];
           if ((ey == dy || ey == 1 - dy) && (ex == dx || ex == 1 - dx)) used[j] = 1;
         }
       }
     }
+    // Every expansion of a kernel that is even in dy and in dx (all kernels
+    // the plans take: each Haar level group is symmetric on both axes) pairs
+    // all of its taps; a tap left over would need raw table values, which
+    // wrap, so such a plan is refused.
     for (int i = 0; i < nt; ++i)
       if (!used[i]) {
-        t.single_dy[t.n_single] = f.tap_dy[i];
-        t.single_dx[t.n_single] = f.tap_dx[i];
-        t.single_w[t.n_single] = f.tap_w[i];
-        ++t.n_single;
+        delete p;
+        return BF_ERR_UNSUPPORTED;
       }
   }
   int slot = 0;
@@ -270,7 +254,7 @@ bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, co
     if (o.in_dtype == BF_IN_U8) fk /= 255.0;
     t.f_hi[i] = (float)fk;
     t.f_lo[i] = (float)(fk - (double)t.f_hi[i]);
-    t.a[i] = f.a[i];
+    t.a[i] = (float)f.a[i];
     t.k_is_zero[i] = f.k[i] == 0;
     t.slot[i] = slot;
     const int nparts = f.k[i] == 0 ? 1 : 4;
@@ -285,7 +269,7 @@ bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, co
   }
   t.n_images = slot;
   t.gmax = (float)gmax;
-  t.den_floor = 1e-7 * f.sum_abs_K;
+  t.den_floor = (float)(1e-7 * f.sum_abs_K);
   t.in_u8 = o.in_dtype == BF_IN_U8;
 
   // direct summation: on request, or where its cost model is lower
@@ -294,13 +278,13 @@ bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, co
   // (1700 + n_images (85 + 10 quadruplets)) (1 + r / 120).
   if (reduced) {
     t.reduced = 1;
-    if (bf::reduced_tile(t) == 0 || t.n_quads > 12 || t.n_single != 0) {
+    if (bf::reduced_tile(t) == 0 || t.n_quads > 12) {
       delete p;
       return BF_ERR_UNSUPPORTED;
     }
   }
   if (range_box || level_fold) {
-    if (f.radius > bf::kMaxRangeBoxRadius || t.n_single != 0) {
+    if (f.radius > bf::kMaxRangeBoxRadius) {
       delete p;
       return BF_ERR_UNSUPPORTED;
     }
@@ -316,21 +300,22 @@ bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, co
       double w = 0.0;
       if (std::abs(d) <= t.box_zr)
         for (size_t i = 0; i < f.k.size(); ++i) w += f.a[i] * std::cos(f.omega[i] * (d / 255.0));
-      t.box_w[d + 255] = w;
-      wmax = std::max(wmax, std::fabs(w));
+      t.box_w[d + 255] = (float)w;
+      wmax = std::max(wmax, std::fabs((double)t.box_w[d + 255]));
     }
-    // slab values |W(d) z / 255| <= wmax are stored as round(v 2^q); every box
-    // of a quadruplet lies inside the (2r+1)^2 window, so q is the largest
-    // shift (<= 24) with (2r + 1)^2 (wmax 2^q + 1) <= 2^31 - 1
+    // slab values |W(d) z / 255| <= wmax are stored as round(v 2^q), computed
+    // in FP32; every box of a quadruplet lies inside the (2r+1)^2 window, so q
+    // is the largest shift (<= 24) with
+    // (2r + 1)^2 (wmax 2^q (1 + 2^-20) + 1) <= 2^31 - 1
     const double area = (double)(2 * f.radius + 1) * (2 * f.radius + 1);
     int q = 24;
-    while (q > 0 && area * (wmax * std::ldexp(1.0, q) + 1.0) > 2147483647.0) --q;
-    t.box_scale = std::ldexp(1.0, q);
+    while (q > 0 && area * (wmax * std::ldexp(1.0, q) * (1.0 + std::ldexp(1.0, -20)) + 1.0) > 2147483647.0) --q;
+    t.box_scale = std::ldexp(1.0f, q);
   }
   bool direct = (o.flags & BF_FLAG_DIRECT) != 0;
   if (!direct && !tabulated && (o.flags & BF_FLAG_DIRECT_AUTO) && f.radius <= bf::kMaxDirectRadius) {
     const double e = (double)(2 * f.radius + 1) * (2 * f.radius + 1);
-    const double expansion = (1700.0 + t.n_images * (85.0 + 10.0 * (t.n_quads + t.n_single))) * (1.0 + f.radius / 120.0);
+    const double expansion = (1700.0 + t.n_images * (85.0 + 10.0 * t.n_quads)) * (1.0 + f.radius / 120.0);
     direct = 8.5 * e < expansion;
   }
   if (direct && f.radius > bf::kMaxDirectRadius) {
@@ -633,7 +618,6 @@ bf_status_t bf_precomputed_compatible(bf_plan_t tables_plan, bf_plan_t plan) {
   const bf::DevTables &a = tables_plan->host_tables, &b = plan->host_tables;
   if (tables_plan->in_dtype != plan->in_dtype) return BF_ERR_INVALID_ARG;
   if (plan->fit.radius > tables_plan->fit.radius) return BF_ERR_INVALID_ARG;  // halo too small
-  if (b.n_single != 0) return BF_ERR_UNSUPPORTED;  // lone taps read raw (possibly wrapped) entries
   if (b.n_terms > a.n_terms) return BF_ERR_INVALID_ARG;
   for (int i = 0; i < b.n_terms; ++i)  // the same terms, in the same table slots
     if (plan->fit.k[i] != tables_plan->fit.k[i] || b.f_hi[i] != a.f_hi[i] || b.f_lo[i] != a.f_lo[i] ||
@@ -673,20 +657,20 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   info->box_levels = plan->host_tables.range_box ? plan->host_tables.box_zr : -1;
   info->box_tile = plan->host_tables.range_box ? bf::rangebox_tile(plan->host_tables) : 0;
   info->reduced = plan->host_tables.reduced;
-  info->n_single = plan->host_tables.n_single;
+  info->n_single = 0;
+  info->lds_pitch = bf::lookup_kernel_kind(plan->host_tables) ? plan->host_tables.lds_pitch : 0;
+  info->lds_double_buffered = bf::kb_double_buffered(plan->host_tables);
   if (plan->host_tables.range_box) {
-    info->sat_shift = (int)std::lround(std::log2(plan->host_tables.box_scale));
-  } else if (plan->host_tables.n_single == 0) {  // q depends on r and gmax only
+    info->sat_shift = (int)std::lround(std::log2((double)plan->host_tables.box_scale));
+  } else {  // q depends on r and gmax only
     int tile = 0, q = 0;
-    bf::choose_tiling(64, 64, f.radius, plan->host_tables.n_terms, 64, plan->gmax, 2 * f.radius + 1, &tile, &q);
+    bf::choose_tiling(64, 64, f.radius, plan->host_tables.n_terms, 64, plan->gmax, &tile, &q);
     info->sat_shift = q;
-  } else {
-    info->sat_shift = -1;
   }
   info->T_s = f.T_s;
   info->T_r = f.T_r;
   info->T = f.T;
-  info->den_floor = plan->host_tables.den_floor;
+  info->den_floor = 1e-7 * f.sum_abs_K;  // the kernels compare against its FP32 rounding
   return BF_OK;
 }
 

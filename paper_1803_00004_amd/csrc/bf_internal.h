@@ -12,7 +12,8 @@ namespace bf {
 // Compile-time capacities of the device tables.
 constexpr int kMaxTerms = 64;      // cosine terms per plan
 constexpr int kMaxTapAxis = 16;    // distinct tap offsets per axis (Haar levels <= 3)
-constexpr int kMaxTaps = 256;      // nonzero summed-area-table taps (padded to a multiple of 4)
+constexpr int kMaxTaps = 256;      // nonzero summed-area-table taps
+constexpr int kMaxQuads = kMaxTaps / 4;  // symmetric tap quadruplets
 constexpr int kMaxImages = 4 * kMaxTerms;  // term images (tables) per filter call
 constexpr int kMaxChunks = 8;      // 256-column chunks of one table row (table width <= 2048)
 constexpr int kKA_Threads = 256;   // summed-area-table kernel block size (upper bound)
@@ -57,30 +58,21 @@ constexpr int kMaxRangeSamples = 16385;
 // Fit both expansions; returns BF_OK, BF_ERR_INVALID_ARG or BF_ERR_UNSUPPORTED.
 bf_status_t fit_plan(const KernelSpec &kern, int radius, bf_terms_t N, double eps, double span, Fit *out);
 
-// Device-side constant tables of a plan (one upload per plan).
+// Device-side constant tables of a plan (one upload per plan).  Everything
+// the kernels read is integer or FP32: the FP64 fit stays on the host.
 struct DevTables {
   int n_terms;
-  int n_ty, n_tx;                      // tap grid shape
-  int ty[kMaxTapAxis], tx[kMaxTapAxis];
-  double w[kMaxTapAxis * kMaxTapAxis]; // tap weights on the grid, row stride kMaxTapAxis (0 = none)
-  // compact list of the nonzero taps, padded with zero-weight taps to n_taps4
-  int n_taps4;
-  int tap_dy[kMaxTaps], tap_dx[kMaxTaps];
-  double tap_w[kMaxTaps];
-  int tap_dy_min, tap_dy_max, tap_dx_min, tap_dx_max;
-  // Taps grouped for the LDS tile kernel.  A symmetric kernel has taps
-  // (dy, dx), (1-dy, dx), (dy, 1-dx), (1-dy, 1-dx) with weights w, -w, -w, w:
-  // one box sum of the table, differenced exactly in int32, times w.  Each
-  // quadruplet is stored as its representative (dy >= 1, dx >= 1).
+  int tap_dy_min, tap_dy_max, tap_dx_min, tap_dx_max;  // extent of the summed-area-table taps
+  // The taps of a symmetric kernel come in quadruplets (dy, dx), (1-dy, dx),
+  // (dy, 1-dx), (1-dy, 1-dx) with weights w, -w, -w, w: one box sum of the
+  // table, differenced exactly in int32, times w.  Each quadruplet is stored
+  // as its representative (dy >= 1, dx >= 1).
   int lds_pitch;                       // staged region row pitch; 0: no LDS tile kernel
   int n_quads;
-  int quad_dy[kMaxTaps / 4], quad_dx[kMaxTaps / 4];
-  double quad_w[kMaxTaps / 4];
-  int n_single;                        // taps without a symmetric quadruplet
-  int single_dy[kMaxTaps], single_dx[kMaxTaps];
-  double single_w[kMaxTaps];
+  int quad_dy[kMaxQuads], quad_dx[kMaxQuads];
+  float quad_w[kMaxQuads];
   float f_hi[kMaxTerms], f_lo[kMaxTerms];  // f_k = k / (2T) (u8: k / (2T 255)) as two floats
-  double a[kMaxTerms];                 // a_k
+  float a[kMaxTerms];                  // a_k
   int k_is_zero[kMaxTerms];            // term k = 0: one image (I), analytic denominator
   int slot[kMaxTerms];                 // first table of the term
   // table -> (term, part); part 0: C*I, 1: S*I, 2: C, 3: S, 4: I (k = 0)
@@ -88,9 +80,9 @@ struct DevTables {
   // the slot's term values again, indexed by slot, so that a lookup kernel
   // fetches them without first fetching the slot's term
   float slot_fhi[kMaxImages], slot_flo[kMaxImages];
-  double slot_a[kMaxImages];
+  float slot_a[kMaxImages];
   float gmax;                          // bound of |term value| for [0, span] input
-  double den_floor;
+  float den_floor;
   int in_u8;
   int n_images;
   // direct summation (true BF over the (2r+1)^2 window)
@@ -103,8 +95,8 @@ struct DevTables {
   // range-box regime for 8-bit input (T = T_r, Eq. 1D_box_N_terms)
   int range_box;
   int box_zr;                          // level window half-width floor(255 T_r), <= 255
-  double box_scale;                    // 2^q of the slab tables
-  double box_w[511];                   // W(d) = sum_k a_k cos(omega_k d / 255) [|d| <= zr] at d + 255
+  float box_scale;                     // 2^q of the slab tables
+  float box_w[511];                    // W(d) = sum_k a_k cos(omega_k d / 255) [|d| <= zr] at d + 255
   int reduced;                         // FP16 term images, tables built in LDS (BF_PREC_REDUCED)
   int level_fold;                      // range_box kernel with the window open (BF_FLAG_LEVEL_FOLD)
 };
@@ -128,15 +120,14 @@ Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat
 // else the largest of 512, 256, 128, 64 that gives >= 2048 term waves with a
 // table row of <= 768 columns (the smallest such tile otherwise).  Term values
 // are stored as round(v * 2^q) in int32 and tables are summed with wrapping
-// 32-bit adds.  When every tap belongs to a symmetric quadruplet
-// (box_edge = 2r + 1 > 0) the kernels only ever use box differences, which
-// are exact modulo 2^32, so q is the largest shift with
-// box_edge^2 (gmax 2^q + 1) <= 2^31 - 1 and does not depend on the tile; with
-// lone taps (box_edge = 0) raw table values are used and q keeps the whole
-// tile table in range: (tile + 2r)^2 (gmax 2^q + 1) <= 2^31 - 1.  q <= 24.
+// 32-bit adds.  Every tap belongs to a symmetric quadruplet, so the kernels
+// only ever use box differences, which are exact modulo 2^32 whenever the box
+// fits in int32: q is the largest shift (<= 24) with
+// (2r + 1)^2 (gmax 2^q (1 + 2^-20) + 1) <= 2^31 - 1 (the factor covers the
+// FP32 rounding of the products that are quantised), independent of the tile.
 // A pure function of its arguments, so every call path tiles an image alike.
-void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int box_edge,
-                   int *tile, int *sat_shift);
+void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int *tile,
+                   int *sat_shift);
 
 // Row pitch (int32 elements) of the LDS tile kernel's staged table region for
 // a region `width` columns wide: one of the compiled pitches, or 0 if none fits.
@@ -196,6 +187,8 @@ bf_status_t launch_batch(const BatchItem *items, int n, uint32_t *heads, void *s
 // Which lookup kernel a plan's images use: 1 the LDS tile kernel, 0 the
 // per-pixel kernel.
 int lookup_kernel_kind(const DevTables &h);
+bool kb_tile_eligible(const DevTables &h);
+bool kb_double_buffered(const DevTables &h);  // two staged regions fit in LDS
 
 // Optional per-kernel event recording (bf_profile_enable); kernel 0 / 1.
 void profile_mark(int kernel, int begin, void *stream);

@@ -43,8 +43,8 @@ namespace bf {
 struct ImageParams {
   int H, W, tile, radius, tiles_x, n_images, pitch, n_terms;
   long long table_elems;
-  float sat_scale;       // 2^q
-  double inv_sat_scale;  // 2^-q
+  float sat_scale;      // 2^q
+  float inv_sat_scale;  // 2^-q
 };
 
 // Phase of term k at intensity x in revolutions, reduced to about [-0.5, 0.5]:
@@ -262,8 +262,7 @@ __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageP
 // the LDS tile kernel): one thread per pixel, block 64 x 4 pixels, never
 // straddling a tile (tile % 64 == 0).  Table reads are raw buffer loads with
 // the table offset as a scalar; corners are clamped to [0, H] x [0, W].
-// Quadruplets are box sums differenced in int32 like the tile kernel; lone
-// taps use the table value itself.
+// Quadruplets are box sums differenced in int32 like the tile kernel.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
   // raw buffer (stride 0), word 3 = 0x00020000 on gfx9-family targets
@@ -279,6 +278,20 @@ __device__ __forceinline__ int load_i32(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 // entries have wrapped.
 __device__ __forceinline__ int box_of(int a, int b, int c, int d) {
   return (int)(((uint32_t)a - (uint32_t)b) - ((uint32_t)c - (uint32_t)d));
+}
+
+// Denominator of the k = 0 term at pixel (y, x): K~_s correlated with the
+// image of ones, whose box sums are the in-image areas of the quadruplets'
+// boxes (corners clamped to [0, H] x [0, W]), exact integers.
+__device__ __forceinline__ float k0_denominator(const DevTables *__restrict__ tab, int y, int x, int H, int W) {
+  float d0 = 0.0f;
+  for (int q = 0; q < tab->n_quads; ++q) {
+    const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
+    const int h = min(max(y + dy, 0), H) - min(max(y + 1 - dy, 0), H);
+    const int w = min(max(x + dx, 0), W) - min(max(x + 1 - dx, 0), W);
+    d0 = __builtin_fmaf(tab->quad_w[q], (float)(h * w), d0);
+  }
+  return d0;
 }
 
 template <bool U8>
@@ -301,63 +314,47 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
     const int Y = min(max(y + dy, 0), p.H) - oy, X = min(max(x + dx, 0), p.W) - ox;
     return (uint32_t)(Y * p.pitch + X) * 4u;
   };
-  const int nq = tab->n_quads, ns = tab->n_single;
+  const int nq = tab->n_quads;
 
   float px, xv;
   load_pixel<U8>(I, (long long)y * p.W + x, &px, &xv);
-  const double inv = p.inv_sat_scale;
-  double num = 0.0, den = 0.0;
+  const float inv = p.inv_sat_scale;
+  float num = 0.0f, den = 0.0f;
   for (int t = 0; t < p.n_terms; ++t) {
     const uint32_t sb = (uint32_t)tab->slot[t] * te4;
     const bool k0 = tab->k_is_zero[t] != 0;
     const int nimg = k0 ? 1 : 4;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int q = 0; q < nq; ++q) {
       const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
       const uint32_t oa = corner(dy, dx), ob = corner(1 - dy, dx);
       const uint32_t oc = corner(dy, 1 - dx), od = corner(1 - dy, 1 - dx);
-      const double w = tab->quad_w[q];
+      const float w = tab->quad_w[q];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         if (m >= nimg) break;
         const uint32_t so = sb + (uint32_t)m * te4;
         const int box = box_of(load_i32(rsrc, oa, so), load_i32(rsrc, ob, so), load_i32(rsrc, oc, so),
                                load_i32(rsrc, od, so));
-        s[m] = __builtin_fma(w, (double)box, s[m]);
+        s[m] = __builtin_fmaf(w, (float)box, s[m]);
       }
     }
-    for (int q = 0; q < ns; ++q) {
-      const uint32_t o = corner(tab->single_dy[q], tab->single_dx[q]);
-      const double w = tab->single_w[q];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        if (m >= nimg) break;
-        s[m] = __builtin_fma(w, (double)load_i32(rsrc, o, sb + (uint32_t)m * te4), s[m]);
-      }
-    }
-    const double a = tab->a[t];
+    const float a = tab->a[t];
     if (k0) {
-      // numerator a_0 (K * I); denominator a_0 (K * 1) from the clamped corner
-      // coordinates (the table of ones is (Y - oy)(X - ox))
-      double d0 = 0.0;
-      for (int i = 0; i < tab->n_taps4; ++i) {
-        const int Y = min(max(y + tab->tap_dy[i], 0), p.H) - oy;
-        const int X = min(max(x + tab->tap_dx[i], 0), p.W) - ox;
-        d0 = __builtin_fma(tab->tap_w[i], (double)(Y * X), d0);
-      }
-      num = __builtin_fma(a * (U8 ? 1.0 / 255.0 : inv), s[0], num);
-      den = __builtin_fma(a, d0, den);
+      // numerator a_0 (K * I); denominator a_0 (K * 1)
+      num = __builtin_fmaf(a * (U8 ? 1.0f / 255.0f : inv), s[0], num);
+      den = __builtin_fmaf(a, k0_denominator(tab, y, x, p.H, p.W), den);
       continue;
     }
     const float fr = phase_rev(tab->f_hi[t], tab->f_lo[t], px);
-    const double C = (double)__builtin_amdgcn_cosf(fr), S = (double)__builtin_amdgcn_sinf(fr);
-    num = __builtin_fma(a * inv, C * s[0] + S * s[1], num);
-    den = __builtin_fma(a * inv, C * s[2] + S * s[3], den);
+    const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
+    num = __builtin_fmaf(a * inv, C * s[0] + S * s[1], num);
+    den = __builtin_fmaf(a * inv, C * s[2] + S * s[3], den);
   }
   const long long idx = (long long)y * p.W + x;
-  out[idx] = den > tab->den_floor ? (float)(num / den) : xv;
-  if (num_out) num_out[idx] = (float)num;
-  if (den_out) den_out[idx] = (float)den;
+  out[idx] = den > tab->den_floor ? num / den : xv;
+  if (num_out) num_out[idx] = num;
+  if (den_out) den_out[idx] = den;
 }
 
 // ---------------------------------------------------------------------------
@@ -367,7 +364,7 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
 // the per-lane source columns -- from the workspace straight into LDS with
 // buffer-to-LDS loads (no registers, no vector instructions), then every
 // pixel reads its taps from LDS.  Symmetric quadruplets of taps are one box
-// sum differenced exactly in int32 and one FP64 FMA.  Each thread owns the
+// sum differenced exactly in int32 and one FP32 FMA.  Each thread owns the
 // pixels (wave + 16 i, lane), i < 4, of the tile: one precomputed LDS address
 // per quadruplet corner serves all four through instruction offsets.  When
 // two regions fit in LDS they are double-buffered with their rows
@@ -453,7 +450,7 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
   const uint32_t lb = (uint32_t)(wave * RS + lane) * 4u;
   const int nq = tab->n_quads;
   uint32_t qa[NQ][4];
-  double qw[NQ];
+  float qw[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     if (q < nq) {
@@ -466,12 +463,12 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
       qw[q] = tab->quad_w[q];
     } else {
       qa[q][0] = qa[q][1] = qa[q][2] = qa[q][3] = lb;
-      qw[q] = 0.0;
+      qw[q] = 0.0f;
     }
   }
 
   float pxv[PX];
-  double num[PX], den[PX];
+  float num[PX], den[PX];
 #pragma unroll
   for (int i = 0; i < PX; ++i) {
     const int y = y0 + wave + NW * i;
@@ -481,19 +478,19 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
       load_pixel<U8>(I, (long long)y * p.W + x, &px, &v);
       pxv[i] = px;
     }
-    num[i] = 0.0;
-    den[i] = 0.0;
+    num[i] = 0.0f;
+    den[i] = 0.0f;
   }
-  const double inv = p.inv_sat_scale;
+  const float inv = p.inv_sat_scale;
   float cs[PX], sn[PX];
 
-  // one table: box sums of every quadruplet (and lone taps), then the fold of
-  // Eq. 1D_N_terms into the numerator / denominator
+  // one table: box sums of every quadruplet, then the fold of Eq. 1D_N_terms
+  // into the numerator / denominator
   auto body = [&](int m, auto BUF) {
     constexpr uint32_t bo = decltype(BUF)::value * BSTEP;
     const int part = tab->slot_part[m];
     const float fhi = tab->slot_fhi[m], flo = tab->slot_flo[m];
-    const double at = tab->slot_a[m];
+    const float at = tab->slot_a[m];
     if (part == 0) {
 #pragma unroll
       for (int i = 0; i < PX; ++i) {
@@ -502,9 +499,9 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
         sn[i] = __builtin_amdgcn_sinf(fr);
       }
     }
-    double s[PX];
+    float s[PX];
 #pragma unroll
-    for (int i = 0; i < PX; ++i) s[i] = 0.0;
+    for (int i = 0; i < PX; ++i) s[i] = 0.0f;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
 #pragma unroll
@@ -512,7 +509,7 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
         const uint32_t o = i * PSTEP + bo;
         const int box = box_of(lds_ld(lds, qa[q][0] + o), lds_ld(lds, qa[q][1] + o),
                                lds_ld(lds, qa[q][2] + o), lds_ld(lds, qa[q][3] + o));
-        s[i] = __builtin_fma(qw[q], (double)box, s[i]);
+        s[i] = __builtin_fmaf(qw[q], (float)box, s[i]);
       }
     }
     // software pipeline of the quadruplet loop: the reads of two quadruplets
@@ -524,43 +521,31 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
       __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
     }
     __builtin_amdgcn_sched_group_barrier(0x002, 10 * PX, 0);
-    for (int q = 0; q < tab->n_single; ++q) {
-      const uint32_t a =
-          lb + (uint32_t)((tab->single_dy[q] - dy0) * RS + tab->single_dx[q] - dx0) * 4u + bo;
-      const double w = tab->single_w[q];
+    // the box sums are complete here (an empty statement that keeps the
+    // compiler from interleaving the pixels' quadruplet chains, which spills)
 #pragma unroll
-      for (int i = 0; i < PX; ++i) s[i] = __builtin_fma(w, (double)lds_ld(lds, a + i * PSTEP), s[i]);
-    }
+    for (int i = 0; i < PX; ++i) asm volatile("" : "+v"(s[i]));
     // the k = 0 table of 8-bit input holds bytes: scale 1/255 instead of 2^-q
-    const double ai = at * (U8 && part == 4 ? 1.0 / 255.0 : inv);
+    const float ai = at * (U8 && part == 4 ? 1.0f / 255.0f : inv);
 #pragma unroll
     for (int i = 0; i < PX; ++i) {
       if (part == 4) {
-        num[i] = __builtin_fma(ai, s[i], num[i]);
+        num[i] = __builtin_fmaf(ai, s[i], num[i]);
       } else if (part == 0) {
-        num[i] = __builtin_fma(ai * cs[i], s[i], num[i]);
+        num[i] = __builtin_fmaf(ai * cs[i], s[i], num[i]);
       } else if (part == 1) {
-        num[i] = __builtin_fma(ai * sn[i], s[i], num[i]);
+        num[i] = __builtin_fmaf(ai * sn[i], s[i], num[i]);
       } else if (part == 2) {
-        den[i] = __builtin_fma(ai * cs[i], s[i], den[i]);
+        den[i] = __builtin_fmaf(ai * cs[i], s[i], den[i]);
       } else {
-        den[i] = __builtin_fma(ai * sn[i], s[i], den[i]);
+        den[i] = __builtin_fmaf(ai * sn[i], s[i], den[i]);
       }
     }
     if (part == 4) {
-      // denominator of the k = 0 term: a_0 (K * 1) from the clamped corners
-      // (the table of ones is (Y - oy)(X - ox))
+      // denominator of the k = 0 term: a_0 (K * 1)
 #pragma unroll
-      for (int i = 0; i < PX; ++i) {
-        const int y = y0 + wave + NW * i;
-        double d0 = 0.0;
-        for (int q = 0; q < tab->n_taps4; ++q) {
-          const int Y = min(max(y + tab->tap_dy[q], 0), p.H) - oy;
-          const int X = min(max(x + tab->tap_dx[q], 0), p.W) - ox;
-          d0 = __builtin_fma(tab->tap_w[q], (double)(Y * X), d0);
-        }
-        den[i] = __builtin_fma(at, d0, den[i]);
-      }
+      for (int i = 0; i < PX; ++i)
+        den[i] = __builtin_fmaf(at, k0_denominator(tab, y0 + wave + NW * i, x, p.H, p.W), den[i]);
     }
   };
 
@@ -598,9 +583,9 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
     if (!xin || y >= p.H) continue;
     const long long idx = (long long)y * p.W + x;
     const float xv = U8 ? pxv[i] * (1.0f / 255.0f) : pxv[i];
-    out[idx] = den[i] > tab->den_floor ? (float)(num[i] / den[i]) : xv;
-    if (num_out) num_out[idx] = (float)num[i];
-    if (den_out) den_out[idx] = (float)den[i];
+    out[idx] = den[i] > tab->den_floor ? num[i] / den[i] : xv;
+    if (num_out) num_out[idx] = num[i];
+    if (den_out) den_out[idx] = den[i];
   }
 }
 
@@ -709,7 +694,7 @@ bf_status_t launch_direct(const DevTables &host, const void *I, float *out, floa
 // fold into one weight per level difference before the box sums:
 //   num(p) = sum_rect w_rect sum_{y in rect} W(L - Z(y)) I(y),
 //   den(p) = sum_rect w_rect sum_{y in rect} W(L - Z(y)),
-//   W(d) = sum_k a_k cos(omega_k d / 255) [|d| <= zr]   (tabulated in FP64),
+//   W(d) = sum_k a_k cos(omega_k d / 255) [|d| <= zr]   (tabulated on the host),
 // two tables per output level whatever the number of range terms.  One block
 // per 32 x 32 output tile stages the levels of the region its taps read; for
 // every level L among its outputs it builds both slab tables at once in LDS
@@ -767,7 +752,7 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   int *levels = cursor + 256;                                // [256]: the output levels present
   uint16_t *list = reinterpret_cast<uint16_t *>(levels + 256);        // [kZTile^2]: tile pixels by level
   uint8_t *lv = reinterpret_cast<uint8_t *>(sat);  // the region's levels, staged before the tables exist
-  const double scale = tab->box_scale;
+  const float scale = tab->box_scale;
   // wave w builds the region rows [w seg, (w + 1) seg) with sums restarting at
   // its first row; lane l holds the columns 2l, 2l + 1
   const int seg = (RS + kZWaves - 1) / kZWaves;
@@ -837,8 +822,8 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
     int2 *lut = luts + 264 * b;
     if (tid < 256) {
       const int z = tid;
-      const double w = tab->box_w[L - z + 255];  // zero outside the window
-      lut[z] = make_int2(__double2int_rn(w * (z * (1.0 / 255.0)) * scale), __double2int_rn(w * scale));
+      const float w = tab->box_w[L - z + 255];  // zero outside the window
+      lut[z] = make_int2(__float2int_rn(w * ((float)z * (1.0f / 255.0f)) * scale), __float2int_rn(w * scale));
     } else if (tid == 256) {
       lut[256] = make_int2(0, 0);
     }
@@ -906,23 +891,23 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
     for (int j = tid; j < cnt; j += kZThreads) {
       const int pi = list[s0 + j];
       const int py = ty0 + pi / kZTile, px = tx0 + pi % kZTile;
-      double num = 0.0, den = 0.0;
+      float num = 0.0f, den = 0.0f;
       for (int q = 0; q < nq; ++q) {
         const int dy = tab->quad_dy[q], dx = tab->quad_dx[q];
         const int Ya = min(max(py + dy, 0), H) - cy0, Yb = min(max(py + 1 - dy, 0), H) - cy0;
         const int Xa = min(max(px + dx, 0), W) - cx0, Xb = min(max(px + 1 - dx, 0), W) - cx0;
         const int2 a = corner(Ya, Xa), b = corner(Yb, Xa), c = corner(Ya, Xb), d = corner(Yb, Xb);
-        const double w = tab->quad_w[q];
-        num = __builtin_fma(w, (double)box_of(a.x, b.x, c.x, d.x), num);
-        den = __builtin_fma(w, (double)box_of(a.y, b.y, c.y, d.y), den);
+        const float w = tab->quad_w[q];
+        num = __builtin_fmaf(w, (float)box_of(a.x, b.x, c.x, d.x), num);
+        den = __builtin_fmaf(w, (float)box_of(a.y, b.y, c.y, d.y), den);
       }
-      const double inv = 1.0 / scale;
+      const float inv = 1.0f / scale;  // a power of two: exact
       num *= inv;
       den *= inv;
       const long long idx = (long long)py * W + px;
-      out[idx] = den > tab->den_floor ? (float)(num / den) : (float)L * (1.0f / 255.0f);
-      if (num_out) num_out[idx] = (float)num;
-      if (den_out) den_out[idx] = (float)den;
+      out[idx] = den > tab->den_floor ? num / den : (float)L * (1.0f / 255.0f);
+      if (num_out) num_out[idx] = num;
+      if (den_out) den_out[idx] = den;
     }
   }
 }
@@ -1014,7 +999,7 @@ __global__ __launch_bounds__(256) void kr_modulate(const void *__restrict__ I, i
 template <int TE, int NT, int NQ, bool U8>
 __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H, int W,
                                               const DevTables *__restrict__ tab,
-                                              const _Float16 *__restrict__ img, float scale, double inv_scale,
+                                              const _Float16 *__restrict__ img, float scale, float inv_scale,
                                               float *__restrict__ out, float *__restrict__ num_out,
                                               float *__restrict__ den_out) {
   constexpr int NW = NT / 64;              // waves: one row segment each
@@ -1061,7 +1046,7 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
   const uint32_t lb = (uint32_t)(prow * P + pcol);
   const int nq = tab->n_quads;
   uint32_t qa[NQ][4];
-  double qw[NQ];
+  float qw[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     if (q < nq) {
@@ -1074,11 +1059,11 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
       qw[q] = tab->quad_w[q];
     } else {
       qa[q][0] = qa[q][1] = qa[q][2] = qa[q][3] = lb * 4u;
-      qw[q] = 0.0;
+      qw[q] = 0.0f;
     }
   }
   float pxv[PPT], cs[PPT], sn[PPT];
-  double num[PPT], den[PPT];
+  float num[PPT], den[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
     const int y = ty0 + prow + RSTEP * i, x = tx0 + pcol;
@@ -1088,8 +1073,8 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
       load_pixel<U8>(I, (long long)y * W + x, &px, &v);
       pxv[i] = px;
     }
-    num[i] = 0.0;
-    den[i] = 0.0;
+    num[i] = 0.0f;
+    den[i] = 0.0f;
     cs[i] = sn[i] = 0.0f;
   }
 
@@ -1098,7 +1083,7 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
   for (int m = 0; m < n; ++m) {
     const int part = tab->slot_part[m];
     const float fhi = tab->slot_fhi[m], flo = tab->slot_flo[m];
-    const double at = tab->slot_a[m];
+    const float at = tab->slot_a[m];
     const float sc = (U8 && part == 4) ? 1.0f : scale;  // 8-bit k = 0: exact byte sums
     // the segment's fixed-point values and their column totals; the totals of
     // the segments above are the columns' carry into this segment
@@ -1142,9 +1127,9 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
         sn[i] = __builtin_amdgcn_sinf(fr);
       }
     }
-    double sv[PPT];
+    float sv[PPT];
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) sv[i] = 0.0;
+    for (int i = 0; i < PPT; ++i) sv[i] = 0.0f;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
 #pragma unroll
@@ -1152,30 +1137,24 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
         const uint32_t o = i * RSTEP * P * 4u;
         const int box = box_of(lds_ld(sat, qa[q][0] + o), lds_ld(sat, qa[q][1] + o),
                                lds_ld(sat, qa[q][2] + o), lds_ld(sat, qa[q][3] + o));
-        sv[i] = __builtin_fma(qw[q], (double)box, sv[i]);
+        sv[i] = __builtin_fmaf(qw[q], (float)box, sv[i]);
       }
     }
-    const double ai = at * (U8 && part == 4 ? 1.0 / 255.0 : inv_scale);
+    const float ai = at * (U8 && part == 4 ? 1.0f / 255.0f : inv_scale);
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
       if (part == 4) {
-        num[i] = __builtin_fma(ai, sv[i], num[i]);
-        // denominator of the k = 0 term from the clamped corners (table of ones)
-        const int y = ty0 + prow + RSTEP * i, x = tx0 + pcol;
-        double d0 = 0.0;
-        for (int k = 0; k < tab->n_taps4; ++k) {
-          const int Yc = min(max(y + tab->tap_dy[k], 0), H), Xc = min(max(x + tab->tap_dx[k], 0), W);
-          d0 = __builtin_fma(tab->tap_w[k], (double)Yc * (double)Xc, d0);
-        }
-        den[i] = __builtin_fma(at, d0, den[i]);
+        num[i] = __builtin_fmaf(ai, sv[i], num[i]);
+        // denominator of the k = 0 term (table of ones)
+        den[i] = __builtin_fmaf(at, k0_denominator(tab, ty0 + prow + RSTEP * i, tx0 + pcol, H, W), den[i]);
       } else if (part == 0) {
-        num[i] = __builtin_fma(ai * cs[i], sv[i], num[i]);
+        num[i] = __builtin_fmaf(ai * cs[i], sv[i], num[i]);
       } else if (part == 1) {
-        num[i] = __builtin_fma(ai * sn[i], sv[i], num[i]);
+        num[i] = __builtin_fmaf(ai * sn[i], sv[i], num[i]);
       } else if (part == 2) {
-        den[i] = __builtin_fma(ai * cs[i], sv[i], den[i]);
+        den[i] = __builtin_fmaf(ai * cs[i], sv[i], den[i]);
       } else {
-        den[i] = __builtin_fma(ai * sn[i], sv[i], den[i]);
+        den[i] = __builtin_fmaf(ai * sn[i], sv[i], den[i]);
       }
     }
   }
@@ -1185,9 +1164,9 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
     if (y >= H || x >= W) continue;
     const long long idx = (long long)y * W + x;
     const float xv = U8 ? pxv[i] * (1.0f / 255.0f) : pxv[i];
-    out[idx] = den[i] > tab->den_floor ? (float)(num[i] / den[i]) : xv;
-    if (num_out) num_out[idx] = (float)num[i];
-    if (den_out) den_out[idx] = (float)den[i];
+    out[idx] = den[i] > tab->den_floor ? num[i] / den[i] : xv;
+    if (num_out) num_out[idx] = num[i];
+    if (den_out) den_out[idx] = den[i];
   }
 }
 
@@ -1205,7 +1184,7 @@ size_t reduced_workspace_bytes(const DevTables &host, int H, int W) {
 
 template <int TE, int NT, bool U8>
 static hipError_t launch_kr_nq(int nq, dim3 grid, size_t lds, hipStream_t s, const void *I, int H, int W,
-                               const DevTables *dev, const _Float16 *img, float scale, double inv, float *out,
+                               const DevTables *dev, const _Float16 *img, float scale, float inv, float *out,
                                float *num, float *den) {
   auto go = [&](auto k) {
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1222,7 +1201,7 @@ bf_status_t launch_reduced(const DevTables *dev, const DevTables &host, const Ge
                            float *out, float *num, float *den, void *ws, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int te = reduced_tile(host);
-  if (te == 0 || host.n_quads > 12 || host.n_single != 0) return BF_ERR_UNSUPPORTED;
+  if (te == 0 || host.n_quads > 12) return BF_ERR_UNSUPPORTED;
   const int RS = te - 1 + host.tap_dy_max - host.tap_dy_min;
   const size_t lds = (size_t)(RS + 1 + 512 / 64) * kZPitch * 4;  // table and the waves' column totals
   _Float16 *img = static_cast<_Float16 *>(ws);
@@ -1238,7 +1217,7 @@ bf_status_t launch_reduced(const DevTables *dev, const DevTables &host, const Ge
   profile_mark(0, 0, stream);
   if (e != hipSuccess) return BF_ERR_DEVICE;
   const float scale = std::ldexp(1.0f, g.sat_shift);
-  const double inv = std::ldexp(1.0, -g.sat_shift);
+  const float inv = std::ldexp(1.0f, -g.sat_shift);
   const dim3 grid(((g.W + te - 1) / te) * ((g.H + te - 1) / te));
   profile_mark(1, 1, stream);
   e = host.in_u8 ? launch_kr_nq<32, 512, true>(host.n_quads, grid, lds, s, I, g.H, g.W, dev, img, scale, inv, out, num, den)
@@ -1367,7 +1346,7 @@ int lds_pitch_for(int width) {
 static size_t kb_region_bytes(const DevTables &h) {
   return (size_t)(64 + h.tap_dy_max - h.tap_dy_min) * h.lds_pitch * sizeof(int32_t);
 }
-static bool kb_double_buffered(const DevTables &h) {
+bool kb_double_buffered(const DevTables &h) {
   return h.lds_pitch == 128 && 2 * kb_region_bytes(h) <= 160 * 1024;
 }
 
@@ -1407,8 +1386,8 @@ static hipError_t launch_kb_tile_any(const DevTables &h, bool single, dim3 grid,
   }
 }
 
-void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int box_edge,
-                   int *tile, int *sat_shift) {
+void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int *tile,
+                   int *sat_shift) {
   int t = fixed_tile;
   if (!t) {
     t = 64;
@@ -1419,10 +1398,10 @@ void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double
       if (waves >= 2048) break;
     }
   }
-  const double E = box_edge > 0 ? (double)box_edge : t + 2.0 * radius;
+  const double E = 2.0 * radius + 1.0;
   const double lim = 2147483647.0 / (E * E);  // bound of |round(v 2^q)| per entry
   int q = 0;
-  while (q < 24 && gmax * std::ldexp(1.0, q + 1) + 1.0 <= lim) ++q;
+  while (q < 24 && gmax * std::ldexp(1.0, q + 1) * (1.0 + std::ldexp(1.0, -20)) + 1.0 <= lim) ++q;
   *tile = t;
   *sat_shift = q;
 }
@@ -1456,7 +1435,7 @@ static ImageParams image_params(const DevTables &host, const Geometry &g) {
   p.n_terms = host.n_terms;
   p.table_elems = (long long)g.table_elems;
   p.sat_scale = std::ldexp(1.0f, g.sat_shift);
-  p.inv_sat_scale = std::ldexp(1.0, -g.sat_shift);
+  p.inv_sat_scale = std::ldexp(1.0f, -g.sat_shift);
   return p;
 }
 
@@ -1466,7 +1445,7 @@ static int ka_chunks(const Geometry &g) {
   return (Ew + 255) / 256;
 }
 
-static bool kb_tile_eligible(const DevTables &h) {
+bool kb_tile_eligible(const DevTables &h) {
   return h.lds_pitch > 0 && kb_region_bytes(h) <= 160 * 1024 && h.n_quads <= 12;
 }
 
@@ -1682,8 +1661,7 @@ bf_status_t launch_batch(const BatchItem *items_all, int n_all, uint32_t *heads,
   for (int i = 0; i < n; ++i) order[i] = i;
   auto cost = [&](int i) {
     const BatchItem &it = items[i];
-    return (double)((it.g.W + 63) / 64) * ((it.g.H + 63) / 64) * it.host->n_images *
-           std::max(1, it.host->n_quads + it.host->n_single);
+    return (double)((it.g.W + 63) / 64) * ((it.g.H + 63) / 64) * it.host->n_images * std::max(1, it.host->n_quads);
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     if (items[a].host->in_u8 != items[b].host->in_u8) return items[a].host->in_u8 < items[b].host->in_u8;

@@ -42,9 +42,17 @@ def make_plans(reqs):
     return plans
 
 
+def _inputs_ready():
+    """The server's streams wait for no other stream: whatever produced the
+    inputs, or may still write the outputs, must be finished before submit."""
+    import torch
+    torch.cuda.synchronize()
+
+
 def run_open_loop(srv, reqs, plans, imgs, outs, t_scale=1.0):
     """Submit request i at t_arrive[i] * t_scale after the start; poll until
     every request completes.  Returns (completions by tag, makespan s)."""
+    _inputs_ready()
     n = len(reqs)
     done = {}
     t0 = time.perf_counter()
@@ -61,6 +69,7 @@ def run_open_loop(srv, reqs, plans, imgs, outs, t_scale=1.0):
 
 def run_closed_loop(srv, reqs, plans, imgs, outs):
     """Every request submitted at once; returns the makespan in seconds."""
+    _inputs_ready()
     done = {}
     t0 = time.perf_counter()
     for i, r in enumerate(reqs):

@@ -2,7 +2,7 @@
 
 Tolerance: max-abs 1e-4 on [0, 1] intensities against the expanded form
 (oracle T3 on whole images, T2 on sampled pixels at 4096^2).  The plain path
-keeps exact int32 tables and FP64 tap sums, so its error is far below that;
+keeps exact int32 tables and FP32 tap sums, so its error is far below that;
 the tests also assert a tighter 5e-5 to catch regressions early.
 """
 import numpy as np
@@ -78,6 +78,49 @@ def test_shapes_vs_oracle(torch_dev, H, W, tile, ss, r, ns, sr, nr):
     err = np.abs(out - ref).max()
     _report("%dx%d tile %d r %d" % (H, W, gp.geometry(H, W)[0], r), err)
     assert err <= TIGHT
+
+
+# Radii whose staged region (64 + 2r + 1 columns) selects each single-buffered
+# pitch class of the LDS tile lookup kernel, with 4, 8 and 12 quadruplets:
+# (H, W, sigma_s, r, N_s, sigma_r, N_r, pitch, quadruplets).
+WIDE_CASES = [
+    (300, 500, 13.0, 40, 6, 0.1, 16, 160, 8),
+    (301, 499, 15.0, 45, 8, 0.1, 8, 160, 12),
+    (290, 470, 17.0, 52, 4, 0.2, 8, 176, 4),
+    (310, 520, 20.0, 60, 6, 0.2, 8, 192, 8),
+    (257, 333, 21.0, 63, 8, 0.3, 8, 192, 12),
+]
+
+
+@pytest.mark.parametrize("H,W,ss,r,ns,sr,nr,pitch,nq", WIDE_CASES)
+def test_wide_regions_vs_oracle(torch_dev, H, W, ss, r, ns, sr, nr, pitch, nq):
+    """Every pitch class of the LDS tile kernel (regions wider than 128
+    columns, single-buffered) against T3 on whole images."""
+    I = synth.gen_image(H, W, 7, 0.03, 7 * r + H)
+    gp, op = _plans(ss, r, ns, sr, nr)
+    info = gp.info
+    assert (info.lookup_kernel, info.lds_pitch, info.lds_double_buffered, info.n_quads) == (1, pitch, 0, nq)
+    out = _run(torch_dev, gp, I)
+    ref = oracle.expanded_box(I, op)
+    err = np.abs(out - ref).max()
+    _report("%dx%d r %d pitch %d quads %d" % (H, W, r, pitch, nq), err)
+    assert err <= TIGHT
+
+
+def test_wide_regions_in_one_batch(torch_dev):
+    """All pitch classes (and a double-buffered plan) in one batch: each output
+    is bitwise its single-image result."""
+    import torch
+    bf = _bf()
+    plans, imgs = [], []
+    for (H, W, ss, r, ns, sr, nr, _, _) in WIDE_CASES + [(200, 260, 3.0, 9, 4, 0.1, 8, 128, 4)]:
+        plans.append(bf.Plan(ss, sr, r, nr, ns))
+        imgs.append(torch.from_numpy(synth.gen_image(H, W, 5, 0.03, 11 * r)).cuda())
+    singles = [bf.filter(p, I).clone() for p, I in zip(plans, imgs)]
+    outs = bf.filter_batch(plans, imgs)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(outs, singles)):
+        assert torch.equal(a, b), i
 
 
 def test_u8_input(torch_dev):
@@ -601,6 +644,7 @@ def test_served_mixed_plan_kinds(torch_dev):
     imgs = [torch.from_numpy(synth.gen_image_u8(h, w, 4, 0.03, 100 + i)).cuda() for i, (h, w) in enumerate(sizes)]
     which = [i % len(plans) for i in range(len(imgs))]
     outs = [torch.full(I.shape, -1.0, device="cuda") for I in imgs]
+    torch.cuda.synchronize()  # the server's streams do not wait for the fills and copies above
     srv = bf.Server(hbm_budget=1 << 30, max_batch=5, n_streams=2)
     for i, I in enumerate(imgs):
         srv.submit(plans[which[i]], I, outs[i], tag=i, now=0.0)

@@ -404,11 +404,16 @@ def test_tabulated_plan_rules():
     assert create(ks, kr, 0.01, flags=bf.BF_FLAG_HOST_ONLY | bf.BF_FLAG_DIRECT) == bf.BF_ERR_UNSUPPORTED
     p = bf.Plan.tabulated(ks, kr, 0.01, n_range=32, n_spatial=4, host_only=True, direct="auto")
     assert p.info.direct == 0
-    # a rough table keeps energy in fine Haar levels: more tap offsets per axis than the kernels take
-    rough = np.random.default_rng(1).uniform(0.1, 1.0, (10, 10))
+    # a rough table keeps energy in fine Haar levels: at r = 19 (levels up to
+    # 4) more tap offsets per axis than the kernels take
+    rough = np.random.default_rng(1).uniform(0.1, 1.0, (20, 20))
     rough = np.concatenate([rough[:0:-1], rough])
     rough = np.concatenate([rough[:, :0:-1], rough], axis=1)
     assert create(rough, kr, 0.01, n=(8, 6)) == bf.BF_ERR_UNSUPPORTED
+    # at r = 9 (levels up to 3) the same roughness gives 16 offsets per axis,
+    # 64 quadruplets: the per-pixel lookup kernel takes them
+    p = bf.Plan.tabulated(rough[10:29, 10:29], kr, 0.01, n_range=8, n_spatial=6, host_only=True)
+    assert p.info.n_taps == 256 and p.info.n_quads == 64 and p.info.lookup_kernel == 0
     # the other regimes take tables
     p = bf.Plan.tabulated(ks, K.tukey_range(0.2, 1 / 255.0), 1 / 255.0, n_range=5, n_spatial=4, dtype="u8",
                           range_box=True, host_only=True)
