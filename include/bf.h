@@ -204,6 +204,20 @@ bf_status_t bf_filter(bf_plan_t plan, const void *I, float *out, int H, int W, v
 bf_status_t bf_filter_ws(bf_plan_t plan, const void *I, float *out, int H, int W, void *ws,
                          size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): as
+ * bf_filter_ws, with the workspace taken from a device array of
+ * BF_NOALLOC_SCRATCH_BYTES (256 MiB) that the library holds on each GPU from
+ * its first use until the process ends.  Allocates nothing: no hipMalloc, no
+ * hipFree.  BF_ERR_INVALID_ARG, with nothing enqueued, when
+ * bf_workspace_size(plan, H, W) exceeds BF_NOALLOC_SCRATCH_BYTES.  Every call
+ * on one GPU uses that GPU's one array, which keeps the last call's tables:
+ * calls that overlap on one GPU (other streams, or other host threads without
+ * ordering) race, so order them on one stream.  The result is bitwise the
+ * one bf_filter_ws gives. */
+#define BF_NOALLOC_SCRATCH_BYTES (256ull << 20)
+bf_status_t bf_filter_noalloc(bf_plan_t plan, const void *I, float *out, int H, int W, void *stream);
+
 /* As bf_filter_ws, also writing the numerator and denominator of Eq. BF
  * (device float32 arrays of H*W; either may be NULL).  For validation. */
 bf_status_t bf_filter_parts(bf_plan_t plan, const void *I, float *out, float *num, float *den,

@@ -33,7 +33,9 @@ EXPORTED = [
     "bf_server_create", "bf_server_destroy", "bf_server_submit", "bf_server_poll", "bf_server_pending",
     "bf_server_stats", "bf_autotune", "bf_tuning_set", "bf_autotune_clear",
     "bf_precompute_size", "bf_precompute", "bf_precomputed_compatible", "bf_filter_precomputed",
+    "bf_filter_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class BFError(RuntimeError):
@@ -84,6 +86,7 @@ def lib():
         L.bf_workspace_size.argtypes = [vp, i, i, ctypes.POINTER(sz)]
         L.bf_filter.argtypes = [vp, vp, vp, i, i, vp]
         L.bf_filter_ws.argtypes = [vp, vp, vp, i, i, vp, sz, vp]
+        L.bf_filter_noalloc.argtypes = [vp, vp, vp, i, i, vp]
         L.bf_filter_parts.argtypes = [vp, vp, vp, vp, vp, i, i, vp, sz, vp]
         L.bf_batch_workspace_size.argtypes = [ctypes.POINTER(vp), i, ip, ip, ctypes.POINTER(sz)]
         L.bf_filter_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -316,6 +319,16 @@ def filter(plan, I, out=None, ws=None, stream=None, num=None, den=None):
                                ctypes.c_void_p(out.data_ptr()), nump, denp, H, W,
                                ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), s)
     _check(st, "bf_filter_parts")
+    return out
+
+
+def filter_noalloc(plan, I, out, stream=None):
+    """Filter one image into `out` with the library's per-GPU scratch array
+    as workspace (bf_filter_noalloc): no device memory is allocated."""
+    H, W = _image_args(plan, I)
+    st = lib().bf_filter_noalloc(plan.handle, ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 H, W, _stream_handle(stream))
+    _check(st, "bf_filter_noalloc")
     return out
 
 

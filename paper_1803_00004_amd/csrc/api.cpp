@@ -435,6 +435,18 @@ bf_status_t bf_filter(bf_plan_t plan, const void *I, float *out, int H, int W, v
                            static_cast<int32_t *>(plan->own_ws), stream);
 }
 
+bf_status_t bf_filter_noalloc(bf_plan_t plan, const void *I, float *out, int H, int W, void *stream) {
+  bf_status_t st = check_image(plan, I, out, H, W);
+  if (st != BF_OK) return st;
+  const bf::Geometry g = geometry_of(plan, H, W);
+  if (g.bytes > bf::kScratchBytes) return BF_ERR_INVALID_ARG;
+  void *ws = nullptr;
+  st = bf::scratch_workspace(&ws);
+  if (st != BF_OK) return st;
+  return bf::launch_filter(plan->dev_tables, plan->host_tables, g, I, out, nullptr, nullptr,
+                           static_cast<int32_t *>(ws), stream);
+}
+
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 bf_status_t bf_batch_workspace_size(const bf_plan_t *plans, int n, const int *H, const int *W,

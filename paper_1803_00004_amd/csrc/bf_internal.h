@@ -190,6 +190,12 @@ int lookup_kernel_kind(const DevTables &h);
 bool kb_tile_eligible(const DevTables &h);
 bool kb_double_buffered(const DevTables &h);  // two staged regions fit in LDS
 
+// Device workspace of bf_filter_noalloc: kScratchBytes of a static device
+// array, resolved once per device (the current one); BF_ERR_DEVICE if the
+// symbol cannot be resolved.
+constexpr size_t kScratchBytes = size_t(BF_NOALLOC_SCRATCH_BYTES);
+bf_status_t scratch_workspace(void **ptr);
+
 // Optional per-kernel event recording (bf_profile_enable); kernel 0 / 1.
 void profile_mark(int kernel, int begin, void *stream);
 

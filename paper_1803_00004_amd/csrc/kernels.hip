@@ -32,6 +32,7 @@
 
 #include <cstdint>
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -1297,6 +1298,32 @@ __global__ __launch_bounds__(1024) void kb_batch(BatchArgs a) {
     const BatchImage &im = a.img[found];
     kb_body<PITCH, NQ, DB, U8>(im.I, im.p, im.tab, im.ws, im.out, nullptr, nullptr, L);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free entry point: a file-scope device array
+// that every GPU the library runs on holds from module load to process end.
+// In host code `scratch` is only a stand-in for the symbol; its device
+// address on each GPU comes from hipGetSymbolAddress, taken once per device
+// with that device current and kept, and only that address is handed to
+// kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+bf_status_t scratch_workspace(void **ptr) {
+  static std::mutex mu;
+  static std::vector<void *> per_device;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return BF_ERR_DEVICE;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((size_t)dev >= per_device.size()) per_device.resize((size_t)dev + 1, nullptr);
+  if (!per_device[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BF_ERR_DEVICE;
+    per_device[dev] = p;
+  }
+  *ptr = per_device[dev];
+  return BF_OK;
 }
 
 // ---------------------------------------------------------------------------
