@@ -264,6 +264,12 @@ typedef struct {
   int lds_pitch;      /* LDS tile lookup kernel: row pitch (int32) of its staged table region
                          (128, 160, 176 or 192); 0 when the per-pixel kernel is used */
   int lds_double_buffered; /* 1: two staged regions fit in LDS (pitch 128) */
+  int lattice;        /* 1: the lattice lookup kernel applies (quadruplet rows on a lattice of step
+                         lattice_step <= 16, at most 4 rows and 4 columns of boxes) */
+  int lattice_step;
+  int default_lookup; /* lookup kernel of an untuned image: 0 per-pixel, 1 LDS tile double-buffered,
+                         2 LDS tile single-buffered, 3 lattice (where the LDS tile kernel does not
+                         apply: more than 12 quadruplets) */
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);
@@ -295,8 +301,9 @@ bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, i
 
 /* Autotuner.  Times the candidate launch shapes for H x W images under this
  * plan -- table tiles of 64, 128, 256 and 512 (tile + 2r + 1 <= 1024), each
- * with one range term or one table per table-kernel wave, and with the
- * lookup kernel double- and single-buffered where two staged regions fit --
+ * with one range term or one table per table-kernel wave, and with every
+ * lookup kernel the plan can use (LDS tile double- or single-buffered,
+ * lattice; all give the same bits) --
  * on a temporary mid-grey image (reps launches each, at least
  * 3) and keeps the fastest, process-wide, for the plan's shape class (the
  * radius, term and quadruplet counts, input type) and images in the same
@@ -310,8 +317,10 @@ bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, i
 bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, int *tile);
 /* Set the launch shape for this plan's shape class and H x W's size bucket
  * by hand, as bf_autotune would: table tile (a multiple of 64 with
- * tile + 2r + 1 <= 1024), kb_single (1: single-buffered lookup kernel),
- * ka_one (1: one table per table-kernel wave).  BF_ERR_UNSUPPORTED for plans
+ * tile + 2r + 1 <= 1024), kb_single (the lookup kernel: 0 the default
+ * choice, 1 the LDS tile kernel single-buffered, 2 the lattice kernel; a
+ * kernel the plan cannot use falls back to the default), ka_one (1: one table
+ * per table-kernel wave).  BF_ERR_UNSUPPORTED for plans
  * that are not tuned (a fixed tile, direct, range-box or reduced plans). */
 bf_status_t bf_tuning_set(bf_plan_t plan, int H, int W, int tile, int kb_single, int ka_one);
 /* Forget every tuned shape. */

@@ -61,7 +61,8 @@ class PlanInfo(ctypes.Structure):
                 ("den_floor", ctypes.c_double), ("n_quads", ctypes.c_int), ("n_single", ctypes.c_int),
                 ("lookup_kernel", ctypes.c_int), ("direct", ctypes.c_int), ("range_box", ctypes.c_int),
                 ("box_levels", ctypes.c_int), ("box_tile", ctypes.c_int), ("reduced", ctypes.c_int),
-                ("level_fold", ctypes.c_int), ("lds_pitch", ctypes.c_int), ("lds_double_buffered", ctypes.c_int)]
+                ("level_fold", ctypes.c_int), ("lds_pitch", ctypes.c_int), ("lds_double_buffered", ctypes.c_int),
+                ("lattice", ctypes.c_int), ("lattice_step", ctypes.c_int), ("default_lookup", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -238,6 +238,27 @@ bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, co
         }
       }
     }
+    // quadruplets in (dy, dx) order: every lookup kernel sums a pixel's box
+    // sums in this order, so they agree bit for bit
+    {
+      std::vector<int> ord(t.n_quads);
+      for (int q = 0; q < t.n_quads; ++q) ord[q] = q;
+      std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+        return t.quad_dy[a] != t.quad_dy[b] ? t.quad_dy[a] < t.quad_dy[b] : t.quad_dx[a] < t.quad_dx[b];
+      });
+      int dy[bf::kMaxQuads], dx[bf::kMaxQuads];
+      float w[bf::kMaxQuads];
+      for (int q = 0; q < t.n_quads; ++q) {
+        dy[q] = t.quad_dy[ord[q]];
+        dx[q] = t.quad_dx[ord[q]];
+        w[q] = t.quad_w[ord[q]];
+      }
+      for (int q = 0; q < t.n_quads; ++q) {
+        t.quad_dy[q] = dy[q];
+        t.quad_dx[q] = dx[q];
+        t.quad_w[q] = w[q];
+      }
+    }
     // Every expansion of a kernel that is even in dy and in dx (all kernels
     // the plans take: each Haar level group is symmetric on both axes) pairs
     // all of its taps; a tap left over would need raw table values, which
@@ -247,6 +268,47 @@ bf_status_t create_plan(const bf::KernelSpec &kern, int radius, bf_terms_t N, co
         delete p;
         return BF_ERR_UNSUPPORTED;
       }
+  }
+  // the quadruplets' row lattice (lattice lookup kernel): distinct dy in an
+  // arithmetic progression of step s; a step above 16 is split into d equal
+  // steps with empty rows between
+  {
+    std::vector<int> dys, dxs;
+    for (int q = 0; q < t.n_quads; ++q) {
+      dys.push_back(t.quad_dy[q]);
+      dxs.push_back(t.quad_dx[q]);
+    }
+    std::sort(dys.begin(), dys.end());
+    dys.erase(std::unique(dys.begin(), dys.end()), dys.end());
+    std::sort(dxs.begin(), dxs.end());
+    dxs.erase(std::unique(dxs.begin(), dxs.end()), dxs.end());
+    bool ok = dys.size() >= 2 && dxs.size() <= 4;
+    int step = ok ? dys[1] - dys[0] : 0;
+    for (size_t j = 1; ok && j < dys.size(); ++j) ok = dys[j] - dys[j - 1] == step;
+    int d = 1;
+    while (ok && step / d > 16) {
+      ++d;
+      while (step % d) ++d;
+    }
+    const int m = ok ? (int)(dys.size() - 1) * d + 1 : 0;
+    if (ok && m <= 4 && step / d >= 1) {
+      t.lat_s = step / d;
+      t.lat_m = m;
+      t.lat_dy0 = dys[0];
+      t.lat_n = dxs.size() <= 2 ? 2 : 4;
+      for (int i = 0; i < 4; ++i) t.lat_dx[i] = dxs[std::min<size_t>(i, dxs.size() - 1)];
+      for (int q = 0; q < t.n_quads; ++q) {
+        const int j = (t.quad_dy[q] - t.lat_dy0) / t.lat_s;
+        const int i = (int)(std::find(dxs.begin(), dxs.end(), t.quad_dx[q]) - dxs.begin());
+        t.lat_w[4 * j + i] = t.quad_w[q];
+        t.lat_mask |= 1 << (4 * j + i);
+      }
+      const int rw = 64 + t.tap_dx_max - t.tap_dx_min;
+      t.lat_pitch = rw <= 128 ? 128 : rw <= 192 ? 192 : 0;
+      t.lat_g = std::max(1, 16 / t.lat_s);
+      while (t.lat_g > 1 && bf::lattice_lds_bytes(t) > 160 * 1024) --t.lat_g;
+      t.lat = t.lat_pitch > 0 && bf::lattice_lds_bytes(t) <= 160 * 1024;
+    }
   }
   int slot = 0;
   for (int i = 0; i < t.n_terms; ++i) {
@@ -515,13 +577,15 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
     int tile, single, one;
   };
   std::vector<Cand> cands;
-  const bool db_fits = h.lds_pitch == 128;
   for (int t : {64, 128, 256, 512}) {
     if (t + 2 * r + 1 > 1024) continue;
     if ((t > 64 && (t / 2) >= std::max(H, W))) continue;  // one tile already covers the image
     for (int one = 0; one < 2; ++one) {
+      // the default lookup kernel, and each other one the plan can use
+      const int dflt = bf::lookup_kernel_for(h, 0);
       cands.push_back({t, 0, one});
-      if (db_fits) cands.push_back({t, 1, one});
+      if (bf::kb_tile_eligible(h) && dflt != 2) cands.push_back({t, 1, one});
+      if (bf::lattice_eligible(h) && dflt != 3) cands.push_back({t, 2, one});
     }
   }
   if (cands.empty()) cands.push_back({64, 0, 0});
@@ -584,7 +648,8 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
 
 bf_status_t bf_tuning_set(bf_plan_t plan, int H, int W, int tile, int kb_single, int ka_one) {
   if (!plan || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
-  if (tile < 64 || tile % 64 || tile + 2 * plan->fit.radius + 1 > 1024 || (kb_single | ka_one) & ~1)
+  if (tile < 64 || tile % 64 || tile + 2 * plan->fit.radius + 1 > 1024 || kb_single < 0 || kb_single > 2 ||
+      ka_one & ~1)
     return BF_ERR_INVALID_ARG;
   if (!tunable(plan)) return BF_ERR_UNSUPPORTED;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -671,7 +736,10 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
   info->reduced = plan->host_tables.reduced;
   info->n_single = 0;
   info->lds_pitch = bf::lookup_kernel_kind(plan->host_tables) ? plan->host_tables.lds_pitch : 0;
-  info->lds_double_buffered = bf::kb_double_buffered(plan->host_tables);
+  info->lds_double_buffered = bf::kb_tile_eligible(plan->host_tables) && bf::kb_double_buffered(plan->host_tables);
+  info->lattice = bf::lattice_eligible(plan->host_tables);
+  info->lattice_step = info->lattice ? plan->host_tables.lat_s : 0;
+  info->default_lookup = bf::lookup_kernel_for(plan->host_tables, 0);
   if (plan->host_tables.range_box) {
     info->sat_shift = (int)std::lround(std::log2((double)plan->host_tables.box_scale));
   } else {  // q depends on r and gmax only

@@ -18,7 +18,9 @@ constexpr int kMaxImages = 4 * kMaxTerms;  // term images (tables) per filter ca
 constexpr int kMaxChunks = 8;      // 256-column chunks of one table row (table width <= 2048)
 constexpr int kKA_Threads = 256;   // summed-area-table kernel block size (upper bound)
 constexpr int kMaxBatch = 24;      // images per batched launch (descriptors travel as kernel arguments)
-constexpr size_t kBatchHeadBytes = 256;  // batch workspace prefix: the K-B work-queue heads
+constexpr int kLatClasses = 12;            // lattice lookup kernel classes (pitch, rows, columns)
+constexpr int kBatchQueues = 8 * (2 + kLatClasses);  // K-B work queues of a batch: 8 per lookup class
+constexpr size_t kBatchHeadBytes = 1024;   // batch workspace prefix: the K-B work-queue heads
 constexpr int kMaxDirectRadius = 32;     // direct summation window limit
 constexpr int kMaxCellFitRadius = 511;   // non-separable K_s: Haar levels <= 8 (cell integrals)
 
@@ -68,6 +70,16 @@ struct DevTables {
   // table, differenced exactly in int32, times w.  Each quadruplet is stored
   // as its representative (dy >= 1, dx >= 1).
   int lds_pitch;                       // staged region row pitch; 0: no LDS tile kernel
+  // Row lattice of the quadruplets for the lattice lookup kernel (lat = 1):
+  // their dy take lat_m values dy_j = lat_dy0 + j lat_s (j < lat_m, lat_s <=
+  // 16; values between the plan's rows may carry no quadruplet), their dx the
+  // lat_n values lat_dx[i] (padded by repeating the last); the quadruplet
+  // (dy_j, lat_dx[i]) has weight lat_w[4 j + i] when bit 4 j + i of lat_mask
+  // is set.  lat_g lattice groups of lat_s waves compute; lat_pitch is the
+  // staged band's row pitch.
+  int lat, lat_s, lat_m, lat_n, lat_g, lat_pitch, lat_dy0, lat_mask;
+  int lat_dx[4];
+  float lat_w[16];
   int n_quads;
   int quad_dy[kMaxQuads], quad_dx[kMaxQuads];
   float quad_w[kMaxQuads];
@@ -110,7 +122,8 @@ struct Geometry {
   int E_max, pitch;                 // max table edge (tile + 2r + 1) and padded row pitch
   size_t table_elems;               // E_max * pitch per table
   size_t bytes;                     // whole workspace
-  int kb_single = 0;                // 1: single-buffered lookup kernel even where two regions fit
+  int kb_single = 0;                // lookup kernel: 0 the default choice, 1 the LDS tile kernel
+                                    // single-buffered, 2 the lattice kernel (lookup_kernel_for)
   int ka_one = 0;                   // 1: one table per table-kernel wave (else one range term)
 };
 
@@ -187,6 +200,13 @@ bf_status_t launch_batch(const BatchItem *items, int n, uint32_t *heads, void *s
 // Which lookup kernel a plan's images use: 1 the LDS tile kernel, 0 the
 // per-pixel kernel.
 int lookup_kernel_kind(const DevTables &h);
+// The lookup kernel an image runs: 0 per-pixel, 1 LDS tile double-buffered,
+// 2 LDS tile single-buffered, 3 lattice (Geometry.kb_single selects among
+// the eligible ones; 0 there: the LDS tile kernel where it applies, else the
+// lattice kernel where it applies).
+int lookup_kernel_for(const DevTables &h, int kb_single);
+bool lattice_eligible(const DevTables &h);
+size_t lattice_lds_bytes(const DevTables &h);
 bool kb_tile_eligible(const DevTables &h);
 bool kb_double_buffered(const DevTables &h);  // two staged regions fit in LDS
 

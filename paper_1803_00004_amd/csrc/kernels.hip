@@ -606,6 +606,276 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
 }
 
 // ---------------------------------------------------------------------------
+// K-B, lattice form.  For plans whose quadruplet rows lie on a lattice, dy_j
+// = dy_0 + j s (j < M), every thread owns U = 4 pixels of one column spaced
+// s rows apart: pixel u's top corner of row j (1 - dy_j) and pixel u''s with
+// u' - j' = u - j are the same table row, and likewise at the bottom, so the
+// U pixels' boxes read only U + M - 1 distinct rows per side, and each row's
+// difference between a box's right and left corner columns, h = S(row, R_i)
+// - S(row, L_i), is taken once and serves up to min(U, M) boxes:
+//   box(u, j, i) = h(bottom row u + j, i) - h(top row u + M - 1 - j, i),
+// exact in int32 like the four-corner form (the same integer).
+//
+// The staged region is cut into two bands, the rows of the top corners and
+// the rows of the bottom corners, which alternate between two LDS buffers:
+// the copy of the bottom band of table m runs while the top band is read
+// (its differences kept in registers), and the copy of the top band of table
+// m + 1 while the bottom band is read and folded, so the copies hide behind
+// the arithmetic even where two whole regions would not fit.  Within a band
+// the rows are stored by residue modulo s, so a thread's U + M - 1 rows are
+// consecutive and their offsets are instruction immediates.
+//
+// Output tiles are TR = s U G rows (G groups of s waves) by 64 columns,
+// clipped to the table tile they lie in.  The block has 16 waves: all copy,
+// the first s G compute.  Each pixel sums its boxes in (dy, dx) order, the
+// order of the plan's quadruplet list, so the result is bitwise that of the
+// LDS tile kernel.
+// ---------------------------------------------------------------------------
+constexpr int kLatU = 4;
+
+// Band buffers of the lattice kernel: two (three, with each band copied two
+// phases ahead, measured slower).
+constexpr int kLatBuffers = 2;
+
+size_t lattice_lds_bytes(const DevTables &h) {
+  const int KB = kLatU * h.lat_g + h.lat_m - 1;
+  return (size_t)kLatBuffers * h.lat_s * KB * h.lat_pitch * sizeof(int32_t);
+}
+
+// Output-tile grid of the lattice kernel for an image: rows of tiles per table
+// tile (nsub), tile rows in all (nty) and columns (ntx).
+struct LatGrid {
+  int TR, nsub, nty, ntx;
+};
+__host__ __device__ inline LatGrid lat_grid(int H, int W, int tile, int s, int g) {
+  LatGrid q;
+  q.TR = s * kLatU * g;
+  q.nsub = (tile + q.TR - 1) / q.TR;
+  const int tty = (H + tile - 1) / tile;
+  const int last = H - (tty - 1) * tile;
+  q.nty = (tty - 1) * q.nsub + (last + q.TR - 1) / q.TR;
+  q.ntx = (W + 63) / 64;
+  return q;
+}
+
+template <int PITCH, int M, int N, bool U8>
+__device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageParams &p,
+                                        const DevTables *__restrict__ tab,
+                                        const int32_t *__restrict__ ws, float *__restrict__ out,
+                                        float *__restrict__ num_out, float *__restrict__ den_out, int L) {
+  constexpr int U = kLatU;
+  constexpr int KR = U + M - 1;      // distinct corner rows per band and thread
+  constexpr uint32_t P4 = PITCH * 4u;
+  constexpr int CC = (PITCH + 63) / 64;
+  extern __shared__ int lds[];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int s = tab->lat_s, G = tab->lat_g;
+  const int KB = U * G + M - 1;      // band rows per residue
+  const int BR = s * KB;             // band rows
+  constexpr int NB = kLatBuffers;
+  const LatGrid lg = lat_grid(p.H, p.W, p.tile, s, G);
+  // XCD-aware patches of 8 x 4 tiles (as the LDS tile kernel)
+  constexpr int PW = 8, PH = 4;
+  const int pr = L / (PH * lg.ntx);
+  const int rem = L - pr * PH * lg.ntx;
+  const int ph = min(PH, lg.nty - pr * PH);
+  const int pc = rem / (PW * ph);
+  const int in = rem - pc * PW * ph;
+  const int pw = min(PW, lg.ntx - pc * PW);
+  const int bx = pc * PW + in % pw, by = pr * PH + in / pw;
+  const int tyt = by / lg.nsub, ksub = by - tyt * lg.nsub;
+  const int y0 = tyt * p.tile + ksub * lg.TR;                 // tile rows [y0, y1)
+  const int y1 = min(min(y0 + lg.TR, (tyt + 1) * p.tile), p.H);
+  const int x0 = bx * 64, txt = x0 / p.tile;
+  const int tile_id = tyt * p.tiles_x + txt;
+  const int oy = max(tyt * p.tile - p.radius, 0), ox = max(txt * p.tile - p.radius, 0);
+  const int dy0 = tab->tap_dy_min, dx0 = tab->tap_dx_min;
+  const int RW = 64 + tab->tap_dx_max - dx0;
+  const int dymax = tab->lat_dy0 + (M - 1) * s;
+  const int B0 = tab->lat_dy0 + dymax - 1;                     // region row of the bottom band's start
+  const int erows = (int)(p.table_elems / p.pitch);            // rows of a table
+  const uint32_t te4 = (uint32_t)p.table_elems * 4u;
+  const __amdgpu_buffer_rsrc_t rsrc =
+      make_rsrc(ws + (long long)tile_id * p.n_images * p.table_elems, te4 * (uint32_t)p.n_images);
+  const int x = x0 + lane;
+  const bool xin = x < p.W;
+
+  // Copies.  Band k is the top (k even) or bottom (k odd) band of table k / 2,
+  // in buffer k mod NB; its row R (region row R, or B0 + R) goes to LDS row
+  // (R mod s) KB + R div s.  Every wave copies rows wave, wave + 16, ...
+  uint32_t xoff4[CC];
+#pragma unroll
+  for (int c = 0; c < CC; ++c) xoff4[c] = (uint32_t)(min(max(x0 + dx0 + lane + 64 * c, 0), p.W) - ox) * 4u;
+  const uint32_t gp4 = (uint32_t)p.pitch * 4u;
+  const int QR = (BR + 15) / 16;
+  // where the region's columns need no clamp and start on a 16-byte boundary
+  // of the table, a row is one 16-byte copy per lane (lanes 0 .. RW/4)
+  const int cx0 = x0 + dx0 - ox;  // table column of region column 0
+  const bool wide = x0 + dx0 >= 0 && x0 + dx0 + RW - 1 <= p.W && (cx0 & 3) == 0;
+  const uint32_t xoff16 = (uint32_t)(cx0 + 4 * lane) * 4u;
+  const bool lane16 = 4 * lane < RW;
+  const int nchunk = (RW + 63) / 64;
+  auto stage = [&](int k) {
+    const int m = k >> 1, b = k & 1;
+    const uint32_t sm = (uint32_t)m * te4;
+    int *base = lds + (k % NB) * BR * PITCH;
+    int R = wave, rq = wave / s, rr = wave - (wave / s) * s;
+    for (int t = 0; t < QR && R < BR; ++t) {
+      const int Rc = R;
+      const int Y = min(min(max(y0 + dy0 + (b ? B0 : 0) + Rc, 0), p.H) - oy, erows - 1);
+      const uint32_t soff = sm + (uint32_t)Y * gp4;
+      int *dst = base + (rr * KB + rq) * PITCH;
+      if (wide) {
+        if (lane16) __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)dst, 16, xoff16, soff, 0, 0);
+      } else {
+#pragma unroll
+        for (int c = 0; c < CC; ++c)
+          if (c < nchunk && lane + 64 * c < RW)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)(dst + 64 * c), 4, xoff4[c], soff, 0, 0);
+      }
+      R += 16;
+      rq += 16 / s;
+      rr += 16 - (16 / s) * s;
+      if (rr >= s) {
+        rr -= s;
+        ++rq;
+      }
+    }
+  };
+
+  // this wave's pixels: group g, residue rho; pixel u at tile row g s U + rho + u s
+  const bool comp = wave < s * G;
+  const int g = comp ? wave / s : 0, rho = comp ? wave - (wave / s) * s : 0;
+  const int brow = rho * KB + g * U;  // LDS row of the thread's first corner row in a band
+  uint32_t aL0[N], aR0[N];            // LDS byte addresses in buffer 0, per column pair
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int dx = tab->lat_dx[i];
+    const uint32_t rb = (uint32_t)(brow * PITCH + lane) * 4u;
+    aL0[i] = rb + (uint32_t)(1 - dx - dx0) * 4u;
+    aR0[i] = rb + (uint32_t)(dx - dx0) * 4u;
+  }
+  float wq[M][N];
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+#pragma unroll
+    for (int i = 0; i < N; ++i) wq[j][i] = tab->lat_w[4 * j + i];
+
+  float pxv[U], num[U], den[U], d0[U], cs[U], sn[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int y = y0 + g * s * U + rho + u * s;
+    pxv[u] = 0.0f;
+    if (comp && xin && y < y1) {
+      float px, v;
+      load_pixel<U8>(I, (long long)y * p.W + x, &px, &v);
+      pxv[u] = px;
+    }
+    num[u] = den[u] = 0.0f;
+    d0[u] = comp ? k0_denominator(tab, y, x, p.H, p.W) : 0.0f;
+    cs[u] = sn[u] = 0.0f;
+  }
+  const float inv = p.inv_sat_scale;
+  int ht[KR][N];  // top-band differences of the current table
+
+  const int n = tab->n_images;  // this plan's tables (the workspace may hold more: p.n_images)
+  const int nbands = 2 * n;
+  stage(0);
+  __builtin_amdgcn_s_waitcnt(0);  // band 0 has landed
+  __syncthreads();
+  for (int k = 0; k < nbands; ++k) {
+    const bool ahead = k + NB - 1 < nbands;
+    if (ahead) stage(k + NB - 1);  // its buffer held band k - 1, which every wave has finished
+    const uint32_t bo = (uint32_t)((k % NB) * BR * PITCH) * 4u;
+    if (comp && !(k & 1)) {
+#pragma unroll
+      for (int kt = 0; kt < KR; ++kt)
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+          ht[kt][i] = (int)((uint32_t)lds_ld(lds, aR0[i] + bo + kt * P4) - (uint32_t)lds_ld(lds, aL0[i] + bo + kt * P4));
+    } else if (comp) {
+      const int m = k >> 1;
+      const int part = tab->slot_part[m];
+      const float fhi = tab->slot_fhi[m], flo = tab->slot_flo[m];
+      const float at = tab->slot_a[m];
+      if (part == 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const float fr = phase_rev(fhi, flo, pxv[u]);
+          cs[u] = __builtin_amdgcn_cosf(fr);
+          sn[u] = __builtin_amdgcn_sinf(fr);
+        }
+      }
+      float sv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) sv[u] = 0.0f;
+#pragma unroll
+      for (int kb = 0; kb < KR; ++kb) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          const uint32_t hb =
+              (uint32_t)lds_ld(lds, aR0[i] + bo + kb * P4) - (uint32_t)lds_ld(lds, aL0[i] + bo + kb * P4);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int j = kb - u;
+            if (j < 0 || j >= M) continue;
+            // pairs without a quadruplet carry weight 0 (adding 0 changes no bit)
+            const int box = (int)(hb - (uint32_t)ht[u + M - 1 - j][i]);
+            sv[u] = __builtin_fmaf(wq[j][i], (float)box, sv[u]);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) asm volatile("" : "+v"(sv[u]));
+      // the k = 0 table of 8-bit input holds bytes: scale 1/255 instead of 2^-q
+      const float ai = at * (U8 && part == 4 ? 1.0f / 255.0f : inv);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (part == 4) {
+          num[u] = __builtin_fmaf(ai, sv[u], num[u]);
+          den[u] = __builtin_fmaf(at, d0[u], den[u]);
+        } else if (part == 0) {
+          num[u] = __builtin_fmaf(ai * cs[u], sv[u], num[u]);
+        } else if (part == 1) {
+          num[u] = __builtin_fmaf(ai * sn[u], sv[u], num[u]);
+        } else if (part == 2) {
+          den[u] = __builtin_fmaf(ai * cs[u], sv[u], den[u]);
+        } else {
+          den[u] = __builtin_fmaf(ai * sn[u], sv[u], den[u]);
+        }
+      }
+    }
+    // band k + 1 has landed; after the barrier every wave's has, and every
+    // wave is done with band k
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  if (!comp || !xin) return;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int y = y0 + g * s * U + rho + u * s;
+    if (y >= y1) continue;
+    const long long idx = (long long)y * p.W + x;
+    const float xv = U8 ? pxv[u] * (1.0f / 255.0f) : pxv[u];
+    out[idx] = den[u] > tab->den_floor ? num[u] / den[u] : xv;
+    if (num_out) num_out[idx] = num[u];
+    if (den_out) den_out[idx] = den[u];
+  }
+}
+
+template <int PITCH, int M, int N, bool U8>
+__global__ __launch_bounds__(1024) void kl_tile(const void *__restrict__ I, ImageParams p,
+                                               const DevTables *__restrict__ tab,
+                                               const int32_t *__restrict__ ws,
+                                               float *__restrict__ out, float *__restrict__ num_out,
+                                               float *__restrict__ den_out, int n_tiles) {
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (L >= n_tiles) return;
+  kl_body<PITCH, M, N, U8>(I, p, tab, ws, out, num_out, den_out, L);
+}
+
+// ---------------------------------------------------------------------------
 // Direct summation of Eq. BF (the brute-force baseline of the paper): one
 // thread per pixel, 64 x 4 pixels per block; the block's image tile with an
 // r-pixel halo and the K_s window are staged in LDS.  Neighbours outside the
@@ -1261,7 +1531,7 @@ struct BatchArgs {
 
 template <int G, bool U8, bool ONE>
 __global__ __launch_bounds__(256) void ka_batch(BatchArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x < 16) a.heads[threadIdx.x] = 0u;  // two classes x 8 queues
+  if (blockIdx.x == 0 && threadIdx.x < kBatchQueues) a.heads[threadIdx.x] = 0u;  // every lookup class x 8 queues
   const int b = blockIdx.x;
   int i = 0;
   while (i + 1 < a.n && b >= a.ka_start[i + 1]) ++i;
@@ -1297,6 +1567,37 @@ __global__ __launch_bounds__(1024) void kb_batch(BatchArgs a) {
     }
     const BatchImage &im = a.img[found];
     kb_body<PITCH, NQ, DB, U8>(im.I, im.p, im.tab, im.ws, im.out, nullptr, nullptr, L);
+  }
+}
+
+// The lattice lookup kernel over a batch: as kb_batch, for the images of one
+// (pitch, M, N) class (each with its own lattice step and tile grid).
+template <int PITCH, int M, int N, bool U8>
+__global__ __launch_bounds__(1024) void kl_batch(BatchArgs a) {
+  __shared__ int item_sh;
+  int q = blockIdx.x & 7;
+  for (int exhausted = 0; exhausted < 8;) {
+    __syncthreads();  // the previous tile is done with LDS and item_sh
+    if (threadIdx.x == 0) item_sh = (int)atomicAdd(&a.heads[q], 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(item_sh);
+    int found = -1, L = 0, base = 0;
+    for (int i = 0; i < a.n; ++i) {
+      const int c = min(max(a.img[i].n_tiles - q * a.img[i].per_xcd, 0), a.img[i].per_xcd);
+      if (item < base + c) {
+        found = i;
+        L = q * a.img[i].per_xcd + (item - base);
+        break;
+      }
+      base += c;
+    }
+    if (found < 0) {  // queue q is empty: move on to the next XCD's queue
+      q = (q + 1) & 7;
+      ++exhausted;
+      continue;
+    }
+    const BatchImage &im = a.img[found];
+    kl_body<PITCH, M, N, U8>(im.I, im.p, im.tab, im.ws, im.out, nullptr, nullptr, L);
   }
 }
 
@@ -1476,7 +1777,56 @@ bool kb_tile_eligible(const DevTables &h) {
   return h.lds_pitch > 0 && kb_region_bytes(h) <= 160 * 1024 && h.n_quads <= 12;
 }
 
-int lookup_kernel_kind(const DevTables &h) { return kb_tile_eligible(h) ? 1 : 0; }
+int lookup_kernel_kind(const DevTables &h) { return kb_tile_eligible(h) || lattice_eligible(h) ? 1 : 0; }
+
+bool lattice_eligible(const DevTables &h) {
+  return h.lat && h.lat_pitch > 0 && lattice_lds_bytes(h) <= 160 * 1024;
+}
+
+int lookup_kernel_for(const DevTables &h, int kb_single) {
+  const bool tile = kb_tile_eligible(h), lat = lattice_eligible(h);
+  const bool db = tile && kb_double_buffered(h);
+  if (kb_single == 2 && lat) return 3;
+  if (kb_single == 1 && tile) return 2;
+  if (db) return 1;
+  if (tile) return 2;
+  return lat ? 3 : 0;
+}
+
+template <int PITCH, int M, int N, bool U8>
+static hipError_t launch_kl1(int n_tiles, size_t lds, hipStream_t s, const void *I, ImageParams p,
+                             const DevTables *tab, const int32_t *ws, float *out, float *num, float *den) {
+  auto k = kl_tile<PITCH, M, N, U8>;
+  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(8 * ((n_tiles + 7) / 8)), dim3(1024), lds, s, I, p, tab, ws, out, num, den, n_tiles);
+  return hipGetLastError();
+}
+
+template <int PITCH, bool U8>
+static hipError_t launch_kl_mn(const DevTables &h, int n_tiles, size_t lds, hipStream_t s, const void *I,
+                               ImageParams p, const DevTables *tab, const int32_t *ws, float *out, float *num,
+                               float *den) {
+  const bool n4 = h.lat_n > 2;
+  switch (h.lat_m) {
+    case 2: return n4 ? launch_kl1<PITCH, 2, 4, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den)
+                      : launch_kl1<PITCH, 2, 2, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den);
+    case 3: return n4 ? launch_kl1<PITCH, 3, 4, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den)
+                      : launch_kl1<PITCH, 3, 2, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den);
+    default: return n4 ? launch_kl1<PITCH, 4, 4, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den)
+                       : launch_kl1<PITCH, 4, 2, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den);
+  }
+}
+
+template <bool U8>
+static hipError_t launch_kl(const DevTables &h, const Geometry &g, hipStream_t s, const void *I, ImageParams p,
+                            const DevTables *tab, const int32_t *ws, float *out, float *num, float *den) {
+  const LatGrid lg = lat_grid(g.H, g.W, g.tile, h.lat_s, h.lat_g);
+  const int n_tiles = lg.nty * lg.ntx;
+  const size_t lds = lattice_lds_bytes(h);
+  return h.lat_pitch == 128 ? launch_kl_mn<128, U8>(h, n_tiles, lds, s, I, p, tab, ws, out, num, den)
+                            : launch_kl_mn<192, U8>(h, n_tiles, lds, s, I, p, tab, ws, out, num, den);
+}
 
 bf_status_t launch_tables(const DevTables *dev, const DevTables &host, const Geometry &g,
                           const void *I, int32_t *ws, void *stream) {
@@ -1502,10 +1852,14 @@ bf_status_t launch_lookup(const DevTables *dev, const DevTables &host, const Geo
   // LDS tile kernel when the staged region fits and the quadruplets' corner
   // addresses fit in registers, else the per-pixel kernel
   profile_mark(1, 1, stream);
-  if (kb_tile_eligible(host)) {
+  const int kind = lookup_kernel_for(host, g.kb_single);
+  if (kind == 3) {
+    e = host.in_u8 ? launch_kl<true>(host, g, s, I, p, dev, ws, out, num, den)
+                   : launch_kl<false>(host, g, s, I, p, dev, ws, out, num, den);
+  } else if (kind != 0) {
     const int n_tiles = ((g.W + 63) / 64) * ((g.H + 63) / 64);
     dim3 gt(8 * ((n_tiles + 7) / 8));
-    const bool single = g.kb_single != 0;
+    const bool single = kind == 2;
     e = host.in_u8 ? launch_kb_tile_any<true>(host, single, gt, s, I, p, dev, ws, out, num, den)
                    : launch_kb_tile_any<false>(host, single, gt, s, I, p, dev, ws, out, num, den);
   } else {
@@ -1556,6 +1910,38 @@ static hipError_t launch_kb_batch1(int blocks, size_t lds, hipStream_t s, const 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(blocks), dim3(1024), lds, s, a);
   return hipGetLastError();
+}
+
+template <int PITCH, int M, int N, bool U8>
+static hipError_t launch_kl_batch1(int blocks, size_t lds, hipStream_t s, const BatchArgs &a) {
+  auto k = kl_batch<PITCH, M, N, U8>;
+  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(1024), lds, s, a);
+  return hipGetLastError();
+}
+
+// the lattice class index (pitch, M, N) of a plan: 0 .. kLatClasses - 1
+static int lattice_class(const DevTables &h) {
+  return (h.lat_pitch == 128 ? 0 : 6) + (h.lat_m - 2) * 2 + (h.lat_n > 2 ? 1 : 0);
+}
+
+template <int PITCH, bool U8>
+static hipError_t launch_kl_batch_mn(int mn, int blocks, size_t lds, hipStream_t s, const BatchArgs &a) {
+  switch (mn) {
+    case 0: return launch_kl_batch1<PITCH, 2, 2, U8>(blocks, lds, s, a);
+    case 1: return launch_kl_batch1<PITCH, 2, 4, U8>(blocks, lds, s, a);
+    case 2: return launch_kl_batch1<PITCH, 3, 2, U8>(blocks, lds, s, a);
+    case 3: return launch_kl_batch1<PITCH, 3, 4, U8>(blocks, lds, s, a);
+    case 4: return launch_kl_batch1<PITCH, 4, 2, U8>(blocks, lds, s, a);
+    default: return launch_kl_batch1<PITCH, 4, 4, U8>(blocks, lds, s, a);
+  }
+}
+
+template <bool U8>
+static hipError_t launch_kl_batch(int cls, int blocks, size_t lds, hipStream_t s, const BatchArgs &a) {
+  return cls < 6 ? launch_kl_batch_mn<128, U8>(cls % 6, blocks, lds, s, a)
+                 : launch_kl_batch_mn<192, U8>(cls % 6, blocks, lds, s, a);
 }
 
 template <int PITCH, bool DB, bool U8>
@@ -1621,6 +2007,9 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
   }
+  // each image's lookup kernel, as its single-image call would choose it
+  int kind[kMaxBatch];
+  for (int j = 0; j < n; ++j) kind[j] = lookup_kernel_for(*items[idx[j]].host, items[idx[j]].g.kb_single);
   for (int cls = 0; cls < 2; ++cls) {
     BatchArgs kb{};
     kb.heads = heads + 8 * cls;
@@ -1628,9 +2017,7 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
     for (int j = 0; j < n; ++j) {
       const BatchItem &it = items[idx[j]];
       const DevTables &h = *it.host;
-      if (!kb_tile_eligible(h)) continue;
-      const bool db = kb_double_buffered(h) && !it.g.kb_single;
-      if (db != (cls == 0)) continue;
+      if (kind[j] != 1 + cls) continue;
       kb.img[kb.n++] = ka.img[j];
       pitch = std::max(pitch, h.lds_pitch);
       nq = std::max(nq, h.n_quads);
@@ -1648,9 +2035,36 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
       return BF_ERR_DEVICE;
     }
   }
+  // lattice kernels: one persistent launch per (pitch, M, N) class, queue
+  // heads 16 + 8 class onwards
+  for (int cls = 0; cls < kLatClasses; ++cls) {
+    BatchArgs kb{};
+    kb.heads = heads + 16 + 8 * cls;
+    int tiles = 0;
+    size_t lds = 0;
+    for (int j = 0; j < n; ++j) {
+      const BatchItem &it = items[idx[j]];
+      const DevTables &h = *it.host;
+      if (kind[j] != 3 || lattice_class(h) != cls) continue;
+      BatchImage im = ka.img[j];
+      const LatGrid lg = lat_grid(it.g.H, it.g.W, it.g.tile, h.lat_s, h.lat_g);
+      im.n_tiles = lg.nty * lg.ntx;
+      im.per_xcd = (im.n_tiles + 7) / 8;
+      kb.img[kb.n++] = im;
+      lds = std::max(lds, lattice_lds_bytes(h));
+      tiles += im.n_tiles;
+    }
+    if (kb.n == 0) continue;
+    const int grid = std::min(8 * ((tiles + 7) / 8), 8 * ((n_cu + 7) / 8));
+    e = u8 ? launch_kl_batch<true>(cls, grid, lds, s, kb) : launch_kl_batch<false>(cls, grid, lds, s, kb);
+    if (e != hipSuccess) {
+      profile_mark(1, 0, s);
+      return BF_ERR_DEVICE;
+    }
+  }
   for (int j = 0; j < n; ++j) {
     const BatchItem &it = items[idx[j]];
-    if (kb_tile_eligible(*it.host)) continue;
+    if (kind[j] != 0) continue;
     const BatchImage &im = ka.img[j];
     dim3 gb((it.g.W + 63) / 64, (it.g.H + 3) / 4), bb(256);
     e = u8 ? launch_kb<true>(gb, bb, s, it.I, im.p, it.dev, it.ws, it.out, nullptr, nullptr)

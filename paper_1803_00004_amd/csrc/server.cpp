@@ -153,7 +153,7 @@ void schedule(bf_server_s *s, double now) {
     if (stream < 0) return;
     // requests that can never fit complete with an error
     const Request &h = s->queue.front();
-    if (kAlign + h.ws > s->arena.cap) {
+    if (bf::kBatchHeadBytes + h.ws > s->arena.cap) {
       Batch b;
       b.id = -1;
       b.status = BF_ERR_OUT_OF_MEMORY;
@@ -164,7 +164,7 @@ void schedule(bf_server_s *s, double now) {
       continue;
     }
     const size_t room = s->arena.largest();
-    size_t need = kAlign;  // the batch's work-queue heads
+    size_t need = bf::kBatchHeadBytes;  // the batch's work-queue heads
     size_t take = 0;
     for (const Request &r : s->queue) {
       if ((int)take >= s->o.max_batch || need + r.ws > room) break;

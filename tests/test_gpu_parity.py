@@ -123,6 +123,71 @@ def test_wide_regions_in_one_batch(torch_dev):
         assert torch.equal(a, b), i
 
 
+# Plans whose quadruplet rows lie on a lattice, with the step s, the rows M
+# (after splitting steps above 16) and the LDS pitch of the lattice kernel:
+# (H, W, sigma_s, r, N_s, sigma_r, N_r, dtype, table tile, s).
+LATTICE_CASES = [
+    (300, 517, 16.0, 48, 8, 0.05, 32, "f32", 512, 12),   # M 4, N 4, pitch 192
+    (333, 290, 16.0, 48, 4, 0.1, 8, "u8", 128, 12),      # step 24 split in two (M 3); tiles clip at 128
+    (261, 389, 8.0, 24, 6, 0.1, 16, "f32", 64, 6),       # two groups of 6 waves, 64-row table tiles
+    (200, 300, 3.0, 9, 4, 0.1, 8, "u8", 64, 5),          # M 2, N 2, three groups
+    (130, 129, 2.0, 6, 4, 0.3, 8, "f32", 64, 3),         # five groups of 3 waves
+    (310, 520, 20.0, 60, 6, 0.2, 8, "f32", 256, 15),     # pitch 192, step 15
+    (7, 13, 16.0, 48, 8, 0.05, 32, "f32", 64, 12),       # image smaller than the window
+    (1, 1, 13.0, 40, 6, 0.1, 16, "f32", 64, 10),
+]
+
+
+@pytest.mark.parametrize("H,W,ss,r,ns,sr,nr,dt,tile,step", LATTICE_CASES)
+def test_lattice_kernel_vs_oracle(torch_dev, H, W, ss, r, ns, sr, nr, dt, tile, step):
+    """The lattice lookup kernel against T3, and bitwise against the LDS tile
+    kernel on the same tables (both sum each pixel's boxes in (dy, dx)
+    order)."""
+    import torch
+    bf = _bf()
+    I = synth.gen_image_u8(H, W, 5, 0.03, H + r) if dt == "u8" else synth.gen_image(H, W, 5, 0.03, H + r)
+    gp, op = bf.Plan(ss, sr, r, nr, ns, dtype=dt), oracle.make_plan(ss, r, ns, sr, nr)
+    assert gp.info.lattice == 1 and gp.info.lattice_step == step
+    dev = torch.from_numpy(np.ascontiguousarray(I)).cuda()
+    gp.set_tuning(H, W, tile, 2, 0)
+    lat = bf.filter(gp, dev).clone()
+    ref = oracle.expanded_box(I, op)
+    err = np.abs(lat.cpu().numpy().astype(np.float64) - ref).max()
+    _report("lattice %dx%d r %d s %d tile %d %s" % (H, W, r, step, tile, dt), err)
+    assert err <= TIGHT
+    gp.set_tuning(H, W, tile, 1, 1)  # LDS tile kernel, single-buffered (one table per table-kernel wave)
+    other = bf.filter(gp, dev)
+    torch.cuda.synchronize()
+    assert torch.equal(lat, other)
+    bf.lib().bf_autotune_clear()
+
+
+def test_lattice_plans_in_one_batch(torch_dev):
+    """Lattice plans of several classes (pitch, rows, columns) beside LDS tile
+    and per-pixel plans in one batch: each output is bitwise its single-image
+    result."""
+    import torch
+    bf = _bf()
+    specs = [(300, 517, 16.0, 48, 8, 0.05, 32), (333, 290, 16.0, 48, 4, 0.1, 8), (310, 520, 20.0, 60, 6, 0.2, 8),
+             (257, 301, 13.0, 40, 6, 0.1, 16), (200, 260, 3.0, 9, 4, 0.1, 8), (150, 170, 15.0, 45, 8, 0.1, 8),
+             (120, 90, 23.3, 70, 4, 0.1, 8)]
+    plans, imgs = [], []
+    for H, W, ss, r, ns, sr, nr in specs:
+        plans.append(bf.Plan(ss, sr, r, nr, ns))
+        imgs.append(torch.from_numpy(synth.gen_image(H, W, 5, 0.03, 3 * r + H)).cuda())
+    kinds = sorted(set(p.info.default_lookup for p in plans))
+    assert kinds == [0, 1, 2], kinds
+    for p, (H, W, *_) in zip(plans, specs):  # the lattice kernel for every plan that can use it
+        if p.info.lattice:
+            p.set_tuning(H, W, p.geometry(H, W)[0], 2, 0)
+    singles = [bf.filter(p, I).clone() for p, I in zip(plans, imgs)]
+    outs = bf.filter_batch(plans, imgs)
+    torch.cuda.synchronize()
+    bf.lib().bf_autotune_clear()
+    for i, (a, b) in enumerate(zip(outs, singles)):
+        assert torch.equal(a, b), i
+
+
 def test_u8_input(torch_dev):
     Iu = synth.gen_image_u8(200, 300, 8, 0.03, 9)
     gp, op = _plans(3.0, 9, 4, 0.1, 8, dtype="u8", tile=128)

@@ -229,7 +229,7 @@ def test_batch_workspace_is_the_sum_of_aligned_parts():
     plans = [ps[0], ps[1], ps[0]]
     total = bf.batch_workspace_size(plans, shapes)
     parts = [p.workspace_size(h, w) for p, (h, w) in zip(plans, shapes)]
-    assert total == 256 + sum((b + 255) // 256 * 256 for b in parts)
+    assert total == 1024 + sum((b + 255) // 256 * 256 for b in parts)  # 1024: the lookup work-queue heads
 
 
 def test_precomputed_tables_compatibility():
@@ -445,7 +445,7 @@ def test_empty_batch_is_a_no_op():
     hw = (ctypes.c_int * 1)()
     size = ctypes.c_size_t()
     assert L.bf_batch_workspace_size(plans, 0, hw, hw, ctypes.byref(size)) == bf.BF_OK
-    assert size.value == 256
+    assert size.value == 1024  # the lookup work-queue heads only
     ptrs = (vp * 1)()
     assert L.bf_filter_batch(plans, 0, ptrs, ptrs, hw, hw, None, 0, None) == bf.BF_OK
     assert L.bf_filter_batch(plans, -1, ptrs, ptrs, hw, hw, None, 0, None) == bf.BF_ERR_INVALID_ARG

@@ -46,11 +46,14 @@ def test_every_request_completes_once_in_fifo_batches():
     assert st.peak_batches_in_flight <= 2
 
 
+HEADS = 1024  # a batch's work-queue heads (bf_batch_workspace_size of an empty batch)
+
+
 def test_admission_keeps_the_arena_budget():
     plans = _plans()
     p = plans[16.0]
     one = (p.workspace_size(1500, 1500) + 255) // 256 * 256
-    budget = 256 + 2 * one + 1000  # room for two such requests at once, not three
+    budget = HEADS + 2 * one + 1000  # room for two such requests at once, not three
     srv = bf.Server(hbm_budget=budget, max_batch=8, n_streams=4, dry_run=True, dry_rate=1e9)
     for i in range(7):
         srv.submit(p, FAKE_I, FAKE_O, tag=i, now=0.0, H=1500, W=1500)
@@ -65,7 +68,7 @@ def test_admission_keeps_the_arena_budget():
 def test_oversized_request_fails_alone_and_does_not_block():
     plans = _plans()
     small = (plans[2.0].workspace_size(100, 100) + 255) // 256 * 256
-    srv = bf.Server(hbm_budget=256 + 4 * small, max_batch=8, n_streams=2, dry_run=True)
+    srv = bf.Server(hbm_budget=HEADS + 4 * small, max_batch=8, n_streams=2, dry_run=True)
     srv.submit(plans[16.0], FAKE_I, FAKE_O, tag=0, now=0.0, H=2048, W=2048)
     for i in range(1, 4):
         srv.submit(plans[2.0], FAKE_I, FAKE_O, tag=i, now=0.0, H=100, W=100)
