@@ -375,6 +375,28 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// The fold of one table's correlation s (Eq. 1D_N_terms): parts 0 and 1
+// (C I, S I) add a_k C s and a_k S s to the numerator, parts 2 and 3 (C, S)
+// the same to the denominator, part 4 (I of k = 0) a_0 s to the numerator.
+// The wave-uniform part picks the weights (an, ad) = (a, 0) or (0, a) and
+// the per-pixel factor; the other accumulator takes 0 * s, which leaves it
+// unchanged.  No branch selects the accumulator, so the per-pixel arrays stay
+// in registers (a branch that stores to num[i] or den[i] is merged by the
+// compiler into one store through a selected pointer, which puts both arrays
+// in scratch memory).
+__device__ __forceinline__ void fold_weights(int part, float a, float *an, float *ad) {
+  const bool to_num = part < 2 || part == 4;
+  *an = to_num ? a : 0.0f;
+  *ad = to_num ? 0.0f : a;
+}
+
+__device__ __forceinline__ void fold_table(int part, float an, float ad, float cs, float sn, float s,
+                                           float &num, float &den) {
+  const float f = part == 4 ? 1.0f : (part & 1) ? sn : cs;
+  num = __builtin_fmaf(an * f, s, num);
+  den = __builtin_fmaf(ad * f, s, den);
+}
+
 __device__ __forceinline__ int lds_ld(const int *lds, uint32_t byte_addr) {
   return *reinterpret_cast<const int *>(reinterpret_cast<const char *>(lds) + byte_addr);
 }
@@ -484,6 +506,8 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
   }
   const float inv = p.inv_sat_scale;
   float cs[PX], sn[PX];
+#pragma unroll
+  for (int i = 0; i < PX; ++i) cs[i] = sn[i] = 0.0f;
 
   // one table: box sums of every quadruplet, then the fold of Eq. 1D_N_terms
   // into the numerator / denominator
@@ -528,20 +552,10 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
     for (int i = 0; i < PX; ++i) asm volatile("" : "+v"(s[i]));
     // the k = 0 table of 8-bit input holds bytes: scale 1/255 instead of 2^-q
     const float ai = at * (U8 && part == 4 ? 1.0f / 255.0f : inv);
+    float an, ad;
+    fold_weights(part, ai, &an, &ad);
 #pragma unroll
-    for (int i = 0; i < PX; ++i) {
-      if (part == 4) {
-        num[i] = __builtin_fmaf(ai, s[i], num[i]);
-      } else if (part == 0) {
-        num[i] = __builtin_fmaf(ai * cs[i], s[i], num[i]);
-      } else if (part == 1) {
-        num[i] = __builtin_fmaf(ai * sn[i], s[i], num[i]);
-      } else if (part == 2) {
-        den[i] = __builtin_fmaf(ai * cs[i], s[i], den[i]);
-      } else {
-        den[i] = __builtin_fmaf(ai * sn[i], s[i], den[i]);
-      }
-    }
+    for (int i = 0; i < PX; ++i) fold_table(part, an, ad, cs[i], sn[i], s[i], num[i], den[i]);
     if (part == 4) {
       // denominator of the k = 0 term: a_0 (K * 1)
 #pragma unroll
@@ -829,20 +843,13 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
       for (int u = 0; u < U; ++u) asm volatile("" : "+v"(sv[u]));
       // the k = 0 table of 8-bit input holds bytes: scale 1/255 instead of 2^-q
       const float ai = at * (U8 && part == 4 ? 1.0f / 255.0f : inv);
+      float an, ad;
+      fold_weights(part, ai, &an, &ad);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (part == 4) {
-          num[u] = __builtin_fmaf(ai, sv[u], num[u]);
-          den[u] = __builtin_fmaf(at, d0[u], den[u]);
-        } else if (part == 0) {
-          num[u] = __builtin_fmaf(ai * cs[u], sv[u], num[u]);
-        } else if (part == 1) {
-          num[u] = __builtin_fmaf(ai * sn[u], sv[u], num[u]);
-        } else if (part == 2) {
-          den[u] = __builtin_fmaf(ai * cs[u], sv[u], den[u]);
-        } else {
-          den[u] = __builtin_fmaf(ai * sn[u], sv[u], den[u]);
-        }
+      for (int u = 0; u < U; ++u) fold_table(part, an, ad, cs[u], sn[u], sv[u], num[u], den[u]);
+      if (part == 4) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) den[u] = __builtin_fmaf(at, d0[u], den[u]);
       }
     }
     // band k + 1 has landed; after the barrier every wave's has, and every
@@ -1337,6 +1344,7 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
   float num[PPT], den[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
+    cs[i] = sn[i] = 0.0f;
     const int y = ty0 + prow + RSTEP * i, x = tx0 + pcol;
     pxv[i] = 0.0f;
     if (y < H && x < W) {
@@ -1412,21 +1420,15 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
       }
     }
     const float ai = at * (U8 && part == 4 ? 1.0f / 255.0f : inv_scale);
+    float an, ad;
+    fold_weights(part, ai, &an, &ad);
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      if (part == 4) {
-        num[i] = __builtin_fmaf(ai, sv[i], num[i]);
-        // denominator of the k = 0 term (table of ones)
+    for (int i = 0; i < PPT; ++i) fold_table(part, an, ad, cs[i], sn[i], sv[i], num[i], den[i]);
+    if (part == 4) {
+      // denominator of the k = 0 term (table of ones)
+#pragma unroll
+      for (int i = 0; i < PPT; ++i)
         den[i] = __builtin_fmaf(at, k0_denominator(tab, ty0 + prow + RSTEP * i, tx0 + pcol, H, W), den[i]);
-      } else if (part == 0) {
-        num[i] = __builtin_fmaf(ai * cs[i], sv[i], num[i]);
-      } else if (part == 1) {
-        num[i] = __builtin_fmaf(ai * sn[i], sv[i], num[i]);
-      } else if (part == 2) {
-        den[i] = __builtin_fmaf(ai * cs[i], sv[i], den[i]);
-      } else {
-        den[i] = __builtin_fmaf(ai * sn[i], sv[i], den[i]);
-      }
     }
   }
 #pragma unroll
