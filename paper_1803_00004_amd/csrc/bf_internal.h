@@ -209,6 +209,7 @@ bool lattice_eligible(const DevTables &h);
 size_t lattice_lds_bytes(const DevTables &h);
 bool kb_tile_eligible(const DevTables &h);
 bool kb_double_buffered(const DevTables &h);  // two staged regions fit in LDS
+bool kb_overlap_staged(const DevTables &h, int pitch);  // overlap staging applies at this pitch
 
 // Device workspace of bf_filter_noalloc: kScratchBytes of a static device
 // array, resolved once per device (the current one); BF_ERR_DEVICE if the

@@ -375,6 +375,32 @@ __global__ __launch_bounds__(256) void kb_lookup(const void *__restrict__ I, Ima
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// How the LDS tile kernel stages each table's region:
+// - single: copies straight into one LDS buffer after the barrier that ends
+//   the previous table;
+// - double: two interleaved LDS buffers, the next table's copy running while
+//   the current one is read;
+// - overlap: where two regions do not fit, two layouts that overlap, the
+//   second kOverlapBase(PITCH) rows below the first.  Tables alternate
+//   between them; the rows of the next table that fall outside the current
+//   one's are copied straight into LDS while it is read, the overlapping
+//   rows are loaded into registers meanwhile and written to LDS after the
+//   barrier that ends the current table.
+constexpr int kStageSingle = 0, kStageDouble = 1, kStageOverlap = 2;
+constexpr int kLdsBytes = 160 * 1024;
+// The second layout's first row: as far down as LDS allows for regions 15
+// rows shorter than the pitch (the shortest of the pitch's class), but with
+// the layout's byte offset plus a thread's pixel offsets (3 x 4 rows)
+// within an instruction offset, a multiple of 256 bytes (paired reads count
+// offsets in 256-byte units up to 255).  Regions up to kLdsBytes / (4 pitch)
+// - kOverlapBase(pitch) rows tall take overlap staging.
+__host__ __device__ constexpr int kOverlapBase(int pitch) {
+  int ob = kLdsBytes / (pitch * 4) - (pitch - 15);
+  while (ob > 0 && ((ob + 12) * pitch * 4 > 65535 || (ob * pitch * 4) % 256 != 0)) --ob;
+  return ob;
+}
+__host__ __device__ constexpr int kOverlapMaxRows(int pitch) { return kLdsBytes / (pitch * 4) - kOverlapBase(pitch); }
+
 // The fold of one table's correlation s (Eq. 1D_N_terms): parts 0 and 1
 // (C I, S I) add a_k C s and a_k S s to the numerator, parts 2 and 3 (C, S)
 // the same to the denominator, part 4 (I of k = 0) a_0 s to the numerator.
@@ -403,18 +429,24 @@ __device__ __forceinline__ int lds_ld(const int *lds, uint32_t byte_addr) {
 
 // One 64 x 64 output tile of one image; L is the tile's index in the
 // XCD-aware order (below).  Every thread of the block calls it.
-template <int PITCH, int NQ, bool DB, bool U8>
+template <int PITCH, int NQ, int ST, bool U8>
 __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageParams &p,
                                         const DevTables *__restrict__ tab,
                                         const int32_t *__restrict__ ws, float *__restrict__ out,
                                         float *__restrict__ num_out, float *__restrict__ den_out,
                                         int L) {
+  constexpr bool DB = ST == kStageDouble, OV = ST == kStageOverlap;
   constexpr int NW = 16;                          // waves
   constexpr int PX = 64 / NW;                     // rows of the tile per thread
   constexpr int RS = DB ? 2 * PITCH : PITCH;      // LDS row stride (int32 elements)
   constexpr int CC = (PITCH + 63) / 64;           // 64-column chunks of a staged row
-  constexpr uint32_t PSTEP = NW * RS * 4;         // bytes between a thread's pixels
-  constexpr uint32_t BSTEP = PITCH * 4;           // bytes from buffer 0 to buffer 1
+  constexpr int OB = OV ? kOverlapBase(PITCH) : 0;  // first row of the second layout
+  // a thread's pixels: tile rows wave + NW i, or with overlap staging
+  // 16 (wave / 4) + wave % 4 + 4 i (the second layout's offset and the
+  // pixels' offsets then both fit an instruction offset)
+  constexpr int PROW = OV ? 4 : NW;
+  constexpr uint32_t PSTEP = PROW * RS * 4;       // bytes between a thread's pixels
+  constexpr uint32_t BSTEP = (OV ? OB * PITCH : PITCH) * 4;  // bytes from buffer 0 to buffer 1
   extern __shared__ int lds[];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // XCD-aware order: XCD k takes the k-th contiguous eighth of the tiles
@@ -443,6 +475,7 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
       make_rsrc(ws + (long long)tile_id * p.n_images * p.table_elems, te4 * (uint32_t)p.n_images);
   const int x = x0 + lane;
   const bool xin = x < p.W;
+  const int prow0 = OV ? 16 * (wave >> 2) + (wave & 3) : wave;  // tile row of the thread's pixel 0
 
   // staging: wave w copies region rows w, w + NW, ...; lane l columns l,
   // l + 64, ...  The clamped source column is fixed per lane (vector offset),
@@ -452,25 +485,75 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
 #pragma unroll
   for (int c = 0; c < CC; ++c) xoff4[c] = (uint32_t)(min(max(x0 + dx0 + lane + 64 * c, 0), p.W) - ox) * 4u;
   const uint32_t gp4 = (uint32_t)p.pitch * 4u;
-  auto stage = [&](int m, int buf) {
-    const uint32_t sm = (uint32_t)m * te4;
-    for (int r = wave; r < RH; r += NW) {
-      const int Y = min(max(y0 + dy0 + r, 0), p.H) - oy;
-      const uint32_t soff = sm + (uint32_t)Y * gp4;
-      int *dst = lds + r * RS + buf * PITCH;
+  // where the region's columns need no clamp and start on a 16-byte boundary
+  // of the table, a row is one 16-byte copy per lane (lanes 0 .. RW / 4; the
+  // last lane's spare columns land in the row's padding)
+  const int cx0 = x0 + dx0 - ox;  // table column of region column 0
+  const bool wide = x0 + dx0 >= 0 && x0 + dx0 + RW - 1 <= p.W && (cx0 & 3) == 0;
+  const uint32_t xoff16 = (uint32_t)(cx0 + 4 * lane) * 4u;
+  const bool lane16 = 4 * lane < RW;
+  auto copy_row = [&](int *dst, uint32_t soff) {
+    if (wide) {
+      if (lane16) __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)dst, 16, xoff16, soff, 0, 0);
+    } else {
 #pragma unroll
       for (int c = 0; c < CC; ++c)
         if (lane + 64 * c < RW)
           __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)(dst + 64 * c), 4, xoff4[c], soff, 0, 0);
     }
   };
+  auto stage = [&](int m, int buf) {
+    const uint32_t sm = (uint32_t)m * te4;
+    for (int r = wave; r < RH; r += NW) {
+      const int Y = min(max(y0 + dy0 + r, 0), p.H) - oy;
+      copy_row(lds + r * RS + buf * PITCH, sm + (uint32_t)Y * gp4);
+    }
+  };
+
+  // overlap staging: region rows [r0, r1) of table m straight into LDS rows
+  // base + r; rows r0 + wave + NW i < r1 (i < RR) into registers and from
+  // there into LDS rows base + r
+  auto stage_rows = [&](int m, int base, int r0, int r1) {
+    const uint32_t sm = (uint32_t)m * te4;
+    for (int r = r0 + wave; r < r1; r += NW) {
+      const int Y = min(max(y0 + dy0 + r, 0), p.H) - oy;
+      copy_row(lds + (base + r) * PITCH, sm + (uint32_t)Y * gp4);
+    }
+  };
+  constexpr int RR = OV ? (kOverlapMaxRows(PITCH) - OB + NW - 1) / NW : 1;
+  int rv[RR][CC];
+  // (every register is loaded, rows past the range from clamped rows of the
+  // table, and only the range is written to LDS: a load under a condition
+  // would make the compiler wait for it to merge the register's two values)
+  auto fetch = [&](int m, int r0) {
+    const uint32_t sm = (uint32_t)m * te4;
+#pragma unroll
+    for (int i = 0; i < RR; ++i) {
+      const int r = r0 + wave + NW * i;
+      const int Y = min(max(y0 + dy0 + r, 0), p.H) - oy;
+      const uint32_t soff = sm + (uint32_t)Y * gp4;
+#pragma unroll
+      for (int c = 0; c < CC; ++c) rv[i][c] = load_i32(rsrc, xoff4[c], soff);
+    }
+  };
+  auto deposit = [&](int base, int r0, int r1) {
+#pragma unroll
+    for (int i = 0; i < RR; ++i) {
+      const int r = r0 + wave + NW * i;
+      if (r < r1) {
+#pragma unroll
+        for (int c = 0; c < CC; ++c)
+          if (lane + 64 * c < RW) lds[(base + r) * PITCH + lane + 64 * c] = rv[i][c];
+      }
+    }
+  };
 
   // LDS byte address of each quadruplet corner for this thread's pixel 0 in
   // buffer 0: region row r holds image row y0 + dy0 + r, so tap (dy, dx) of
-  // the pixel in tile row wave, column lane is at element
-  // (wave + dy - dy0) * RS + lane + dx - dx0.  Padding quadruplets read one
+  // the pixel in tile row prow0, column lane is at element
+  // (prow0 + dy - dy0) * RS + lane + dx - dx0.  Padding quadruplets read one
   // valid element four times with weight 0.
-  const uint32_t lb = (uint32_t)(wave * RS + lane) * 4u;
+  const uint32_t lb = (uint32_t)(prow0 * RS + lane) * 4u;
   const int nq = tab->n_quads;
   uint32_t qa[NQ][4];
   float qw[NQ];
@@ -494,7 +577,7 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
   float num[PX], den[PX];
 #pragma unroll
   for (int i = 0; i < PX; ++i) {
-    const int y = y0 + wave + NW * i;
+    const int y = y0 + prow0 + PROW * i;
     pxv[i] = 0.0f;
     if (xin && y < p.H) {
       float px, v;
@@ -508,6 +591,11 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
   float cs[PX], sn[PX];
 #pragma unroll
   for (int i = 0; i < PX; ++i) cs[i] = sn[i] = 0.0f;
+  // the pixels have landed before the table loop: otherwise the first use of
+  // a pixel inside the loop waits for every load in flight, the next table's
+  // region included
+#pragma unroll
+  for (int i = 0; i < PX; ++i) asm volatile("" ::"v"(pxv[i]));
 
   // one table: box sums of every quadruplet, then the fold of Eq. 1D_N_terms
   // into the numerator / denominator
@@ -537,15 +625,18 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
         s[i] = __builtin_fmaf(qw[q], (float)box, s[i]);
       }
     }
-    // software pipeline of the quadruplet loop: the reads of two quadruplets
-    // first, then the arithmetic of quadruplet q beside the reads of q + 2
-    __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+    // software pipeline of the quadruplet loop: the reads of D quadruplets
+    // first, then the arithmetic of quadruplet q beside the reads of q + D
+    // (D = 1 with overlap staging, whose registers also hold the next
+    // table's overlapping rows)
+    constexpr int D = OV ? 1 : 2;
+    __builtin_amdgcn_sched_group_barrier(0x100, 8 * D, 0);
 #pragma unroll
-    for (int q = 0; q + 2 < NQ; ++q) {
+    for (int q = 0; q + D < NQ; ++q) {
       __builtin_amdgcn_sched_group_barrier(0x002, 5 * PX, 0);
       __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x002, 10 * PX, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 5 * D * PX, 0);
     // the box sums are complete here (an empty statement that keeps the
     // compiler from interleaving the pixels' quadruplet chains, which spills)
 #pragma unroll
@@ -560,7 +651,7 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
       // denominator of the k = 0 term: a_0 (K * 1)
 #pragma unroll
       for (int i = 0; i < PX; ++i)
-        den[i] = __builtin_fmaf(at, k0_denominator(tab, y0 + wave + NW * i, x, p.H, p.W), den[i]);
+        den[i] = __builtin_fmaf(at, k0_denominator(tab, y0 + prow0 + PROW * i, x, p.H, p.W), den[i]);
     }
   };
 
@@ -583,6 +674,27 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
         body(m + 1, B1{});
       }
     }
+  } else if (OV) {
+    // table m in layout m & 1 (LDS rows (m & 1) OB + r).  Table m + 1 in
+    // layout 1: rows [nov, RH) fall below table m's rows, [0, nov) on them;
+    // in layout 0: rows [0, OB) fall above table m's rows, [OB, RH) on them
+    // (none when RH <= OB).
+    const int nov = max(RH - OB, 0);
+    stage_rows(0, 0, 0, RH);
+    for (int m = 0; m < n; ++m) {
+      const int b = m & 1;
+      __syncthreads();  // every wave is done reading table m - 1
+      if (m > 0) deposit(b ? OB : 0, b ? 0 : OB, b ? nov : RH);
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies and writes of table m are done
+      __syncthreads();                // table m is whole in LDS
+      // table m + 1 (the last table loads itself again, unused)
+      if (m + 1 < n) stage_rows(m + 1, b ? 0 : OB, b ? 0 : nov, b ? min(OB, RH) : RH);
+      fetch(min(m + 1, n - 1), b ? OB : 0);
+      // the loads of table m + 1 stay ahead of the reads of table m
+      __builtin_amdgcn_sched_barrier(0);
+      if (b) body(m, B1{});
+      else body(m, B0{});
+    }
   } else {
     for (int m = 0; m < n; ++m) {
       __syncthreads();  // every wave is done reading table m - 1
@@ -594,7 +706,7 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
   }
 #pragma unroll
   for (int i = 0; i < PX; ++i) {
-    const int y = y0 + wave + NW * i;
+    const int y = y0 + prow0 + PROW * i;
     if (!xin || y >= p.H) continue;
     const long long idx = (long long)y * p.W + x;
     const float xv = U8 ? pxv[i] * (1.0f / 255.0f) : pxv[i];
@@ -606,7 +718,7 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
 
 // Blocks are dispatched round-robin over the 8 XCDs: block b runs on XCD
 // b % 8 and takes the (b / 8)-th tile of that XCD's eighth.
-template <int PITCH, int NQ, bool DB, bool U8>
+template <int PITCH, int NQ, int ST, bool U8>
 __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, ImageParams p,
                                                const DevTables *__restrict__ tab,
                                                const int32_t *__restrict__ ws,
@@ -616,7 +728,7 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
   const int per_xcd = (n_tiles + 7) / 8;
   const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (L >= n_tiles) return;
-  kb_body<PITCH, NQ, DB, U8>(I, p, tab, ws, out, num_out, den_out, L);
+  kb_body<PITCH, NQ, ST, U8>(I, p, tab, ws, out, num_out, den_out, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -1543,7 +1655,7 @@ __global__ __launch_bounds__(256) void ka_batch(BatchArgs a) {
   ka_body<G, U8, ONE>(im.I, im.p, im.tab, const_cast<int32_t *>(im.ws), lb % tiles, lb / tiles);
 }
 
-template <int PITCH, int NQ, bool DB, bool U8>
+template <int PITCH, int NQ, int ST, bool U8>
 __global__ __launch_bounds__(1024) void kb_batch(BatchArgs a) {
   __shared__ int item_sh;
   int q = blockIdx.x & 7;
@@ -1568,7 +1680,7 @@ __global__ __launch_bounds__(1024) void kb_batch(BatchArgs a) {
       continue;
     }
     const BatchImage &im = a.img[found];
-    kb_body<PITCH, NQ, DB, U8>(im.I, im.p, im.tab, im.ws, im.out, nullptr, nullptr, L);
+    kb_body<PITCH, NQ, ST, U8>(im.I, im.p, im.tab, im.ws, im.out, nullptr, nullptr, L);
   }
 }
 
@@ -1679,25 +1791,42 @@ static size_t kb_region_bytes(const DevTables &h) {
 bool kb_double_buffered(const DevTables &h) {
   return h.lds_pitch == 128 && 2 * kb_region_bytes(h) <= 160 * 1024;
 }
+// overlap staging at pitch 160 and 176 (at 192 the overlap would take too
+// many registers), for regions it can hold
+bool kb_overlap_staged(const DevTables &h, int pitch) {
+  return (pitch == 160 || pitch == 176) && 64 + h.tap_dy_max - h.tap_dy_min <= kOverlapMaxRows(pitch);
+}
 
-template <int PITCH, int NQ, bool DB, bool U8>
+template <int PITCH, int NQ, int ST, bool U8>
 static hipError_t launch_kb_tile(dim3 grid, size_t lds, hipStream_t s, const void *I,
                                  ImageParams p, const DevTables *tab, const int32_t *ws, float *out,
                                  float *num, float *den) {
-  auto k = kb_tile<PITCH, NQ, DB, U8>;
+  auto k = kb_tile<PITCH, NQ, ST, U8>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, grid, dim3(1024), lds, s, I, p, tab, ws, out, num, den);
   return hipGetLastError();
 }
 
-template <int PITCH, bool DB, bool U8>
+template <int PITCH, int ST, bool U8>
 static hipError_t launch_kb_tile_nq(int nq, dim3 grid, size_t lds, hipStream_t s, const void *I,
                                     ImageParams p, const DevTables *tab, const int32_t *ws,
                                     float *out, float *num, float *den) {
-  if (nq <= 4) return launch_kb_tile<PITCH, 4, DB, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
-  if (nq <= 8) return launch_kb_tile<PITCH, 8, DB, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
-  return launch_kb_tile<PITCH, 12, DB, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+  if (nq <= 4) return launch_kb_tile<PITCH, 4, ST, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+  if (nq <= 8) return launch_kb_tile<PITCH, 8, ST, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+  return launch_kb_tile<PITCH, 12, ST, U8>(grid, lds, s, I, p, tab, ws, out, num, den);
+}
+
+template <int ST, bool U8>
+static hipError_t launch_kb_tile_pitch(int pitch, int nq, dim3 grid, size_t lds, hipStream_t s,
+                                       const void *I, ImageParams p, const DevTables *tab,
+                                       const int32_t *ws, float *out, float *num, float *den) {
+  switch (pitch) {
+    case 128: return launch_kb_tile_nq<128, ST, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    case 160: return launch_kb_tile_nq<160, ST, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    case 176: return launch_kb_tile_nq<176, ST, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    default: return launch_kb_tile_nq<192, ST, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+  }
 }
 
 template <bool U8>
@@ -1707,13 +1836,14 @@ static hipError_t launch_kb_tile_any(const DevTables &h, bool single, dim3 grid,
   const size_t lds = kb_region_bytes(h);
   const int nq = h.n_quads;
   if (!single && kb_double_buffered(h))
-    return launch_kb_tile_nq<128, true, U8>(nq, grid, 2 * lds, s, I, p, tab, ws, out, num, den);
-  switch (h.lds_pitch) {
-    case 128: return launch_kb_tile_nq<128, false, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
-    case 160: return launch_kb_tile_nq<160, false, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
-    case 176: return launch_kb_tile_nq<176, false, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
-    default: return launch_kb_tile_nq<192, false, U8>(nq, grid, lds, s, I, p, tab, ws, out, num, den);
+    return launch_kb_tile_nq<128, kStageDouble, U8>(nq, grid, 2 * lds, s, I, p, tab, ws, out, num, den);
+  if (kb_overlap_staged(h, h.lds_pitch)) {
+    const size_t lo = lds + (size_t)kOverlapBase(h.lds_pitch) * h.lds_pitch * sizeof(int32_t);
+    return h.lds_pitch == 160
+               ? launch_kb_tile_nq<160, kStageOverlap, U8>(nq, grid, lo, s, I, p, tab, ws, out, num, den)
+               : launch_kb_tile_nq<176, kStageOverlap, U8>(nq, grid, lo, s, I, p, tab, ws, out, num, den);
   }
+  return launch_kb_tile_pitch<kStageSingle, U8>(h.lds_pitch, nq, grid, lds, s, I, p, tab, ws, out, num, den);
 }
 
 void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int *tile,
@@ -1905,9 +2035,9 @@ static hipError_t launch_ka_batch(int G, bool one, int blocks, hipStream_t s, co
   return one ? launch_ka_batch1<U8, true>(G, blocks, s, a) : launch_ka_batch1<U8, false>(G, blocks, s, a);
 }
 
-template <int PITCH, int NQ, bool DB, bool U8>
+template <int PITCH, int NQ, int ST, bool U8>
 static hipError_t launch_kb_batch1(int blocks, size_t lds, hipStream_t s, const BatchArgs &a) {
-  auto k = kb_batch<PITCH, NQ, DB, U8>;
+  auto k = kb_batch<PITCH, NQ, ST, U8>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(blocks), dim3(1024), lds, s, a);
@@ -1946,23 +2076,32 @@ static hipError_t launch_kl_batch(int cls, int blocks, size_t lds, hipStream_t s
                  : launch_kl_batch_mn<192, U8>(cls % 6, blocks, lds, s, a);
 }
 
-template <int PITCH, bool DB, bool U8>
+template <int PITCH, int ST, bool U8>
 static hipError_t launch_kb_batch_nq(int nq, int blocks, size_t lds, hipStream_t s, const BatchArgs &a) {
-  if (nq <= 4) return launch_kb_batch1<PITCH, 4, DB, U8>(blocks, lds, s, a);
-  if (nq <= 8) return launch_kb_batch1<PITCH, 8, DB, U8>(blocks, lds, s, a);
-  return launch_kb_batch1<PITCH, 12, DB, U8>(blocks, lds, s, a);
+  if (nq <= 4) return launch_kb_batch1<PITCH, 4, ST, U8>(blocks, lds, s, a);
+  if (nq <= 8) return launch_kb_batch1<PITCH, 8, ST, U8>(blocks, lds, s, a);
+  return launch_kb_batch1<PITCH, 12, ST, U8>(blocks, lds, s, a);
+}
+
+template <int ST, bool U8>
+static hipError_t launch_kb_batch_pitch(int pitch, int nq, int blocks, size_t lds, hipStream_t s,
+                                        const BatchArgs &a) {
+  switch (pitch) {
+    case 128: return launch_kb_batch_nq<128, ST, U8>(nq, blocks, lds, s, a);
+    case 160: return launch_kb_batch_nq<160, ST, U8>(nq, blocks, lds, s, a);
+    case 176: return launch_kb_batch_nq<176, ST, U8>(nq, blocks, lds, s, a);
+    default: return launch_kb_batch_nq<192, ST, U8>(nq, blocks, lds, s, a);
+  }
 }
 
 template <bool U8>
-static hipError_t launch_kb_batch(int pitch, bool db, int nq, int blocks, size_t lds, hipStream_t s,
+static hipError_t launch_kb_batch(int pitch, int st, int nq, int blocks, size_t lds, hipStream_t s,
                                   const BatchArgs &a) {
-  if (db) return launch_kb_batch_nq<128, true, U8>(nq, blocks, lds, s, a);
-  switch (pitch) {
-    case 128: return launch_kb_batch_nq<128, false, U8>(nq, blocks, lds, s, a);
-    case 160: return launch_kb_batch_nq<160, false, U8>(nq, blocks, lds, s, a);
-    case 176: return launch_kb_batch_nq<176, false, U8>(nq, blocks, lds, s, a);
-    default: return launch_kb_batch_nq<192, false, U8>(nq, blocks, lds, s, a);
-  }
+  if (st == kStageDouble) return launch_kb_batch_nq<128, kStageDouble, U8>(nq, blocks, lds, s, a);
+  if (st == kStageOverlap)
+    return pitch == 160 ? launch_kb_batch_nq<160, kStageOverlap, U8>(nq, blocks, lds, s, a)
+                        : launch_kb_batch_nq<176, kStageOverlap, U8>(nq, blocks, lds, s, a);
+  return launch_kb_batch_pitch<kStageSingle, U8>(pitch, nq, blocks, lds, s, a);
 }
 
 // One chunk of at most kMaxBatch images of one input type.
@@ -2028,10 +2167,15 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
     }
     if (kb.n == 0) continue;
     const bool db = cls == 0;
-    const size_t lds = (size_t)rh * pitch * sizeof(int32_t) * (db ? 2 : 1);
+    // overlap staging when every image's region is no taller than the class pitch
+    const int st = db ? kStageDouble
+                   : (pitch == 160 || pitch == 176) && rh <= kOverlapMaxRows(pitch) && nq <= 8 ? kStageOverlap
+                                                                                             : kStageSingle;
+    const size_t lds = (size_t)(rh * (db ? 2 : 1) + (st == kStageOverlap ? kOverlapBase(pitch) : 0)) * pitch *
+                       sizeof(int32_t);
     const int grid = std::min(8 * ((tiles + 7) / 8), 8 * ((n_cu + 7) / 8));
-    e = u8 ? launch_kb_batch<true>(pitch, db, nq, grid, lds, s, kb)
-           : launch_kb_batch<false>(pitch, db, nq, grid, lds, s, kb);
+    e = u8 ? launch_kb_batch<true>(pitch, st, nq, grid, lds, s, kb)
+           : launch_kb_batch<false>(pitch, st, nq, grid, lds, s, kb);
     if (e != hipSuccess) {
       profile_mark(1, 0, s);
       return BF_ERR_DEVICE;
