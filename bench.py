@@ -127,6 +127,8 @@ def served_run(args, reqs, host_imgs, with_oracle):
     from paper_1803_00004_amd import bf, serve
 
     n = len(reqs)
+    fused = bool(getattr(args, "fused_batch", False))
+    bf.set_batch_fused(fused)  # process-wide: every batch of the server
     t0 = time.perf_counter()
     plans = serve.make_plans(reqs)
     plan_ms = (time.perf_counter() - t0) * 1e3
@@ -217,6 +219,7 @@ def served_run(args, reqs, host_imgs, with_oracle):
         "oracle_sample": "T2 (FP64 direct sum of the expanded form) at 64 random pixels of each of the first "
                          "32 requests, on the open-loop outputs",
         "plan_ms": round(plan_ms, 1),
+        "fused_batch": fused,
         "kernel_ms_total_open_loop": {"tables": round(kms[0], 3), "lookup": round(kms[1], 3)},
         "lookup_hbm_gbs_open_loop": round(kb_b / max(kms[1], 1e-9) / 1e6, 1),
         "with_direct_auto": {"requests_direct": n_direct,
@@ -673,6 +676,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (no error check)")
     ap.add_argument("--no-served", action="store_true", help="headline without the served stream")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (heuristic tiling)")
+    ap.add_argument("--fused-batch", action="store_true",
+                    help="served stream: each eligible batch as one fused launch (bf_batch_set_fused; "
+                         "its time is all counted as lookup)")
     ap.add_argument("--precision", choices=["plain", "reduced"], default="plain",
                     help="reduced: FP16 term images, tables built in LDS (single-image workloads)")
     ap.add_argument("--level-fold", action="store_true",

@@ -236,6 +236,20 @@ bf_status_t bf_batch_workspace_size(const bf_plan_t *plans, int n, const int *H,
 bf_status_t bf_filter_batch(const bf_plan_t *plans, int n, const void *const *I, float *const *out,
                             const int *H, const int *W, void *ws, size_t ws_bytes, void *stream);
 
+/* Batch launch form, process-wide (default 0).  0: a batch group of one input
+ * type is one table-kernel launch followed by persistent lookup launches, one
+ * per lookup kernel class.  1: where every image of a group is looked up by
+ * the LDS tile kernel (double-buffered, or with regions up to 164 rows at
+ * pitch 176), with at most 8 quadruplets and table rows of at most 1024
+ * columns, the group is ONE persistent launch (after a small counter-reset
+ * launch) that builds the tables and looks them up, an output tile starting
+ * as soon as the tables of its table tile are published (per-tile ready
+ * counters, release/acquire at device scope); other groups as with 0.
+ * Results are bitwise the same either way (Secs. III-IV).  The batch's first
+ * 40 workspace bytes are its queues, counters and error word.  Returns
+ * BF_ERR_INVALID_ARG for values other than 0 and 1. */
+bf_status_t bf_batch_set_fused(int fused);
+
 /* Plan introspection (host side; valid for BF_FLAG_HOST_ONLY plans too). */
 typedef struct {
   int radius;         /* window radius r */

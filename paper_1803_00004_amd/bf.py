@@ -33,7 +33,7 @@ EXPORTED = [
     "bf_server_create", "bf_server_destroy", "bf_server_submit", "bf_server_poll", "bf_server_pending",
     "bf_server_stats", "bf_autotune", "bf_tuning_set", "bf_autotune_clear",
     "bf_precompute_size", "bf_precompute", "bf_precomputed_compatible", "bf_filter_precomputed",
-    "bf_filter_noalloc",
+    "bf_filter_noalloc", "bf_batch_set_fused",
 ]
 NOALLOC_SCRATCH_BYTES = 256 << 20
 
@@ -88,6 +88,7 @@ def lib():
         L.bf_filter.argtypes = [vp, vp, vp, i, i, vp]
         L.bf_filter_ws.argtypes = [vp, vp, vp, i, i, vp, sz, vp]
         L.bf_filter_noalloc.argtypes = [vp, vp, vp, i, i, vp]
+        L.bf_batch_set_fused.argtypes = [i]
         L.bf_filter_parts.argtypes = [vp, vp, vp, vp, vp, i, i, vp, sz, vp]
         L.bf_batch_workspace_size.argtypes = [ctypes.POINTER(vp), i, ip, ip, ctypes.POINTER(sz)]
         L.bf_filter_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -331,6 +332,12 @@ def filter_noalloc(plan, I, out, stream=None):
                                  H, W, _stream_handle(stream))
     _check(st, "bf_filter_noalloc")
     return out
+
+
+def set_batch_fused(on):
+    """bf_batch_set_fused: run eligible batch groups as one fused launch
+    (tables and lookups in one persistent kernel), process-wide."""
+    _check(lib().bf_batch_set_fused(1 if on else 0), "bf_batch_set_fused")
 
 
 def batch_workspace_size(plans, shapes):

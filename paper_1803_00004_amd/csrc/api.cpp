@@ -562,6 +562,12 @@ bf_status_t bf_filter_batch(const bf_plan_t *plans, int n, const void *const *I,
   return bf::launch_batch(items.data(), n, static_cast<uint32_t *>(ws), stream);
 }
 
+bf_status_t bf_batch_set_fused(int fused) {
+  if (fused != 0 && fused != 1) return BF_ERR_INVALID_ARG;
+  bf::set_fused_batch(fused);
+  return BF_OK;
+}
+
 bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, int *tile_out) {
   if (!plan || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
   if (plan->flags & BF_FLAG_HOST_ONLY) return BF_ERR_INVALID_ARG;

@@ -121,6 +121,7 @@ struct Geometry {
   int tiles_y, tiles_x, n_images;
   int E_max, pitch;                 // max table edge (tile + 2r + 1) and padded row pitch
   size_t table_elems;               // E_max * pitch per table
+  size_t ready_off;                 // bytes of the tables; the fused batch's ready counters follow
   size_t bytes;                     // whole workspace
   int kb_single = 0;                // lookup kernel: 0 the default choice, 1 the LDS tile kernel
                                     // single-buffered, 2 the lattice kernel (lookup_kernel_for)
@@ -196,6 +197,8 @@ struct BatchItem {
 // kMaxBatch images of one input type.  `heads` is kBatchHeadBytes of device
 // memory for the K-B work queues.
 bf_status_t launch_batch(const BatchItem *items, int n, uint32_t *heads, void *stream);
+// bf_batch_set_fused: 1 runs eligible batch groups as one fused launch
+void set_fused_batch(int on);
 
 // Which lookup kernel a plan's images use: 1 the LDS tile kernel, 0 the
 // per-pixel kernel.

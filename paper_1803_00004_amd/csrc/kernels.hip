@@ -32,6 +32,7 @@
 
 #include <cstdint>
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -105,15 +106,15 @@ constexpr int kPF = 4;
 // ONE = false: a wave builds the 1 or 4 tables of one range term (one sin/cos
 // per pixel for all four); ONE = true: a wave builds one table (4x the waves
 // for the same tile, so larger tiles keep the chip busy).  Both store the
-// same integers.
-template <int G, bool U8, bool ONE>
-__device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageParams &p,
+// same integers.  One wave builds unit `unit` (a term, or with ONE a table)
+// of table tile tile_id.  DYN: the wave's 8-bit lookup table lives in the
+// dynamic LDS (the fused batch kernel), else in a static array of 4 waves.
+template <int G, bool U8, bool ONE, bool DYN>
+__device__ __forceinline__ void ka_unit(const void *__restrict__ I, const ImageParams &p,
                                         const DevTables *__restrict__ tab, int32_t *__restrict__ ws,
-                                        int tile_id, int unit_group) {
+                                        int tile_id, int unit) {
   // the wave index is uniform; saying so keeps per-term loads scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int unit = unit_group * 4 + wave;
-  if (unit >= (ONE ? p.n_images : p.n_terms)) return;
   const int term = ONE ? tab->slot_term[unit] : unit;
   const int part = ONE ? tab->slot_part[unit] : 0;  // ONE: the table's part (4: k = 0)
   const int ty = tile_id / p.tiles_x, tx = tile_id - ty * p.tiles_x;
@@ -132,15 +133,22 @@ __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageP
   // 8-bit input takes 256 values only: each wave tabulates its term's four
   // quantised values per byte value in LDS, with the very expressions of the
   // per-pixel path below (same integers), and looks them up per pixel.
-  __shared__ int4 lut8[4][256];
+  int4 *lut;
+  if constexpr (!DYN) {
+    __shared__ int4 lut8_s[4][256];
+    lut = lut8_s[wave];
+  } else {
+    extern __shared__ int4 lut8_d[];
+    lut = lut8_d + 256 * wave;
+  }
   if (U8 && !k0) {
     for (int b = lane; b < 256; b += 64) {
       const float px = (float)b;
       const float xs = px * (1.0f / 255.0f) * scale;
       const float fr = phase_rev(f_hi, f_lo, px);
       const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
-      lut8[wave][b] = make_int4(__float2int_rn(C * xs), __float2int_rn(S * xs), __float2int_rn(C * scale),
-                                __float2int_rn(S * scale));
+      lut[b] = make_int4(__float2int_rn(C * xs), __float2int_rn(S * xs), __float2int_rn(C * scale),
+                         __float2int_rn(S * scale));
     }
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's table is in LDS before it reads it
   }
@@ -205,7 +213,7 @@ __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageP
           v[0][c] = U8 ? (uint32_t)px : (uint32_t)__float2int_rn(xs);
           v[1][c] = v[2][c] = v[3][c] = 0;
         } else if (U8) {
-          const int4 e = lut8[wave][(int)px];
+          const int4 e = lut[(int)px];
           if (ONE) {
             v[0][c] = (uint32_t)(part == 0 ? e.x : part == 1 ? e.y : part == 2 ? e.z : e.w);
           } else {
@@ -249,6 +257,16 @@ __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageP
       }
     }
   }
+}
+
+// Blocks of 4 waves: wave w builds unit 4 unit_group + w of the tile.
+template <int G, bool U8, bool ONE>
+__device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageParams &p,
+                                        const DevTables *__restrict__ tab, int32_t *__restrict__ ws,
+                                        int tile_id, int unit_group) {
+  const int unit = unit_group * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (unit >= (ONE ? p.n_images : p.n_terms)) return;
+  ka_unit<G, U8, ONE, false>(I, p, tab, ws, tile_id, unit);
 }
 
 template <int G, bool U8, bool ONE>
@@ -427,8 +445,27 @@ __device__ __forceinline__ int lds_ld(const int *lds, uint32_t byte_addr) {
   return *reinterpret_cast<const int *>(reinterpret_cast<const char *>(lds) + byte_addr);
 }
 
+// The 64 x 64 output tile with index L in the XCD-aware order: XCD k takes
+// the k-th contiguous eighth of the tiles (L in [k per_xcd, (k + 1) per_xcd)),
+// walked in patches of 8 x 4 tiles, so the tiles one XCD runs at the same time
+// are neighbours whose staged halos overlap in that XCD's L2.  Patch rows of
+// PH tile rows (the last may be shorter); within one, patches of PW tile
+// columns (the last may be narrower); tiles row-major in a patch.
+__device__ __forceinline__ void kb_tile_origin(int L, int H, int W, int *y0, int *x0) {
+  const int ntx = (W + 63) / 64, nty = (H + 63) / 64;
+  constexpr int PW = 8, PH = 4;
+  const int pr = L / (PH * ntx);
+  const int rem = L - pr * PH * ntx;
+  const int ph = min(PH, nty - pr * PH);
+  const int pc = rem / (PW * ph);
+  const int in = rem - pc * PW * ph;
+  const int pw = min(PW, ntx - pc * PW);
+  *x0 = (pc * PW + in % pw) * 64;
+  *y0 = (pr * PH + in / pw) * 64;
+}
+
 // One 64 x 64 output tile of one image; L is the tile's index in the
-// XCD-aware order (below).  Every thread of the block calls it.
+// XCD-aware order (kb_tile_origin).  Every thread of the block calls it.
 template <int PITCH, int NQ, int ST, bool U8>
 __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageParams &p,
                                         const DevTables *__restrict__ tab,
@@ -449,22 +486,8 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
   constexpr uint32_t BSTEP = (OV ? OB * PITCH : PITCH) * 4;  // bytes from buffer 0 to buffer 1
   extern __shared__ int lds[];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // XCD-aware order: XCD k takes the k-th contiguous eighth of the tiles
-  // (L in [k per_xcd, (k + 1) per_xcd)), walked in patches of 8 x 4 tiles, so
-  // the tiles one XCD runs at the same time are neighbours whose staged
-  // halos overlap in that XCD's L2.
-  const int ntx = (p.W + 63) / 64, nty = (p.H + 63) / 64;
-  // patch rows of PH tile rows (the last may be shorter); within one, patches
-  // of PW tile columns (the last may be narrower); tiles row-major in a patch
-  constexpr int PW = 8, PH = 4;
-  const int pr = L / (PH * ntx);
-  const int rem = L - pr * PH * ntx;
-  const int ph = min(PH, nty - pr * PH);
-  const int pc = rem / (PW * ph);
-  const int in = rem - pc * PW * ph;
-  const int pw = min(PW, ntx - pc * PW);
-  const int bx = pc * PW + in % pw, by = pr * PH + in / pw;
-  const int x0 = bx * 64, y0 = by * 64;
+  int x0, y0;
+  kb_tile_origin(L, p.H, p.W, &y0, &x0);
   const int ty = y0 / p.tile, tx = x0 / p.tile;
   const int tile_id = ty * p.tiles_x + tx;
   const int oy = max(ty * p.tile - p.radius, 0), ox = max(tx * p.tile - p.radius, 0);
@@ -1684,6 +1707,112 @@ __global__ __launch_bounds__(1024) void kb_batch(BatchArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused batch: one persistent launch runs a batch's table building (phase A)
+// and its lookups (phase B).  Phase-A items are (image, table tile, 16 table
+// units -- range terms, or tables with ONE -- one per wave), from one queue
+// in image and tile order; phase-B items are 64 x 64 output tiles, from 8
+// per-XCD queues as in the batched lookup.  A block takes phase-A items until
+// their queue is empty, then phase-B items.  An output tile needs every table
+// of its table tile: each phase-A item publishes its tables (a release at
+// device scope) and then counts itself in its table tile's ready counter; a
+// phase-B item waits until that counter holds the tile's item count, then
+// acquires at device scope before it reads.  Every phase-A item has been
+// taken before any block waits, by a block that is running, so every wait
+// ends; the wait is bounded all the same (kReadySpin rounds), and one that
+// runs out sets the batch's error word and goes on.
+// ---------------------------------------------------------------------------
+constexpr int kReadySpin = 1 << 22;
+constexpr int kFusedUnits = 16;  // table units (range terms, or tables) per phase-A item: one per wave
+
+struct FusedArgs {
+  int n;
+  uint32_t *ctl;                // [0] phase-A queue, [1 .. 8] phase-B queues, [9] error word
+  int a_start[kMaxBatch + 1];   // phase-A items before image i
+  int groups[kMaxBatch];        // phase-A items per table tile
+  int db[kMaxBatch];            // 1: the double-buffered lookup body (pitch 128), 0: overlap-staged (176)
+  uint32_t *ready[kMaxBatch];   // per table tile: its phase-A items done
+  BatchImage img[kMaxBatch];
+};
+
+__global__ __launch_bounds__(256) void kf_reset(FusedArgs a) {
+  if (threadIdx.x < 10) a.ctl[threadIdx.x] = 0u;
+  for (int i = 0; i < a.n; ++i) {
+    const int tiles = a.img[i].p.tiles_x * ((a.img[i].p.H + a.img[i].p.tile - 1) / a.img[i].p.tile);
+    for (int t = threadIdx.x; t < tiles; t += blockDim.x) a.ready[i][t] = 0u;
+  }
+}
+
+template <int NQ, bool U8, int G, bool ONE>
+__global__ __launch_bounds__(1024) void kf_batch(FusedArgs a) {
+  __shared__ int item_sh;
+  const int n_a = a.a_start[a.n];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (;;) {
+    __syncthreads();  // the previous item is done with LDS and item_sh
+    if (threadIdx.x == 0) item_sh = (int)atomicAdd(&a.ctl[0], 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(item_sh);
+    if (item >= n_a) break;
+    int i = 0;
+    while (i + 1 < a.n && item >= a.a_start[i + 1]) ++i;
+    const BatchImage &im = a.img[i];
+    const int lb = item - a.a_start[i];
+    const int tile = lb / a.groups[i], grp = lb - tile * a.groups[i];
+    const int unit = grp * kFusedUnits + wave;
+    if (unit < (ONE ? im.p.n_images : im.p.n_terms))
+      ka_unit<G, U8, ONE, true>(im.I, im.p, im.tab, const_cast<int32_t *>(im.ws), tile, unit);
+    // every wave's table stores are done (the barrier waits for them); one
+    // release makes them visible to the device, then the item is counted
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(a.ready[i] + tile, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  int q = blockIdx.x & 7;
+  for (int exhausted = 0; exhausted < 8;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_sh = (int)atomicAdd(&a.ctl[1 + q], 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(item_sh);
+    int found = -1, L = 0, base = 0;
+    for (int i = 0; i < a.n; ++i) {
+      const int c = min(max(a.img[i].n_tiles - q * a.img[i].per_xcd, 0), a.img[i].per_xcd);
+      if (item < base + c) {
+        found = i;
+        L = q * a.img[i].per_xcd + (item - base);
+        break;
+      }
+      base += c;
+    }
+    if (found < 0) {  // queue q is empty: move on to the next XCD's queue
+      q = (q + 1) & 7;
+      ++exhausted;
+      continue;
+    }
+    const BatchImage &im = a.img[found];
+    int y0, x0;
+    kb_tile_origin(L, im.p.H, im.p.W, &y0, &x0);
+    const uint32_t *rdy = a.ready[found] + (y0 / im.p.tile) * im.p.tiles_x + x0 / im.p.tile;
+    const uint32_t need = (uint32_t)a.groups[found];
+    // every wave waits itself, so that its acquire follows its own read of the count
+    for (int k = 0;; ++k) {
+      if (__hip_atomic_load(rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) break;
+      if (k == kReadySpin) {
+        atomicOr(&a.ctl[9], 1u);  // every lane: no branch on the lane inside the loop
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (a.db[found])
+      kb_body<128, NQ, kStageDouble, U8>(im.I, im.p, im.tab, im.ws, im.out, nullptr, nullptr, L);
+    else
+      kb_body<176, NQ, kStageOverlap, U8>(im.I, im.p, im.tab, im.ws, im.out, nullptr, nullptr, L);
+  }
+}
+
 // The lattice lookup kernel over a batch: as kb_batch, for the images of one
 // (pitch, M, N) class (each with its own lattice step and tile grid).
 template <int PITCH, int M, int N, bool U8>
@@ -1879,7 +2008,9 @@ Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat
   g.E_max = tile + 2 * radius + 1;
   g.pitch = (g.E_max + 63) / 64 * 64;
   g.table_elems = (size_t)g.E_max * g.pitch;
-  g.bytes = (size_t)g.tiles_y * g.tiles_x * n_images * g.table_elems * sizeof(int32_t);
+  g.ready_off = (size_t)g.tiles_y * g.tiles_x * n_images * g.table_elems * sizeof(int32_t);
+  // the fused batch launch's ready counters, one per table tile (none without tables)
+  g.bytes = g.ready_off + (n_images ? ((size_t)g.tiles_y * g.tiles_x * sizeof(uint32_t) + 255) / 256 * 256 : 0);
   return g;
 }
 
@@ -2104,10 +2235,118 @@ static hipError_t launch_kb_batch(int pitch, int st, int nq, int blocks, size_t 
   return launch_kb_batch_pitch<kStageSingle, U8>(pitch, nq, blocks, lds, s, a);
 }
 
+template <int NQ, int G, bool U8, bool ONE>
+static hipError_t launch_kf1(int blocks, size_t lds, hipStream_t s, const FusedArgs &a) {
+  auto k = kf_batch<NQ, U8, G, ONE>;
+  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(1024), lds, s, a);
+  return hipGetLastError();
+}
+
+// one range term per table wave (ONE = false) for table rows of at most
+// 2 chunks, else one table per wave (fewer registers)
+template <int NQ, bool U8>
+static hipError_t launch_kf_g(int G, bool one, int blocks, size_t lds, hipStream_t s, const FusedArgs &a) {
+  if (!one) return G == 1 ? launch_kf1<NQ, 1, U8, false>(blocks, lds, s, a) : launch_kf1<NQ, 2, U8, false>(blocks, lds, s, a);
+  switch (G) {
+    case 1: return launch_kf1<NQ, 1, U8, true>(blocks, lds, s, a);
+    case 2: return launch_kf1<NQ, 2, U8, true>(blocks, lds, s, a);
+    case 3: return launch_kf1<NQ, 3, U8, true>(blocks, lds, s, a);
+    default: return launch_kf1<NQ, 4, U8, true>(blocks, lds, s, a);
+  }
+}
+
+// the counters and queues first (a fill kernel, so that the pair can be
+// captured in a graph), then the fused launch
+template <bool U8>
+static hipError_t launch_kf(int nq, int G, bool one, int blocks, size_t lds, hipStream_t s, const FusedArgs &a) {
+  hipLaunchKernelGGL(kf_reset, dim3(1), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return nq <= 4 ? launch_kf_g<4, U8>(G, one, blocks, lds, s, a) : launch_kf_g<8, U8>(G, one, blocks, lds, s, a);
+}
+
+// The fused launch takes a group whose every image is looked up by the LDS
+// tile kernel -- double-buffered at pitch 128, or overlap-staged at pitch 176
+// (regions up to kOverlapMaxRows(176) rows) -- with at most 8 quadruplets and
+// table rows of at most 4 chunks; *lds is then the launch's LDS.
+static std::atomic<int> g_fused_batch{0};  // bf_batch_set_fused
+
+void set_fused_batch(int on) { g_fused_batch.store(on); }
+
+static bool fused_eligible(const BatchItem *items, const int *idx, int n, const int *kind, int *nq, int *G,
+                           size_t *lds) {
+  if (!g_fused_batch.load()) return false;
+  *nq = 0;
+  *G = 1;
+  *lds = 0;
+  for (int j = 0; j < n; ++j) {
+    const BatchItem &it = items[idx[j]];
+    const DevTables &h = *it.host;
+    const int rh = 64 + h.tap_dy_max - h.tap_dy_min, rw = 64 + h.tap_dx_max - h.tap_dx_min;
+    if (kind[j] == 1)
+      *lds = std::max(*lds, (size_t)2 * rh * 128 * sizeof(int32_t));
+    else if (kind[j] == 2 && rw <= 176 && rh <= kOverlapMaxRows(176))
+      *lds = std::max(*lds, (size_t)(kOverlapBase(176) + rh) * 176 * sizeof(int32_t));
+    else
+      return false;
+    *nq = std::max(*nq, h.n_quads);
+    *G = std::max(*G, ka_chunks(it.g));
+  }
+  if (items[idx[0]].host->in_u8) *lds = std::max(*lds, (size_t)kFusedUnits * 256 * sizeof(int4));  // a lookup table per wave
+  return *nq <= 8 && *G <= 4;
+}
+
 // One chunk of at most kMaxBatch images of one input type.
 static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, int n, uint32_t *heads,
                                       hipStream_t s) {
   const bool u8 = items[idx[0]].host->in_u8 != 0;
+  int dev = 0, n_cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+  }
+  // each image's lookup kernel, as its single-image call would choose it
+  int kind[kMaxBatch];
+  for (int j = 0; j < n; ++j) kind[j] = lookup_kernel_for(*items[idx[j]].host, items[idx[j]].g.kb_single);
+  {
+    int nq, G;
+    size_t lds;
+    if (fused_eligible(items, idx, n, kind, &nq, &G, &lds)) {
+      FusedArgs f{};
+      f.n = n;
+      f.ctl = heads;
+      // a range term per table wave as the images were tuned, where the rows allow
+      bool one = G > 2;
+      for (int j = 0; j < n; ++j) one = one || items[idx[j]].g.ka_one != 0;
+      int a_items = 0, b_tiles = 0;
+      for (int j = 0; j < n; ++j) {
+        const BatchItem &it = items[idx[j]];
+        BatchImage &im = f.img[j];
+        im.I = it.I;
+        im.out = it.out;
+        im.ws = it.ws;
+        im.tab = it.dev;
+        im.p = image_params(*it.host, it.g);
+        im.n_tiles = ((it.g.W + 63) / 64) * ((it.g.H + 63) / 64);
+        im.per_xcd = (im.n_tiles + 7) / 8;
+        f.groups[j] = ((one ? it.host->n_images : it.host->n_terms) + kFusedUnits - 1) / kFusedUnits;
+        f.db[j] = kind[j] == 1;
+        f.ready[j] = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(it.ws) + it.g.ready_off);
+        f.a_start[j] = a_items;
+        a_items += it.g.tiles_y * it.g.tiles_x * f.groups[j];
+        b_tiles += im.n_tiles;
+      }
+      f.a_start[n] = a_items;
+      const int blocks = std::min(8 * ((std::max(a_items, b_tiles) + 7) / 8), 8 * ((n_cu + 7) / 8));
+      profile_mark(1, 1, s);
+      hipError_t e =
+          u8 ? launch_kf<true>(nq, G, one, blocks, lds, s, f) : launch_kf<false>(nq, G, one, blocks, lds, s, f);
+      profile_mark(1, 0, s);
+      return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
+    }
+  }
   BatchArgs ka{};
   ka.n = n;
   ka.heads = heads;
@@ -2143,14 +2382,6 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
   // of its class, with its own 8 queue heads; the others run the per-pixel
   // kernel one by one.
   profile_mark(1, 1, s);
-  int dev = 0, n_cu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
-  }
-  // each image's lookup kernel, as its single-image call would choose it
-  int kind[kMaxBatch];
-  for (int j = 0; j < n; ++j) kind[j] = lookup_kernel_for(*items[idx[j]].host, items[idx[j]].g.kb_single);
   for (int cls = 0; cls < 2; ++cls) {
     BatchArgs kb{};
     kb.heads = heads + 8 * cls;

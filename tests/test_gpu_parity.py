@@ -306,6 +306,95 @@ def test_mixed_batch_is_bitwise_single(torch_dev):
     assert err <= TIGHT
 
 
+def _fused_group(torch, dtype, seed):
+    """A batch group the fused launch takes: double-buffered lookups (radius
+    6, 12, 24) beside overlap-staged ones (radius 48, pitch 176), 4 and 6
+    spatial terms, ragged sizes over several table tiles and a 1x1 image."""
+    bf = _bf()
+    rng = np.random.default_rng(seed)
+    plans, imgs = [], []
+    for i, (ss, ns, nr, sr) in enumerate([(2.0, 4, 8, 0.2), (16.0, 4, 16, 0.1), (8.0, 6, 16, 0.1),
+                                          (4.0, 4, 32, 0.05), (16.0, 4, 8, 0.3), (2.0, 6, 8, 0.2)]):
+        H, W = (1, 1) if i == 5 else (int(rng.integers(40, 700)), int(rng.integers(40, 700)))
+        plans.append(bf.Plan(ss, sr, int(3 * ss), nr, ns, dtype=dtype))
+        if dtype == "u8":
+            imgs.append(torch.from_numpy(synth.gen_image_u8(H, W, 6, 0.03, seed + i)).cuda())
+        else:
+            imgs.append(torch.from_numpy(synth.gen_image(H, W, 6, 0.03, seed + i)).cuda())
+    return plans, imgs
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8"])
+def test_fused_batch_is_bitwise_single(torch_dev, dtype):
+    """bf_batch_set_fused(1): the group runs as one persistent launch whose
+    lookups wait on per-table-tile ready counters; every output equals its
+    single-image call bit for bit, twice in a row with new inputs (the
+    counters are reset per launch), no wait runs out (the workspace's error
+    word stays 0), and one member is checked against the oracle."""
+    import torch
+    bf = _bf()
+    plans, imgs = _fused_group(torch, dtype, 40 if dtype == "f32" else 60)
+    shapes = [tuple(I.shape) for I in imgs]
+    ws = torch.zeros(bf.batch_workspace_size(plans, shapes), dtype=torch.uint8, device="cuda")
+    bf.set_batch_fused(True)
+    try:
+        for rep in range(2):
+            if rep:
+                imgs = [I.flip(0).contiguous() for I in imgs]
+            singles = [bf.filter(p, I).clone() for p, I in zip(plans, imgs)]
+            outs = bf.filter_batch(plans, imgs, ws=ws)
+            torch.cuda.synchronize()
+            for i, (o, s1) in enumerate(zip(outs, singles)):
+                assert torch.equal(o, s1), (rep, i)
+            assert int(ws[36:40].view(torch.int32).item()) == 0
+    finally:
+        bf.set_batch_fused(False)
+    j = 1  # radius 48, overlap-staged lookup
+    p = plans[j]
+    ref = oracle.expanded_box(imgs[j].cpu().numpy(), oracle.make_plan(16.0, 48, 4, 0.1, 16))
+    err = np.abs(outs[j].cpu().numpy() - ref).max()
+    _report("fused batch member r=48 %s" % dtype, err)
+    assert err <= TIGHT
+
+
+def test_fused_batch_graph_replays(torch_dev):
+    """The fused launch (with its counter reset) captured in a graph and
+    replayed with new inputs, eager work between the replays: every replay
+    equals the single-image calls on its inputs."""
+    import torch
+    bf = _bf()
+    plans, imgs = _fused_group(torch, "f32", 80)
+    static_in = [I.clone() for I in imgs]
+    outs = [torch.empty(I.shape, dtype=torch.float32, device="cuda") for I in imgs]
+    shapes = [tuple(I.shape) for I in imgs]
+    ws = torch.zeros(bf.batch_workspace_size(plans, shapes), dtype=torch.uint8, device="cuda")
+    bf.set_batch_fused(True)
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            bf.filter_batch(plans, static_in, outs=outs, ws=ws)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            bf.filter_batch(plans, static_in, outs=outs, ws=ws)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            for j, I in enumerate(static_in):
+                I.copy_(torch.from_numpy(synth.gen_image(I.shape[0], I.shape[1], 4, 0.03, 700 + 10 * rep + j)))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            eager = [bf.filter(p, I) for p, I in zip(plans, static_in)]
+            torch.cuda.synchronize()
+            for j in range(len(plans)):
+                assert torch.equal(outs[j], eager[j]), (rep, j)
+            assert int(ws[36:40].view(torch.int32).item()) == 0
+    finally:
+        bf.set_batch_fused(False)
+
+
 def test_batch_graph_replays(torch_dev):
     """A batch captured once in a graph and replayed with new inputs, with
     eager work in between: every replay equals the eager single-image calls
