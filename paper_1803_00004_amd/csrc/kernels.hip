@@ -1661,7 +1661,7 @@ struct BatchImage {
 
 struct BatchArgs {
   int n;
-  uint32_t *heads;  // 8 queue heads per lookup launch (two launches: 16)
+  uint32_t *heads;  // 8 queue heads per lookup launch class (kBatchQueues in all)
   int ka_start[kMaxBatch + 1];
   BatchImage img[kMaxBatch];
 };

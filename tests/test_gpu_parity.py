@@ -94,8 +94,9 @@ WIDE_CASES = [
 
 @pytest.mark.parametrize("H,W,ss,r,ns,sr,nr,pitch,nq", WIDE_CASES)
 def test_wide_regions_vs_oracle(torch_dev, H, W, ss, r, ns, sr, nr, pitch, nq):
-    """Every pitch class of the LDS tile kernel (regions wider than 128
-    columns, single-buffered) against T3 on whole images."""
+    """Every pitch class of the LDS tile kernel for regions wider than 128
+    columns (overlap-staged at pitch 160 and, up to 164 region rows, 176;
+    single-buffered beyond) against T3 on whole images."""
     I = synth.gen_image(H, W, 7, 0.03, 7 * r + H)
     gp, op = _plans(ss, r, ns, sr, nr)
     info = gp.info
