@@ -650,9 +650,8 @@ __device__ __forceinline__ void kb_body(const void *__restrict__ I, const ImageP
     }
     // software pipeline of the quadruplet loop: the reads of D quadruplets
     // first, then the arithmetic of quadruplet q beside the reads of q + D
-    // (D = 1 with overlap staging, whose registers also hold the next
-    // table's overlapping rows)
-    constexpr int D = OV ? 1 : 2;
+    // (D = 1 with overlap staging at pitch 160, where it measured faster)
+    constexpr int D = OV && PITCH == 160 ? 1 : 2;
     __builtin_amdgcn_sched_group_barrier(0x100, 8 * D, 0);
 #pragma unroll
     for (int q = 0; q + D < NQ; ++q) {
@@ -1027,15 +1026,15 @@ __global__ __launch_bounds__(1024) void kl_tile(const void *__restrict__ I, Imag
 // (den >= 1: the centre's weight).
 // ---------------------------------------------------------------------------
 template <bool U8, bool ABS>
-__global__ __launch_bounds__(256) void direct_bf(const void *__restrict__ I, int H, int W, int r,
-                                                 const float *__restrict__ Ks, float c,
-                                                 float *__restrict__ out, float *__restrict__ num_out,
-                                                 float *__restrict__ den_out) {
+__device__ __forceinline__ void direct_body(const void *__restrict__ I, int H, int W, int r,
+                                            const float *__restrict__ Ks, float c, float *__restrict__ out,
+                                            float *__restrict__ num_out, float *__restrict__ den_out,
+                                            int bx, int by) {
   extern __shared__ float sh[];
   const int K = 2 * r + 1, TW = 64 + 2 * r, TH = 4 + 2 * r;
   float *ks = sh;
   float *t = sh + K * K;
-  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 4;
+  const int x0 = bx * 64, y0 = by * 4;
   for (int i = threadIdx.x; i < K * K; i += 256) ks[i] = Ks[i];
   for (int i = threadIdx.x; i < TW * TH; i += 256) {
     const int ty = i / TW, tx = i - ty * TW;
@@ -1070,6 +1069,86 @@ __global__ __launch_bounds__(256) void direct_bf(const void *__restrict__ I, int
   out[idx] = nu / de * s;
   if (num_out) num_out[idx] = nu * s;
   if (den_out) den_out[idx] = de;
+}
+
+template <bool U8, bool ABS>
+__global__ __launch_bounds__(256) void direct_bf(const void *__restrict__ I, int H, int W, int r,
+                                                 const float *__restrict__ Ks, float c,
+                                                 float *__restrict__ out, float *__restrict__ num_out,
+                                                 float *__restrict__ den_out) {
+  direct_body<U8, ABS>(I, H, W, r, Ks, c, out, num_out, den_out, blockIdx.x, blockIdx.y);
+}
+
+// Direct summation for the requests of a batch, one launch: a flat grid over
+// every image's 64 x 4 blocks (image i owns blocks [start[i], start[i + 1])),
+// the single-image body, so each output is bitwise its single-image call.
+struct DirectImage {
+  const void *I;
+  float *out;
+  const float *Ks;
+  float c;
+  int H, W, r;
+};
+struct DirectBatchArgs {
+  int n;
+  int start[kMaxBatch + 1];
+  DirectImage img[kMaxBatch];
+};
+
+template <bool U8, bool ABS>
+__global__ __launch_bounds__(256) void direct_batch(DirectBatchArgs a) {
+  const int b = blockIdx.x;
+  int i = 0;
+  while (i + 1 < a.n && b >= a.start[i + 1]) ++i;
+  const DirectImage &im = a.img[i];
+  const int lb = b - a.start[i], bxs = (im.W + 63) / 64;
+  direct_body<U8, ABS>(im.I, im.H, im.W, im.r, im.Ks, im.c, im.out, nullptr, nullptr, lb % bxs, lb / bxs);
+}
+
+// The direct-summation requests of a batch (host tables, inputs, outputs):
+// one launch per input type and range kernel kind, at most kMaxBatch images each.
+bf_status_t launch_direct_batch(const DevTables *const *host, const void *const *I, float *const *out,
+                                const int *H, const int *W, int n, void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int kind = 0; kind < 4; ++kind) {
+    const bool u8 = kind & 1, abs_kind = kind & 2;
+    DirectBatchArgs a{};
+    size_t lds = 0;
+    auto flush = [&]() -> bool {
+      if (!a.n) return true;
+      const int blocks = a.start[a.n];
+      auto go = [&](auto kernel) {
+        if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
+          return false;
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), lds, s, a);
+        return hipGetLastError() == hipSuccess;
+      };
+      const bool ok = u8 ? (abs_kind ? go(direct_batch<true, true>) : go(direct_batch<true, false>))
+                         : (abs_kind ? go(direct_batch<false, true>) : go(direct_batch<false, false>));
+      a = DirectBatchArgs{};
+      lds = 0;
+      return ok;
+    };
+    for (int j = 0; j < n; ++j) {
+      const DevTables &h = *host[j];
+      if ((h.in_u8 != 0) != u8 || (h.direct_abs != 0) != abs_kind) continue;
+      const int r = h.direct_r, K = 2 * r + 1;
+      DirectImage &im = a.img[a.n];
+      im.I = I[j];
+      im.out = out[j];
+      im.Ks = h.direct_ks;
+      im.c = h.direct_c;
+      im.H = H[j];
+      im.W = W[j];
+      im.r = r;
+      a.start[a.n + 1] = a.start[a.n] + ((W[j] + 63) / 64) * ((H[j] + 3) / 4);
+      lds = std::max(lds, ((size_t)K * K + (size_t)(64 + 2 * r) * (4 + 2 * r)) * sizeof(float));
+      if (++a.n == kMaxBatch && !flush()) return BF_ERR_DEVICE;
+    }
+    if (!flush()) return BF_ERR_DEVICE;
+  }
+  return BF_OK;
 }
 
 bf_status_t launch_direct(const DevTables &host, const void *I, float *out, float *num, float *den,
@@ -1132,11 +1211,11 @@ __device__ __forceinline__ uint32_t row16_inclusive_scan(uint32_t v) {
   return x;
 }
 
+// One block of the regime: block blk of an image's tiles x nsplit blocks.
 template <int kZTile, int kZThreads>
-__global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restrict__ I, int H, int W,
-                                                         const DevTables *__restrict__ tab, int nsplit,
-                                                         float *__restrict__ out, float *__restrict__ num_out,
-                                                         float *__restrict__ den_out) {
+__device__ __forceinline__ void kz_body(const uint8_t *__restrict__ I, int H, int W,
+                                        const DevTables *__restrict__ tab, int nsplit, float *__restrict__ out,
+                                        float *__restrict__ num_out, float *__restrict__ den_out, int blk) {
   constexpr int kZWaves = kZThreads / 64;
   static_assert(kZWaves <= 16, "segment carries are scanned in 16-lane rows");
   constexpr int kZSeg = kZMaxRegion / kZWaves;      // region rows per wave
@@ -1153,7 +1232,7 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   const int tiles_x = (W + kZTile - 1) / kZTile;
   // nsplit blocks share a tile (small images): block part takes the tile's
   // levels part, part + nsplit, ...
-  const int tile = blockIdx.x / nsplit, part = blockIdx.x - tile * nsplit;
+  const int tile = blk / nsplit, part = blk - tile * nsplit;
   const int ty0 = (tile / tiles_x) * kZTile, tx0 = (tile % tiles_x) * kZTile;
   const int cy0 = min(max(ty0 + tab->tap_dy_min, 0), H), cy1 = min(max(ty0 + kZTile - 1 + tab->tap_dy_max, 0), H);
   const int cx0 = min(max(tx0 + tab->tap_dx_min, 0), W), cx1 = min(max(tx0 + kZTile - 1 + tab->tap_dx_max, 0), W);
@@ -1325,6 +1404,38 @@ __global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restri
   }
 }
 
+template <int kZTile, int kZThreads>
+__global__ __launch_bounds__(kZThreads) void kz_rangebox(const uint8_t *__restrict__ I, int H, int W,
+                                                         const DevTables *__restrict__ tab, int nsplit,
+                                                         float *__restrict__ out, float *__restrict__ num_out,
+                                                         float *__restrict__ den_out) {
+  kz_body<kZTile, kZThreads>(I, H, W, tab, nsplit, out, num_out, den_out, blockIdx.x);
+}
+
+// The range-box requests of a batch in one launch per output-tile size: a
+// flat grid over every image's blocks (image i owns [start[i], start[i + 1])),
+// the single-image body, so each output is bitwise its single-image call.
+struct ZImage {
+  const uint8_t *I;
+  float *out;
+  const DevTables *tab;
+  int H, W, nsplit;
+};
+struct ZBatchArgs {
+  int n;
+  int start[kMaxBatch + 1];
+  ZImage img[kMaxBatch];
+};
+
+template <int kZTile, int kZThreads>
+__global__ __launch_bounds__(kZThreads) void kz_batch(ZBatchArgs a) {
+  const int b = blockIdx.x;
+  int i = 0;
+  while (i + 1 < a.n && b >= a.start[i + 1]) ++i;
+  const ZImage &im = a.img[i];
+  kz_body<kZTile, kZThreads>(im.I, im.H, im.W, im.tab, im.nsplit, im.out, nullptr, nullptr, b - a.start[i]);
+}
+
 template <int TE, int NT>
 static size_t rangebox_lds(const DevTables &host) {
   const int RS = TE - 1 + host.tap_dy_max - host.tap_dy_min;  // largest region
@@ -1372,6 +1483,51 @@ bf_status_t launch_rangebox(const DevTables *dev, const DevTables &host, const v
   const hipError_t e = hipGetLastError();
   profile_mark(1, 0, stream);
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
+}
+
+// The range-box requests of a batch (device and host tables, inputs,
+// outputs): one launch per output-tile size, at most kMaxBatch images each;
+// each image split as its single-image call splits it.
+bf_status_t launch_rangebox_batch(const DevTables *const *dev, const DevTables *const *host, const void *const *I,
+                                  float *const *out, const int *H, const int *W, int n, void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int big = 1; big >= 0; --big) {
+    ZBatchArgs a{};
+    size_t lds = 0;
+    auto flush = [&]() -> bool {
+      if (!a.n) return true;
+      const void *fn = big ? (const void *)kz_batch<64, 1024> : (const void *)kz_batch<32, 512>;
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return false;
+      if (big)
+        hipLaunchKernelGGL((kz_batch<64, 1024>), dim3(a.start[a.n]), dim3(1024), lds, s, a);
+      else
+        hipLaunchKernelGGL((kz_batch<32, 512>), dim3(a.start[a.n]), dim3(512), lds, s, a);
+      a = ZBatchArgs{};
+      lds = 0;
+      return hipGetLastError() == hipSuccess;
+    };
+    for (int j = 0; j < n; ++j) {
+      const size_t l64 = rangebox_lds<64, 1024>(*host[j]), l32 = rangebox_lds<32, 512>(*host[j]);
+      const bool b = l64 <= kLdsLimit;
+      if (b != (big != 0)) continue;
+      const size_t l = b ? l64 : l32;
+      if (l > kLdsLimit) return BF_ERR_UNSUPPORTED;
+      const int te = b ? 64 : 32;
+      const int tiles = ((W[j] + te - 1) / te) * ((H[j] + te - 1) / te);
+      ZImage &im = a.img[a.n];
+      im.I = static_cast<const uint8_t *>(I[j]);
+      im.out = out[j];
+      im.tab = dev[j];
+      im.H = H[j];
+      im.W = W[j];
+      im.nsplit = std::max(1, std::min(8, 1024 / tiles));
+      a.start[a.n + 1] = a.start[a.n] + tiles * im.nsplit;
+      lds = std::max(lds, l);
+      if (++a.n == kMaxBatch && !flush()) return BF_ERR_DEVICE;
+    }
+    if (!flush()) return BF_ERR_DEVICE;
+  }
+  return BF_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -2229,9 +2385,13 @@ template <bool U8>
 static hipError_t launch_kb_batch(int pitch, int st, int nq, int blocks, size_t lds, hipStream_t s,
                                   const BatchArgs &a) {
   if (st == kStageDouble) return launch_kb_batch_nq<128, kStageDouble, U8>(nq, blocks, lds, s, a);
-  if (st == kStageOverlap)
-    return pitch == 160 ? launch_kb_batch_nq<160, kStageOverlap, U8>(nq, blocks, lds, s, a)
-                        : launch_kb_batch_nq<176, kStageOverlap, U8>(nq, blocks, lds, s, a);
+  if (st == kStageOverlap) {  // at most 8 quadruplets (launch_batch_chunk)
+    if (pitch == 160)
+      return nq <= 4 ? launch_kb_batch1<160, 4, kStageOverlap, U8>(blocks, lds, s, a)
+                     : launch_kb_batch1<160, 8, kStageOverlap, U8>(blocks, lds, s, a);
+    return nq <= 4 ? launch_kb_batch1<176, 4, kStageOverlap, U8>(blocks, lds, s, a)
+                   : launch_kb_batch1<176, 8, kStageOverlap, U8>(blocks, lds, s, a);
+  }
   return launch_kb_batch_pitch<kStageSingle, U8>(pitch, nq, blocks, lds, s, a);
 }
 
@@ -2454,23 +2614,46 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
 
 bf_status_t launch_batch(const BatchItem *items_all, int n_all, uint32_t *heads, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // direct-summation requests need no tables: their own launches
+  // requests without term tables: direct summation in one launch per input
+  // type and range kernel kind, the range-box regime in one launch per output
+  // tile size; reduced-precision requests their own launches
   std::vector<BatchItem> kept;
   kept.reserve(n_all);
+  std::vector<const DevTables *> dh, zd, zh;
+  std::vector<const void *> di, zi;
+  std::vector<float *> dout, zout;
+  std::vector<int> dH, dW, zH, zW;
   for (int i = 0; i < n_all; ++i) {
     const BatchItem &it = items_all[i];
     if (it.host->direct) {
-      bf_status_t st = launch_direct(*it.host, it.I, it.out, nullptr, nullptr, it.g.H, it.g.W, stream);
-      if (st != BF_OK) return st;
+      dh.push_back(it.host);
+      di.push_back(it.I);
+      dout.push_back(it.out);
+      dH.push_back(it.g.H);
+      dW.push_back(it.g.W);
     } else if (it.host->range_box) {
-      bf_status_t st = launch_rangebox(it.dev, *it.host, it.I, it.out, nullptr, nullptr, it.g.H, it.g.W, stream);
-      if (st != BF_OK) return st;
+      zd.push_back(it.dev);
+      zh.push_back(it.host);
+      zi.push_back(it.I);
+      zout.push_back(it.out);
+      zH.push_back(it.g.H);
+      zW.push_back(it.g.W);
     } else if (it.host->reduced) {
       bf_status_t st = launch_reduced(it.dev, *it.host, it.g, it.I, it.out, nullptr, nullptr, it.ws, stream);
       if (st != BF_OK) return st;
     } else {
       kept.push_back(it);
     }
+  }
+  if (!dh.empty()) {
+    bf_status_t st = launch_direct_batch(dh.data(), di.data(), dout.data(), dH.data(), dW.data(), (int)dh.size(),
+                                         stream);
+    if (st != BF_OK) return st;
+  }
+  if (!zd.empty()) {
+    bf_status_t st = launch_rangebox_batch(zd.data(), zh.data(), zi.data(), zout.data(), zH.data(), zW.data(),
+                                           (int)zd.size(), stream);
+    if (st != BF_OK) return st;
   }
   const BatchItem *items = kept.data();
   const int n = (int)kept.size();

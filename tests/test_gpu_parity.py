@@ -700,20 +700,40 @@ def test_direct_summation_vs_true_bf(torch_dev, H, W, ss, r, sr, dtype):
 
 
 def test_direct_plans_in_batches(torch_dev):
-    """Direct-summation requests mixed with expansion requests in a batch:
-    bitwise the single-image results."""
+    """Requests without term tables in a batch beside expansion requests:
+    direct summation of several radii, both input types and both range kernel
+    kinds (one launch per input type and kind, with the largest window's
+    LDS), range-box and level-fold requests of both output-tile sizes (one
+    launch per tile size), 1x1 images: bitwise the single-image results."""
     import torch
     bf = _bf()
     pd = bf.Plan(2.0, 0.05, 6, 32, 4, direct="auto")
+    pd9 = bf.Plan(3.0, 0.1, 9, 8, 4, direct=True)
+    pu = bf.Plan(2.0, 0.1, 6, 8, 4, dtype="u8", direct=True)
+    pue = bf.Plan(2.0, 0.1, 9, 8, 4, dtype="u8", direct=True, kernel_s="exponential", kernel_r="exponential")
     pe = bf.Plan(4.0, 0.1, 12, 16, 4)
     assert pd.info.direct == 1 and pe.info.direct == 0
-    imgs = [torch.from_numpy(synth.gen_image(h, w, 4, 0.03, h * w)).cuda() for h, w in ((120, 333), (77, 64), (256, 256))]
-    plans = [pd, pe, pd]
+    # range-box and level-fold requests (8-bit) share launches per output-tile size too
+    pz = bf.Plan(3.0, 0.1, 9, 5, 4, dtype="u8", range_box=True)
+    pz48 = bf.Plan(16.0, 0.1, 48, 5, 4, dtype="u8", range_box=True)
+    pf = bf.Plan(8.0, 0.1, 24, 16, 6, dtype="u8", level_fold=True)
+    assert pz.info.box_tile == 64 and pz48.info.box_tile == 32
+    specs = [(pd, 120, 333), (pe, 77, 64), (pd, 256, 256), (pd9, 1, 1), (pu, 90, 130), (pd9, 200, 70),
+             (pue, 64, 65), (pu, 3, 500), (pz, 150, 170), (pz48, 70, 90), (pf, 130, 129), (pz, 1, 1),
+             (pz48, 300, 40)]
+    u8 = (pu, pue, pz, pz48, pf)
+    plans, imgs = [], []
+    for p, h, w in specs:
+        plans.append(p)
+        if any(p is q for q in u8):
+            imgs.append(torch.from_numpy(synth.gen_image_u8(h, w, 4, 0.03, h * w)).cuda())
+        else:
+            imgs.append(torch.from_numpy(synth.gen_image(h, w, 4, 0.03, h * w)).cuda())
     singles = [bf.filter(p, I).clone() for p, I in zip(plans, imgs)]
     outs = bf.filter_batch(plans, imgs)
     torch.cuda.synchronize()
-    for o, s in zip(outs, singles):
-        assert torch.equal(o, s)
+    for i, (o, s) in enumerate(zip(outs, singles)):
+        assert torch.equal(o, s), i
 
 
 @pytest.mark.parametrize("H,W,ss,r,ns,sr,nr", [
