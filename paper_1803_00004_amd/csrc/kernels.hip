@@ -1542,11 +1542,11 @@ bf_status_t launch_rangebox_batch(const DevTables *const *dev, const DevTables *
 // is read.  Out-of-image values are zero, so the table's corners need no clamp.
 // ---------------------------------------------------------------------------
 template <bool U8>
-__global__ __launch_bounds__(256) void kr_modulate(const void *__restrict__ I, int H, int W,
-                                                   const DevTables *__restrict__ tab,
-                                                   _Float16 *__restrict__ img) {
+__device__ __forceinline__ void kr_modulate_body(const void *__restrict__ I, int H, int W,
+                                                 const DevTables *__restrict__ tab, _Float16 *__restrict__ img,
+                                                 int blk) {
   const long long n = (long long)H * W;
-  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long idx = (long long)blk * 256 + threadIdx.x;
   if (idx >= n) return;
   float px, v;
   load_pixel<U8>(I, idx, &px, &v);
@@ -1565,12 +1565,19 @@ __global__ __launch_bounds__(256) void kr_modulate(const void *__restrict__ I, i
   }
 }
 
+template <bool U8>
+__global__ __launch_bounds__(256) void kr_modulate(const void *__restrict__ I, int H, int W,
+                                                   const DevTables *__restrict__ tab,
+                                                   _Float16 *__restrict__ img) {
+  kr_modulate_body<U8>(I, H, W, tab, img, blockIdx.x);
+}
+
+// One TE x TE output tile (index blk) of one image.
 template <int TE, int NT, int NQ, bool U8>
-__global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H, int W,
-                                              const DevTables *__restrict__ tab,
-                                              const _Float16 *__restrict__ img, float scale, float inv_scale,
-                                              float *__restrict__ out, float *__restrict__ num_out,
-                                              float *__restrict__ den_out) {
+__device__ __forceinline__ void kr_body(const void *__restrict__ I, int H, int W, const DevTables *__restrict__ tab,
+                                        const _Float16 *__restrict__ img, float scale, float inv_scale,
+                                        float *__restrict__ out, float *__restrict__ num_out,
+                                        float *__restrict__ den_out, int blk) {
   constexpr int NW = NT / 64;              // waves: one row segment each
   static_assert(NW <= 16, "segment carries are scanned in 16-lane rows");
   constexpr int SEGMAX = kZMaxRegion / NW;  // rows per segment
@@ -1583,7 +1590,7 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tiles_x = (W + TE - 1) / TE;
-  const int ty0 = (blockIdx.x / tiles_x) * TE, tx0 = (blockIdx.x % tiles_x) * TE;
+  const int ty0 = (blk / tiles_x) * TE, tx0 = (blk % tiles_x) * TE;
   const int dy0 = tab->tap_dy_min, dx0 = tab->tap_dx_min;
   const int Y0 = ty0 + dy0, X0 = tx0 + dx0;  // image position of table corner (0, 0)
   const int RS = TE - 1 + tab->tap_dy_max - dy0, RC = TE - 1 + tab->tap_dx_max - dx0;  // <= 128 each
@@ -1736,6 +1743,51 @@ __global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H,
 
 // 32 x 32 output tiles (512 threads, two pixels each): 64 x 64 tiles with four
 // pixels per thread exceed 128 registers and spill.
+template <int TE, int NT, int NQ, bool U8>
+__global__ __launch_bounds__(NT) void kr_tile(const void *__restrict__ I, int H, int W,
+                                              const DevTables *__restrict__ tab,
+                                              const _Float16 *__restrict__ img, float scale, float inv_scale,
+                                              float *__restrict__ out, float *__restrict__ num_out,
+                                              float *__restrict__ den_out) {
+  kr_body<TE, NT, NQ, U8>(I, H, W, tab, img, scale, inv_scale, out, num_out, den_out, blockIdx.x);
+}
+
+// The reduced-precision requests of a batch: one modulation launch and one
+// table-and-lookup launch per input type, flat grids over the images' blocks
+// (image i owns [mstart[i], mstart[i + 1]) and [tstart[i], tstart[i + 1])),
+// the single-image bodies, so each output is bitwise its single-image call.
+struct RImage {
+  const void *I;
+  float *out;
+  const DevTables *tab;
+  _Float16 *img;
+  float scale, inv;
+  int H, W;
+};
+struct RBatchArgs {
+  int n;
+  int mstart[kMaxBatch + 1], tstart[kMaxBatch + 1];
+  RImage im[kMaxBatch];
+};
+
+template <bool U8>
+__global__ __launch_bounds__(256) void kr_modulate_batch(RBatchArgs a) {
+  const int b = blockIdx.x;
+  int i = 0;
+  while (i + 1 < a.n && b >= a.mstart[i + 1]) ++i;
+  const RImage &m = a.im[i];
+  kr_modulate_body<U8>(m.I, m.H, m.W, m.tab, m.img, b - a.mstart[i]);
+}
+
+template <int TE, int NT, int NQ, bool U8>
+__global__ __launch_bounds__(NT) void kr_tile_batch(RBatchArgs a) {
+  const int b = blockIdx.x;
+  int i = 0;
+  while (i + 1 < a.n && b >= a.tstart[i + 1]) ++i;
+  const RImage &m = a.im[i];
+  kr_body<TE, NT, NQ, U8>(m.I, m.H, m.W, m.tab, m.img, m.scale, m.inv, m.out, nullptr, nullptr, b - a.tstart[i]);
+}
+
 int reduced_tile(const DevTables &host) {
   if (31 + host.tap_dy_max - host.tap_dy_min <= kZMaxRegion && 31 + host.tap_dx_max - host.tap_dx_min <= kZMaxRegion)
     return 32;
@@ -1788,6 +1840,66 @@ bf_status_t launch_reduced(const DevTables *dev, const DevTables &host, const Ge
                  : launch_kr_nq<32, 512, false>(host.n_quads, grid, lds, s, I, g.H, g.W, dev, img, scale, inv, out, num, den);
   profile_mark(1, 0, stream);
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
+}
+
+template <bool U8>
+static hipError_t launch_reduced_group(const RBatchArgs &a, int nq, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((kr_modulate_batch<U8>), dim3(a.mstart[a.n]), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  auto go = [&](auto k) {
+    hipError_t e2 = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e2 != hipSuccess) return e2;
+    hipLaunchKernelGGL(k, dim3(a.tstart[a.n]), dim3(512), lds, s, a);
+    return hipGetLastError();
+  };
+  if (nq <= 4) return go(kr_tile_batch<32, 512, 4, U8>);
+  if (nq <= 8) return go(kr_tile_batch<32, 512, 8, U8>);
+  return go(kr_tile_batch<32, 512, 12, U8>);
+}
+
+// The reduced-precision requests of a batch (their geometries and FP16
+// workspaces): one pair of launches per input type, at most kMaxBatch images.
+bf_status_t launch_reduced_batch(const DevTables *const *dev, const DevTables *const *host, const Geometry *g,
+                                 const void *const *I, float *const *out, void *const *ws, int n, void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int u8 = 0; u8 < 2; ++u8) {
+    RBatchArgs a{};
+    size_t lds = 0;
+    int nq = 0;
+    auto flush = [&]() -> bool {
+      if (!a.n) return true;
+      const hipError_t e = u8 ? launch_reduced_group<true>(a, nq, lds, s) : launch_reduced_group<false>(a, nq, lds, s);
+      a = RBatchArgs{};
+      lds = 0;
+      nq = 0;
+      return e == hipSuccess;
+    };
+    for (int j = 0; j < n; ++j) {
+      const DevTables &h = *host[j];
+      if ((h.in_u8 != 0) != (u8 != 0)) continue;
+      const int te = reduced_tile(h);
+      if (te == 0 || h.n_quads > 12) return BF_ERR_UNSUPPORTED;
+      const int RS = te - 1 + h.tap_dy_max - h.tap_dy_min;
+      RImage &m = a.im[a.n];
+      m.I = I[j];
+      m.out = out[j];
+      m.tab = dev[j];
+      m.img = static_cast<_Float16 *>(ws[j]);
+      m.scale = std::ldexp(1.0f, g[j].sat_shift);
+      m.inv = std::ldexp(1.0f, -g[j].sat_shift);
+      m.H = g[j].H;
+      m.W = g[j].W;
+      const long long npx = (long long)m.H * m.W;
+      a.mstart[a.n + 1] = a.mstart[a.n] + (int)((npx + 255) / 256);
+      a.tstart[a.n + 1] = a.tstart[a.n] + ((m.W + te - 1) / te) * ((m.H + te - 1) / te);
+      lds = std::max(lds, (size_t)(RS + 1 + 512 / 64) * kZPitch * 4);
+      nq = std::max(nq, h.n_quads);
+      if (++a.n == kMaxBatch && !flush()) return BF_ERR_DEVICE;
+    }
+    if (!flush()) return BF_ERR_DEVICE;
+  }
+  return BF_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -2616,12 +2728,15 @@ bf_status_t launch_batch(const BatchItem *items_all, int n_all, uint32_t *heads,
   hipStream_t s = static_cast<hipStream_t>(stream);
   // requests without term tables: direct summation in one launch per input
   // type and range kernel kind, the range-box regime in one launch per output
-  // tile size; reduced-precision requests their own launches
+  // tile size; reduced-precision requests in one pair of launches per input
+  // type
   std::vector<BatchItem> kept;
   kept.reserve(n_all);
-  std::vector<const DevTables *> dh, zd, zh;
-  std::vector<const void *> di, zi;
-  std::vector<float *> dout, zout;
+  std::vector<const DevTables *> dh, zd, zh, rd, rh;
+  std::vector<const void *> di, zi, ri;
+  std::vector<float *> dout, zout, rout;
+  std::vector<void *> rws;
+  std::vector<Geometry> rg;
   std::vector<int> dH, dW, zH, zW;
   for (int i = 0; i < n_all; ++i) {
     const BatchItem &it = items_all[i];
@@ -2639,8 +2754,12 @@ bf_status_t launch_batch(const BatchItem *items_all, int n_all, uint32_t *heads,
       zH.push_back(it.g.H);
       zW.push_back(it.g.W);
     } else if (it.host->reduced) {
-      bf_status_t st = launch_reduced(it.dev, *it.host, it.g, it.I, it.out, nullptr, nullptr, it.ws, stream);
-      if (st != BF_OK) return st;
+      rd.push_back(it.dev);
+      rh.push_back(it.host);
+      rg.push_back(it.g);
+      ri.push_back(it.I);
+      rout.push_back(it.out);
+      rws.push_back(it.ws);
     } else {
       kept.push_back(it);
     }
@@ -2653,6 +2772,11 @@ bf_status_t launch_batch(const BatchItem *items_all, int n_all, uint32_t *heads,
   if (!zd.empty()) {
     bf_status_t st = launch_rangebox_batch(zd.data(), zh.data(), zi.data(), zout.data(), zH.data(), zW.data(),
                                            (int)zd.size(), stream);
+    if (st != BF_OK) return st;
+  }
+  if (!rd.empty()) {
+    bf_status_t st = launch_reduced_batch(rd.data(), rh.data(), rg.data(), ri.data(), rout.data(), rws.data(),
+                                          (int)rd.size(), stream);
     if (st != BF_OK) return st;
   }
   const BatchItem *items = kept.data();

@@ -108,6 +108,22 @@ def test_wide_regions_vs_oracle(torch_dev, H, W, ss, r, ns, sr, nr, pitch, nq):
     assert err <= TIGHT
 
 
+@pytest.mark.parametrize("ss,r,ns,pitch", [(16.0, 48, 8, 176), (13.0, 40, 6, 160)])
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 200), (200, 1), (63, 65), (129, 70), (64, 64), (65, 257)])
+def test_overlap_staging_small_and_ragged(torch_dev, ss, r, ns, pitch, H, W):
+    """The overlap-staged lookup (both layouts, register and direct rows) on
+    images smaller than the window, single rows and columns and ragged tile
+    edges, against T3 on the whole image."""
+    I = synth.gen_image(H, W, 3, 0.03, 11 * H + W)
+    gp, op = _plans(ss, r, ns, 0.1, 8)
+    assert gp.info.lds_pitch == pitch and gp.info.lds_double_buffered == 0
+    out = _run(torch_dev, gp, I)
+    ref = oracle.expanded_box(I, op)
+    err = np.abs(out - ref).max()
+    _report("overlap %dx%d r %d" % (H, W, r), err)
+    assert err <= TIGHT
+
+
 def test_wide_regions_in_one_batch(torch_dev):
     """All pitch classes (and a double-buffered plan) in one batch: each output
     is bitwise its single-image result."""
@@ -704,7 +720,8 @@ def test_direct_plans_in_batches(torch_dev):
     direct summation of several radii, both input types and both range kernel
     kinds (one launch per input type and kind, with the largest window's
     LDS), range-box and level-fold requests of both output-tile sizes (one
-    launch per tile size), 1x1 images: bitwise the single-image results."""
+    launch per tile size), reduced-precision requests of both input types (a
+    pair of launches per type), 1x1 images: bitwise the single-image results."""
     import torch
     bf = _bf()
     pd = bf.Plan(2.0, 0.05, 6, 32, 4, direct="auto")
@@ -718,10 +735,13 @@ def test_direct_plans_in_batches(torch_dev):
     pz48 = bf.Plan(16.0, 0.1, 48, 5, 4, dtype="u8", range_box=True)
     pf = bf.Plan(8.0, 0.1, 24, 16, 6, dtype="u8", level_fold=True)
     assert pz.info.box_tile == 64 and pz48.info.box_tile == 32
+    # reduced-precision requests: one pair of launches per input type
+    pr = bf.Plan(3.0, 0.1, 9, 8, 4, precision="reduced")
+    pru = bf.Plan(8.0, 0.1, 24, 16, 6, dtype="u8", precision="reduced")
     specs = [(pd, 120, 333), (pe, 77, 64), (pd, 256, 256), (pd9, 1, 1), (pu, 90, 130), (pd9, 200, 70),
              (pue, 64, 65), (pu, 3, 500), (pz, 150, 170), (pz48, 70, 90), (pf, 130, 129), (pz, 1, 1),
-             (pz48, 300, 40)]
-    u8 = (pu, pue, pz, pz48, pf)
+             (pz48, 300, 40), (pr, 100, 170), (pru, 140, 90), (pr, 1, 1), (pru, 33, 270)]
+    u8 = (pu, pue, pz, pz48, pf, pru)
     plans, imgs = [], []
     for p, h, w in specs:
         plans.append(p)
