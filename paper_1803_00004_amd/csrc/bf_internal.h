@@ -193,9 +193,11 @@ struct BatchItem {
   int32_t *ws;
 };
 
-// Launch a batch on `stream`: one K-A and one K-B launch per group of at most
-// kMaxBatch images of one input type.  `heads` is kBatchHeadBytes of device
-// memory for the K-B work queues.
+// Launch a batch on `stream`: per group of at most kMaxBatch images of one
+// input type one K-A launch and one K-B launch per lookup class (or one fused
+// launch, bf_batch_set_fused); table-free requests (direct summation,
+// range-box regime) and reduced-precision requests share launches per kind.
+// `heads` is kBatchHeadBytes of device memory for the work queues.
 bf_status_t launch_batch(const BatchItem *items, int n, uint32_t *heads, void *stream);
 // bf_batch_set_fused: 1 runs eligible batch groups as one fused launch
 void set_fused_batch(int on);
