@@ -138,7 +138,9 @@ def served_run(args, reqs, host_imgs, with_oracle):
     outs_closed = [torch.empty(I.shape, dtype=torch.float32, device=dev) for I in imgs]
     alone = [torch.empty(I.shape, dtype=torch.float32, device=dev) for I in imgs]
     px = np.array([r["H"] * r["W"] for r in reqs], dtype=np.float64)
-    budget, max_batch, n_streams = 48 << 30, 16, 2
+    budget = 48 << 30
+    max_batch = int(getattr(args, "served_max_batch", 16))
+    n_streams = int(getattr(args, "served_streams", 2))
     srv = bf.Server(hbm_budget=budget, max_batch=max_batch, n_streams=n_streams)
     log("[served] %d plans in %.0f ms; %.1f Mpx in total; warm-up" % (len(plans), plan_ms, px.sum() / 1e6))
     for _ in range(max(1, args.warmup)):
@@ -676,6 +678,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (no error check)")
     ap.add_argument("--no-served", action="store_true", help="headline without the served stream")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (heuristic tiling)")
+    ap.add_argument("--served-streams", type=int, default=2, help="served stream: the request loop's streams")
+    ap.add_argument("--served-max-batch", type=int, default=16, help="served stream: largest batch")
     ap.add_argument("--fused-batch", action="store_true",
                     help="served stream: each eligible batch as one fused launch (bf_batch_set_fused; "
                          "its time is all counted as lookup)")
