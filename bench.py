@@ -560,8 +560,9 @@ def single_image(args, workload, pre=None):
     ka_bytes = px * (vb * n_img + in_b)            # write every term image or table once, read I
     kb_bytes = px * (vb * n_img + in_b + 4)        # read every one once, read I, write out
     kb_flops = px * 2.0 * n_img * info.n_quads      # one FP32 FMA per quadruplet box per table
+    lk = plan.lookup_kernel(H, W)  # the lookup kernel the timed calls ran (tuned or default)
     kb_name = "kr_tile" if reduced else "kz_rangebox" if fold else (
-        "kb_tile" if info.lookup_kernel == 1 else "kb_lookup")
+        "kl_tile" if lk == 3 else "kb_tile" if lk in (1, 2) else "kb_lookup")
     ka_name = "kr_modulate" if reduced else "ka_sat"
     if fold:
         # one kernel: integer adds of the level-slab tables it builds

@@ -282,8 +282,9 @@ typedef struct {
                          lattice_step <= 16, at most 4 rows and 4 columns of boxes) */
   int lattice_step;
   int default_lookup; /* lookup kernel of an untuned image: 0 per-pixel, 1 LDS tile double-buffered,
-                         2 LDS tile single-buffered, 3 lattice (where the LDS tile kernel does not
-                         apply: more than 12 quadruplets) */
+                         2 LDS tile single-buffered or overlap-staged, 3 lattice (where the LDS tile
+                         kernel is not double-buffered and the plan has more than 8 quadruplets, or
+                         where the LDS tile kernel does not apply) */
 } bf_plan_info_t;
 
 bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);
@@ -297,6 +298,15 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info);
  * factor 1 + 2^-20 on gmax).  Any pointer may be NULL. */
 bf_status_t bf_image_geometry(bf_plan_t plan, int H, int W, int *tile, int *sat_shift,
                               size_t *ws_bytes);
+
+/* The lookup kernel an H x W image runs under a plan, as bf_filter would
+ * launch it now (after bf_autotune or bf_tuning_set, the tuned one):
+ * *kind = 0 per-pixel, 1 LDS tile double-buffered, 2 LDS tile single-buffered
+ * or overlap-staged, 3 lattice; -1 for plans that keep no tables (direct
+ * summation, range-box and level-fold regimes, reduced precision).  All
+ * lookup kernels give the same bits.  BF_ERR_INVALID_ARG for a null plan or
+ * kind, or sizes outside [1, 32768]. */
+bf_status_t bf_image_lookup_kernel(bf_plan_t plan, int H, int W, int *kind);
 
 /* Range terms: k[i], a[i] (coefficient a_k) and omega[i] = pi k / T, i < n_range. */
 bf_status_t bf_plan_range_terms(bf_plan_t plan, int *k, double *a, double *omega, int capacity);
@@ -314,7 +324,9 @@ bf_status_t bf_plan_taps(bf_plan_t plan, int *dy, int *dx, double *w, int capaci
 bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, int capacity);
 
 /* Autotuner.  Times the candidate launch shapes for H x W images under this
- * plan -- table tiles of 64, 128, 256 and 512 (tile + 2r + 1 <= 1024), each
+ * plan -- table tiles of 64, 128, 256 and 512, and for a plan the lattice
+ * kernel applies to, the multiples of 64 up to 576 that hold whole lattice
+ * tiles (tile + 2r + 1 <= 1024), each
  * with one range term or one table per table-kernel wave, and with every
  * lookup kernel the plan can use (LDS tile double- or single-buffered,
  * lattice; all give the same bits) --

@@ -28,7 +28,7 @@ BF_FLAG_LEVEL_FOLD = 0x10
 EXPORTED = [
     "bf_plan_create", "bf_plan_create_tabulated", "bf_plan_destroy", "bf_workspace_size", "bf_filter", "bf_filter_ws",
     "bf_filter_parts", "bf_batch_workspace_size", "bf_filter_batch", "bf_plan_query",
-    "bf_image_geometry", "bf_plan_range_terms", "bf_plan_spatial_kernel", "bf_plan_taps", "bf_plan_spatial_groups",
+    "bf_image_geometry", "bf_image_lookup_kernel", "bf_plan_range_terms", "bf_plan_spatial_kernel", "bf_plan_taps", "bf_plan_spatial_groups",
     "bf_profile_enable", "bf_profile_read", "bf_status_string", "bf_version",
     "bf_server_create", "bf_server_destroy", "bf_server_submit", "bf_server_poll", "bf_server_pending",
     "bf_server_stats", "bf_autotune", "bf_tuning_set", "bf_autotune_clear",
@@ -95,6 +95,7 @@ def lib():
                                       ip, ip, vp, sz, vp]
         L.bf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.bf_image_geometry.argtypes = [vp, i, i, ip, ip, ctypes.POINTER(sz)]
+        L.bf_image_lookup_kernel.argtypes = [vp, i, i, ip]
         L.bf_plan_range_terms.argtypes = [vp, ip, dp, dp, i]
         L.bf_plan_spatial_kernel.argtypes = [vp, dp, i]
         L.bf_plan_taps.argtypes = [vp, ip, ip, dp, i]
@@ -262,6 +263,13 @@ class Plan:
         _check(lib().bf_image_geometry(self._h, int(H), int(W), ctypes.byref(t), ctypes.byref(q),
                                        ctypes.byref(b)), "bf_image_geometry")
         return t.value, q.value, b.value
+
+    def lookup_kernel(self, H, W):
+        """The lookup kernel an H x W image runs now (bf_image_lookup_kernel):
+        0 per-pixel, 1 / 2 LDS tile double / single-buffered, 3 lattice, -1 none."""
+        k = ctypes.c_int()
+        _check(lib().bf_image_lookup_kernel(self._h, int(H), int(W), ctypes.byref(k)), "bf_image_lookup_kernel")
+        return k.value
 
     def autotune(self, H, W, reps=5, stream=None):
         """Time the candidate tilings for H x W images and keep the fastest

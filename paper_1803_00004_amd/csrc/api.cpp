@@ -10,6 +10,7 @@
 #include <mutex>
 #include <tuple>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "bf.h"
@@ -52,8 +53,12 @@ bool tunable(const bf_plan_s *p) {
 bf::Geometry geometry_with(const bf_plan_s *p, int H, int W, int tile_override, int kb_single,
                            int ka_one) {
   int tile = 0, q = 0;
+  // an untuned image of a lattice-kernel plan gets a table tile of whole lattice tiles
+  const bf::DevTables &ht = p->host_tables;
+  const bool tables = !ht.direct && !ht.range_box && !ht.reduced;
+  const int row_unit = tables && bf::lookup_kernel_for(ht, kb_single) == 3 ? bf::lattice_rows(ht) : 0;
   bf::choose_tiling(H, W, p->fit.radius, p->host_tables.n_terms, tile_override ? tile_override : p->tile,
-                    p->gmax, &tile, &q);
+                    p->gmax, row_unit, &tile, &q);
   // a direct plan keeps no tables: an empty workspace
   const bool no_tables = p->host_tables.direct || p->host_tables.range_box || p->host_tables.reduced;
   bf::Geometry g = bf::make_geometry(H, W, tile, p->fit.radius, no_tables ? 0 : p->host_tables.n_images, q);
@@ -583,7 +588,14 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
     int tile, single, one;
   };
   std::vector<Cand> cands;
-  for (int t : {64, 128, 256, 512}) {
+  // the general tiles, and for a lattice plan the tiles that hold whole lattice tiles
+  std::vector<int> tiles = {64, 128, 256, 512};
+  if (bf::lattice_eligible(h)) {
+    const int l = std::lcm(64, bf::lattice_rows(h));
+    for (int c = l; c <= 576; c += l)
+      if (std::find(tiles.begin(), tiles.end(), c) == tiles.end()) tiles.push_back(c);
+  }
+  for (int t : tiles) {
     if (t + 2 * r + 1 > 1024) continue;
     if ((t > 64 && (t / 2) >= std::max(H, W))) continue;  // one tile already covers the image
     for (int one = 0; one < 2; ++one) {
@@ -750,7 +762,7 @@ bf_status_t bf_plan_query(bf_plan_t plan, bf_plan_info_t *info) {
     info->sat_shift = (int)std::lround(std::log2((double)plan->host_tables.box_scale));
   } else {  // q depends on r and gmax only
     int tile = 0, q = 0;
-    bf::choose_tiling(64, 64, f.radius, plan->host_tables.n_terms, 64, plan->gmax, &tile, &q);
+    bf::choose_tiling(64, 64, f.radius, plan->host_tables.n_terms, 64, plan->gmax, 0, &tile, &q);
     info->sat_shift = q;
   }
   info->T_s = f.T_s;
@@ -767,6 +779,17 @@ bf_status_t bf_image_geometry(bf_plan_t plan, int H, int W, int *tile, int *sat_
   if (tile) *tile = g.tile;
   if (sat_shift) *sat_shift = g.sat_shift;
   if (ws_bytes) *ws_bytes = g.bytes;
+  return BF_OK;
+}
+
+bf_status_t bf_image_lookup_kernel(bf_plan_t plan, int H, int W, int *kind) {
+  if (!plan || !kind || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
+  const bf::DevTables &h = plan->host_tables;
+  if (h.direct || h.range_box || h.level_fold || h.reduced) {
+    *kind = -1;
+    return BF_OK;
+  }
+  *kind = bf::lookup_kernel_for(h, geometry_of(plan, H, W).kb_single);
   return BF_OK;
 }
 

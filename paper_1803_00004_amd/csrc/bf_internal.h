@@ -132,7 +132,9 @@ Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat
 
 // Table tile and fixed-point shift for one image: `fixed_tile` if nonzero,
 // else the largest of 512, 256, 128, 64 that gives >= 2048 term waves with a
-// table row of <= 768 columns (the smallest such tile otherwise).  Term values
+// table row of <= 768 columns (the smallest such tile otherwise); with
+// row_unit > 0 (the output rows of a lattice-kernel tile) the candidates are
+// the multiples of both 64 and row_unit up to 576 instead, where there are any.  Term values
 // are stored as round(v * 2^q) in int32 and tables are summed with wrapping
 // 32-bit adds.  Every tap belongs to a symmetric quadruplet, so the kernels
 // only ever use box differences, which are exact modulo 2^32 whenever the box
@@ -140,7 +142,7 @@ Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat
 // (2r + 1)^2 (gmax 2^q (1 + 2^-20) + 1) <= 2^31 - 1 (the factor covers the
 // FP32 rounding of the products that are quantised), independent of the tile.
 // A pure function of its arguments, so every call path tiles an image alike.
-void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int *tile,
+void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int row_unit, int *tile,
                    int *sat_shift);
 
 // Row pitch (int32 elements) of the LDS tile kernel's staged table region for
@@ -207,9 +209,12 @@ void set_fused_batch(int on);
 int lookup_kernel_kind(const DevTables &h);
 // The lookup kernel an image runs: 0 per-pixel, 1 LDS tile double-buffered,
 // 2 LDS tile single-buffered, 3 lattice (Geometry.kb_single selects among
-// the eligible ones; 0 there: the LDS tile kernel where it applies, else the
-// lattice kernel where it applies).
+// the eligible ones; 0 there: the double-buffered LDS tile kernel where it
+// applies, else the lattice kernel for plans of more than 8 quadruplets where
+// it applies, else the LDS tile kernel, else the lattice kernel).
 int lookup_kernel_for(const DevTables &h, int kb_single);
+// output rows of one lattice-kernel tile (s U G)
+int lattice_rows(const DevTables &h);
 bool lattice_eligible(const DevTables &h);
 size_t lattice_lds_bytes(const DevTables &h);
 bool kb_tile_eligible(const DevTables &h);

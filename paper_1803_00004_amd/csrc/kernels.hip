@@ -35,6 +35,7 @@
 #include <atomic>
 #include <mutex>
 #include <type_traits>
+#include <numeric>
 #include <vector>
 
 #include "bf_internal.h"
@@ -755,23 +756,28 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
 
 // ---------------------------------------------------------------------------
 // K-B, lattice form.  For plans whose quadruplet rows lie on a lattice, dy_j
-// = dy_0 + j s (j < M), every thread owns U = 4 pixels of one column spaced
+// = dy_0 + j s (j < M), every thread owns U = 8 pixels of one column spaced
 // s rows apart: pixel u's top corner of row j (1 - dy_j) and pixel u''s with
 // u' - j' = u - j are the same table row, and likewise at the bottom, so the
 // U pixels' boxes read only U + M - 1 distinct rows per side, and each row's
 // difference between a box's right and left corner columns, h = S(row, R_i)
 // - S(row, L_i), is taken once and serves up to min(U, M) boxes:
 //   box(u, j, i) = h(bottom row u + j, i) - h(top row u + M - 1 - j, i),
-// exact in int32 like the four-corner form (the same integer).
+// exact in int32 like the four-corner form (the same integer).  At r = 48
+// (s = 12, M = N = 4) that is 22 table reads per pixel and table against the
+// four-corner form's 48.
 //
-// The staged region is cut into two bands, the rows of the top corners and
-// the rows of the bottom corners, which alternate between two LDS buffers:
-// the copy of the bottom band of table m runs while the top band is read
-// (its differences kept in registers), and the copy of the top band of table
-// m + 1 while the bottom band is read and folded, so the copies hide behind
-// the arithmetic even where two whole regions would not fit.  Within a band
-// the rows are stored by residue modulo s, so a thread's U + M - 1 rows are
-// consecutive and their offsets are instruction immediates.
+// The block stages the whole region of a table (TR + dy span rows) in LDS,
+// its rows stored by residue modulo s, so a thread's U + M - 1 top rows are
+// consecutive LDS rows, and so are its bottom rows: every offset of one side
+// is an instruction immediate from one address per corner column.  A table
+// is read in two phases, the top rows' differences first (kept in
+// registers), then the bottom rows, the boxes and the fold.  The region's
+// first B0 rows hold top corners only, and with one lattice group the rows of
+// residue rho are read only by wave rho: each wave copies those rows of the
+// next table as soon as its own top phase has read them, so that copy runs
+// beside the bottom phase; the other rows are copied after the barrier that
+// ends the table.
 //
 // Output tiles are TR = s U G rows (G groups of s waves) by 64 columns,
 // clipped to the table tile they lie in.  The block has 16 waves: all copy,
@@ -779,15 +785,14 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
 // order of the plan's quadruplet list, so the result is bitwise that of the
 // LDS tile kernel.
 // ---------------------------------------------------------------------------
-constexpr int kLatU = 4;
+constexpr int kLatU = 8;
 
-// Band buffers of the lattice kernel: two (three, with each band copied two
-// phases ahead, measured slower).
-constexpr int kLatBuffers = 2;
-
+// LDS of the lattice kernel: the region's rows, every residue class modulo s
+// padded to the same count
 size_t lattice_lds_bytes(const DevTables &h) {
-  const int KB = kLatU * h.lat_g + h.lat_m - 1;
-  return (size_t)kLatBuffers * h.lat_s * KB * h.lat_pitch * sizeof(int32_t);
+  const int RH = h.lat_s * kLatU * h.lat_g + h.tap_dy_max - h.tap_dy_min;
+  const int KB = (RH + h.lat_s - 1) / h.lat_s;
+  return (size_t)h.lat_s * KB * h.lat_pitch * sizeof(int32_t);
 }
 
 // Output-tile grid of the lattice kernel for an image: rows of tiles per table
@@ -812,15 +817,12 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
                                         const int32_t *__restrict__ ws, float *__restrict__ out,
                                         float *__restrict__ num_out, float *__restrict__ den_out, int L) {
   constexpr int U = kLatU;
-  constexpr int KR = U + M - 1;      // distinct corner rows per band and thread
+  constexpr int KT = U + M - 1;      // distinct corner rows per side and thread
   constexpr uint32_t P4 = PITCH * 4u;
   constexpr int CC = (PITCH + 63) / 64;
   extern __shared__ int lds[];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = tab->lat_s, G = tab->lat_g;
-  const int KB = U * G + M - 1;      // band rows per residue
-  const int BR = s * KB;             // band rows
-  constexpr int NB = kLatBuffers;
   const LatGrid lg = lat_grid(p.H, p.W, p.tile, s, G);
   // XCD-aware patches of 8 x 4 tiles (as the LDS tile kernel)
   constexpr int PW = 8, PH = 4;
@@ -840,7 +842,9 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
   const int dy0 = tab->tap_dy_min, dx0 = tab->tap_dx_min;
   const int RW = 64 + tab->tap_dx_max - dx0;
   const int dymax = tab->lat_dy0 + (M - 1) * s;
-  const int B0 = tab->lat_dy0 + dymax - 1;                     // region row of the bottom band's start
+  const int B0 = tab->lat_dy0 - dy0;                          // region row of the first bottom corner
+  const int RH = lg.TR + dymax - dy0;                          // region rows (image rows y0 + dy0 + R)
+  const int KB = (RH + s - 1) / s;                             // LDS rows per residue class
   const int erows = (int)(p.table_elems / p.pitch);            // rows of a table
   const uint32_t te4 = (uint32_t)p.table_elems * 4u;
   const __amdgpu_buffer_rsrc_t rsrc =
@@ -848,14 +852,11 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
   const int x = x0 + lane;
   const bool xin = x < p.W;
 
-  // Copies.  Band k is the top (k even) or bottom (k odd) band of table k / 2,
-  // in buffer k mod NB; its row R (region row R, or B0 + R) goes to LDS row
-  // (R mod s) KB + R div s.  Every wave copies rows wave, wave + 16, ...
+  // Copies.  Region row R of table m goes to LDS row (R mod s) KB + R div s.
   uint32_t xoff4[CC];
 #pragma unroll
   for (int c = 0; c < CC; ++c) xoff4[c] = (uint32_t)(min(max(x0 + dx0 + lane + 64 * c, 0), p.W) - ox) * 4u;
   const uint32_t gp4 = (uint32_t)p.pitch * 4u;
-  const int QR = (BR + 15) / 16;
   // where the region's columns need no clamp and start on a 16-byte boundary
   // of the table, a row is one 16-byte copy per lane (lanes 0 .. RW/4)
   const int cx0 = x0 + dx0 - ox;  // table column of region column 0
@@ -863,27 +864,28 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
   const uint32_t xoff16 = (uint32_t)(cx0 + 4 * lane) * 4u;
   const bool lane16 = 4 * lane < RW;
   const int nchunk = (RW + 63) / 64;
-  auto stage = [&](int k) {
-    const int m = k >> 1, b = k & 1;
-    const uint32_t sm = (uint32_t)m * te4;
-    int *base = lds + (k % NB) * BR * PITCH;
-    int R = wave, rq = wave / s, rr = wave - (wave / s) * s;
-    for (int t = 0; t < QR && R < BR; ++t) {
-      const int Rc = R;
-      const int Y = min(min(max(y0 + dy0 + (b ? B0 : 0) + Rc, 0), p.H) - oy, erows - 1);
-      const uint32_t soff = sm + (uint32_t)Y * gp4;
-      int *dst = base + (rr * KB + rq) * PITCH;
-      if (wide) {
-        if (lane16) __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)dst, 16, xoff16, soff, 0, 0);
-      } else {
+  auto copy_row = [&](int m, int R, int lrow) {
+    const int Y = min(min(max(y0 + dy0 + R, 0), p.H) - oy, erows - 1);
+    const uint32_t soff = (uint32_t)m * te4 + (uint32_t)Y * gp4;
+    int *dst = lds + lrow * PITCH;
+    if (wide) {
+      if (lane16) __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)dst, 16, xoff16, soff, 0, 0);
+    } else {
 #pragma unroll
-        for (int c = 0; c < CC; ++c)
-          if (c < nchunk && lane + 64 * c < RW)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)(dst + 64 * c), 4, xoff4[c], soff, 0, 0);
-      }
-      R += 16;
-      rq += 16 / s;
-      rr += 16 - (16 / s) * s;
+      for (int c = 0; c < CC; ++c)
+        if (c < nchunk && lane + 64 * c < RW)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)(dst + 64 * c), 4, xoff4[c], soff, 0, 0);
+    }
+  };
+  // rows [lo, RH) of table m: wave w copies rows lo + w, lo + w + 16, ...
+  const int d16 = 16 / s, m16 = 16 - d16 * s;
+  auto stage_from = [&](int m, int lo) {
+    int R = lo + wave;
+    int rq = R / s, rr = R - rq * s;
+    for (; R < RH; R += 16) {
+      copy_row(m, R, rr * KB + rq);
+      rq += d16;
+      rr += m16;
       if (rr >= s) {
         rr -= s;
         ++rq;
@@ -894,14 +896,18 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
   // this wave's pixels: group g, residue rho; pixel u at tile row g s U + rho + u s
   const bool comp = wave < s * G;
   const int g = comp ? wave / s : 0, rho = comp ? wave - (wave / s) * s : 0;
-  const int brow = rho * KB + g * U;  // LDS row of the thread's first corner row in a band
-  uint32_t aL0[N], aR0[N];            // LDS byte addresses in buffer 0, per column pair
+  const int tq = rho * KB + g * U;             // LDS row of the thread's first top corner row
+  const int cb = B0 + rho;                      // region row of its first bottom corner row (group 0)
+  const int bq = (cb % s) * KB + cb / s + g * U;  // its LDS row
+  uint32_t aTL[N], aTR[N], aBL[N], aBR[N];      // LDS byte addresses per corner column
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     const int dx = tab->lat_dx[i];
-    const uint32_t rb = (uint32_t)(brow * PITCH + lane) * 4u;
-    aL0[i] = rb + (uint32_t)(1 - dx - dx0) * 4u;
-    aR0[i] = rb + (uint32_t)(dx - dx0) * 4u;
+    const uint32_t cl = (uint32_t)(lane + 1 - dx - dx0) * 4u, cr = (uint32_t)(lane + dx - dx0) * 4u;
+    aTL[i] = tq * P4 + cl;
+    aTR[i] = tq * P4 + cr;
+    aBL[i] = bq * P4 + cl;
+    aBR[i] = bq * P4 + cr;
   }
   float wq[M][N];
 #pragma unroll
@@ -909,7 +915,7 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
 #pragma unroll
     for (int i = 0; i < N; ++i) wq[j][i] = tab->lat_w[4 * j + i];
 
-  float pxv[U], num[U], den[U], d0[U], cs[U], sn[U];
+  float pxv[U], num[U], den[U], cs[U], sn[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int y = y0 + g * s * U + rho + u * s;
@@ -920,29 +926,18 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
       pxv[u] = px;
     }
     num[u] = den[u] = 0.0f;
-    d0[u] = comp ? k0_denominator(tab, y, x, p.H, p.W) : 0.0f;
     cs[u] = sn[u] = 0.0f;
   }
   const float inv = p.inv_sat_scale;
-  int ht[KR][N];  // top-band differences of the current table
 
   const int n = tab->n_images;  // this plan's tables (the workspace may hold more: p.n_images)
-  const int nbands = 2 * n;
-  stage(0);
-  __builtin_amdgcn_s_waitcnt(0);  // band 0 has landed
-  __syncthreads();
-  for (int k = 0; k < nbands; ++k) {
-    const bool ahead = k + NB - 1 < nbands;
-    if (ahead) stage(k + NB - 1);  // its buffer held band k - 1, which every wave has finished
-    const uint32_t bo = (uint32_t)((k % NB) * BR * PITCH) * 4u;
-    if (comp && !(k & 1)) {
-#pragma unroll
-      for (int kt = 0; kt < KR; ++kt)
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-          ht[kt][i] = (int)((uint32_t)lds_ld(lds, aR0[i] + bo + kt * P4) - (uint32_t)lds_ld(lds, aL0[i] + bo + kt * P4));
-    } else if (comp) {
-      const int m = k >> 1;
+  const bool own = G == 1;      // copy of the top-only rows by their one reader
+  stage_from(0, 0);
+  for (int m = 0; m < n; ++m) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of table m have landed
+    __syncthreads();                // every wave's have
+    const bool ahead = m + 1 < n;
+    if (comp) {
       const int part = tab->slot_part[m];
       const float fhi = tab->slot_fhi[m], flo = tab->slot_flo[m];
       const float at = tab->slot_a[m];
@@ -954,22 +949,54 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
           sn[u] = __builtin_amdgcn_sinf(fr);
         }
       }
+      // top phase: the differences of the thread's top corner rows
+      int ht[KT][N];
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+          ht[kt][i] = (int)((uint32_t)lds_ld(lds, aTR[i] + kt * P4) - (uint32_t)lds_ld(lds, aTL[i] + kt * P4));
+      if (own && ahead) {
+        // the top rows are in registers before the next table's copy lands on them
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+          for (int i = 0; i < N; ++i) asm volatile("" : "+v"(ht[kt][i]));
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+        for (int R = rho, q = 0; R < B0; R += s, ++q) copy_row(m + 1, R, rho * KB + q);
+      }
+      // bottom phase: the boxes and the fold
       float sv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) sv[u] = 0.0f;
+      // two rows at a time (their reads pair into one instruction per column)
 #pragma unroll
-      for (int kb = 0; kb < KR; ++kb) {
+      for (int k2 = 0; k2 < KT; k2 += 2) {
+        uint32_t hb[2][N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-          const uint32_t hb =
-              (uint32_t)lds_ld(lds, aR0[i] + bo + kb * P4) - (uint32_t)lds_ld(lds, aL0[i] + bo + kb * P4);
+        for (int t = 0; t < 2 && k2 + t < KT; ++t)
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int j = kb - u;
-            if (j < 0 || j >= M) continue;
-            // pairs without a quadruplet carry weight 0 (adding 0 changes no bit)
-            const int box = (int)(hb - (uint32_t)ht[u + M - 1 - j][i]);
-            sv[u] = __builtin_fmaf(wq[j][i], (float)box, sv[u]);
+          for (int i = 0; i < N; ++i)
+            hb[t][i] = (uint32_t)lds_ld(lds, aBR[i] + (k2 + t) * P4) - (uint32_t)lds_ld(lds, aBL[i] + (k2 + t) * P4);
+        // one difference per row, shared by the row's boxes (the compiler
+        // would otherwise fold it into each box as an add and a subtract)
+#pragma unroll
+        for (int t = 0; t < 2 && k2 + t < KT; ++t)
+#pragma unroll
+          for (int i = 0; i < N; ++i) asm volatile("" : "+v"(hb[t][i]));
+#pragma unroll
+        for (int t = 0; t < 2 && k2 + t < KT; ++t) {
+          const int kb = k2 + t;
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int j = kb - u;
+              if (j < 0 || j >= M) continue;
+              // pairs without a quadruplet carry weight 0 (adding 0 changes no bit)
+              const int box = (int)(hb[t][i] - (uint32_t)ht[u + M - 1 - j][i]);
+              sv[u] = __builtin_fmaf(wq[j][i], (float)box, sv[u]);
+            }
           }
         }
       }
@@ -982,14 +1009,14 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
 #pragma unroll
       for (int u = 0; u < U; ++u) fold_table(part, an, ad, cs[u], sn[u], sv[u], num[u], den[u]);
       if (part == 4) {
+        // denominator of the k = 0 term: a_0 (K * 1)
 #pragma unroll
-        for (int u = 0; u < U; ++u) den[u] = __builtin_fmaf(at, d0[u], den[u]);
+        for (int u = 0; u < U; ++u)
+          den[u] = __builtin_fmaf(at, k0_denominator(tab, y0 + g * s * U + rho + u * s, x, p.H, p.W), den[u]);
       }
     }
-    // band k + 1 has landed; after the barrier every wave's has, and every
-    // wave is done with band k
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    __syncthreads();  // every wave is done reading table m
+    if (ahead) stage_from(m + 1, own ? B0 : 0);
   }
   if (!comp || !xin) return;
 #pragma unroll
@@ -2243,12 +2270,20 @@ static hipError_t launch_kb_tile_any(const DevTables &h, bool single, dim3 grid,
   return launch_kb_tile_pitch<kStageSingle, U8>(h.lds_pitch, nq, grid, lds, s, I, p, tab, ws, out, num, den);
 }
 
-void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int *tile,
+void choose_tiling(int H, int W, int radius, int n_terms, int fixed_tile, double gmax, int row_unit, int *tile,
                    int *sat_shift) {
   int t = fixed_tile;
   if (!t) {
-    t = 64;
-    for (int c : {512, 256, 128, 64}) {
+    // table tiles that hold whole lattice tiles (multiples of 64 and of
+    // row_unit, up to 576), else the general ones
+    std::vector<int> cands;
+    if (row_unit > 0) {
+      const int l = std::lcm(64, row_unit);
+      for (int c = (576 / l) * l; c >= l; c -= l) cands.push_back(c);
+    }
+    if (cands.empty()) cands = {512, 256, 128, 64};
+    t = cands.back();
+    for (int c : cands) {
       if (c + 2 * radius + 1 > 768) continue;
       const long long waves = (long long)((H + c - 1) / c) * ((W + c - 1) / c) * n_terms;
       t = c;
@@ -2320,9 +2355,14 @@ int lookup_kernel_for(const DevTables &h, int kb_single) {
   if (kb_single == 2 && lat) return 3;
   if (kb_single == 1 && tile) return 2;
   if (db) return 1;
+  // without double buffering, the lattice kernel's fewer table reads pay for
+  // its staging once a pixel has more than 8 boxes
+  if (lat && h.n_quads > 8) return 3;
   if (tile) return 2;
   return lat ? 3 : 0;
 }
+
+int lattice_rows(const DevTables &h) { return h.lat_s * kLatU * h.lat_g; }
 
 template <int PITCH, int M, int N, bool U8>
 static hipError_t launch_kl1(int n_tiles, size_t lds, hipStream_t s, const void *I, ImageParams p,
@@ -2581,7 +2621,14 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
   }
   // each image's lookup kernel, as its single-image call would choose it
   int kind[kMaxBatch];
-  for (int j = 0; j < n; ++j) kind[j] = lookup_kernel_for(*items[idx[j]].host, items[idx[j]].g.kb_single);
+  // (where the lattice kernel is only the default, a batch keeps the LDS tile
+  // kernel: the lattice kernel's persistent form spills registers; both give
+  // the same bits)
+  for (int j = 0; j < n; ++j) {
+    const BatchItem &it = items[idx[j]];
+    kind[j] = lookup_kernel_for(*it.host, it.g.kb_single);
+    if (kind[j] == 3 && it.g.kb_single != 2 && kb_tile_eligible(*it.host)) kind[j] = 2;
+  }
   {
     int nq, G;
     size_t lds;

@@ -117,11 +117,17 @@ def test_overlap_staging_small_and_ragged(torch_dev, ss, r, ns, pitch, H, W):
     I = synth.gen_image(H, W, 3, 0.03, 11 * H + W)
     gp, op = _plans(ss, r, ns, 0.1, 8)
     assert gp.info.lds_pitch == pitch and gp.info.lds_double_buffered == 0
+    # the LDS tile kernel pinned (the default of the 12-quadruplet plan is the
+    # lattice kernel, which must give the same bits)
+    default = _run(torch_dev, gp, I)
+    gp.set_tuning(H, W, gp.geometry(H, W)[0], 1, 0)
     out = _run(torch_dev, gp, I)
+    _bf().lib().bf_autotune_clear()
     ref = oracle.expanded_box(I, op)
     err = np.abs(out - ref).max()
     _report("overlap %dx%d r %d" % (H, W, r), err)
     assert err <= TIGHT
+    assert np.array_equal(out, default)
 
 
 def test_wide_regions_in_one_batch(torch_dev):
@@ -149,7 +155,7 @@ LATTICE_CASES = [
     (261, 389, 8.0, 24, 6, 0.1, 16, "f32", 64, 6),       # two groups of 6 waves, 64-row table tiles
     (200, 300, 3.0, 9, 4, 0.1, 8, "u8", 64, 5),          # M 2, N 2, three groups
     (130, 129, 2.0, 6, 4, 0.3, 8, "f32", 64, 3),         # five groups of 3 waves
-    (310, 520, 20.0, 60, 6, 0.2, 8, "f32", 256, 15),     # pitch 192, step 15
+    (310, 520, 13.0, 40, 6, 0.2, 8, "f32", 320, 10),     # pitch 192, step 10, 80-row lattice tiles
     (7, 13, 16.0, 48, 8, 0.05, 32, "f32", 64, 12),       # image smaller than the window
     (1, 1, 13.0, 40, 6, 0.1, 16, "f32", 64, 10),
 ]
@@ -193,7 +199,7 @@ def test_lattice_plans_in_one_batch(torch_dev):
         plans.append(bf.Plan(ss, sr, r, nr, ns))
         imgs.append(torch.from_numpy(synth.gen_image(H, W, 5, 0.03, 3 * r + H)).cuda())
     kinds = sorted(set(p.info.default_lookup for p in plans))
-    assert kinds == [0, 1, 2], kinds
+    assert kinds == [0, 1, 2, 3], kinds
     for p, (H, W, *_) in zip(plans, specs):  # the lattice kernel for every plan that can use it
         if p.info.lattice:
             p.set_tuning(H, W, p.geometry(H, W)[0], 2, 0)
@@ -465,17 +471,27 @@ def _sample_pixels(H, W, n, seed):
     rng = np.random.default_rng(seed)
     ys = rng.integers(0, H, n)
     xs = rng.integers(0, W, n)
-    edge_y = [0, 0, H - 1, H - 1, 1, H - 2, H // 2, 48, H - 49, 511, 512]
-    edge_x = [0, W - 1, 0, W - 1, W // 2, 1, W - 1, 47, 512, W - 2, 513]
+    edge_y = [0, 0, H - 1, H - 1, 1, H - 2, H // 2, 48, H - 49, 511, 512, 575, 576, 671, 672]
+    edge_x = [0, W - 1, 0, W - 1, W // 2, 1, W - 1, 47, 512, W - 2, 513, 576, 575, 672, 671]
     return np.concatenate([ys, edge_y]).astype(np.int32), np.concatenate([xs, edge_x]).astype(np.int32)
 
 
 @pytest.mark.parametrize("name", ["cfg3_4096", "cfg5_4096_u8"])
 def test_4096_sampled(torch_dev, name):
+    """4096^2 in the launch shape an untuned call takes (the lattice lookup
+    kernel on 576-row table tiles), sampled against T2 with borders, tile and
+    lattice-tile seams; and bitwise against the LDS tile kernel pinned on
+    512-row table tiles."""
     c = CONFIGS[name]
     I = synth.config_image(name)
     gp, op = _plans(c["sigma_s"], c["radius"], c["n_spatial"], c["sigma_r"], c["n_range"], dtype=c["dtype"])
+    assert gp.info.default_lookup == 3 and gp.geometry(4096, 4096)[0] == 576
     out = _run(torch_dev, gp, I)
+    gp.set_tuning(4096, 4096, 512, 1, 0)
+    try:
+        assert np.array_equal(_run(torch_dev, gp, I), out)
+    finally:
+        _bf().lib().bf_autotune_clear()
     ys, xs = _sample_pixels(4096, 4096, 1500, 7)
     ref = oracle.expanded_brute(I, op, ys, xs)
     err = np.abs(out[ys, xs] - ref).max()

@@ -123,6 +123,35 @@ def test_tiling_keeps_boxes_in_int32():
                 assert nbytes == p.workspace_size(H, W) and p.geometry(H, W) == (tile, q, nbytes)
 
 
+def test_lookup_kernel_choice_and_lattice_tiles():
+    """Which lookup kernel an untuned image runs: the double-buffered LDS tile
+    kernel where two regions fit (r <= 32), the lattice kernel for plans of
+    more than 8 quadruplets on a row lattice (r = 48, N_s = 8: 96-row lattice
+    tiles, table tiles of 576 rows at 4096^2 and whole lattice tiles on every
+    image), else the LDS tile kernel; a tuned choice wins; plans without
+    tables have none."""
+    cfg3 = bf.Plan(16.0, 0.05, 48, 32, 8, host_only=True)
+    assert cfg3.info.lattice == 1 and cfg3.info.lattice_step == 12 and cfg3.info.n_quads == 12
+    assert cfg3.info.default_lookup == 3 and cfg3.lookup_kernel(4096, 4096) == 3
+    for H, W in ((4096, 4096), (1080, 1920), (300, 517), (1, 1), (32768, 48)):
+        tile = cfg3.geometry(H, W)[0]
+        assert tile % 64 == 0 and tile % 96 == 0 and tile <= 576, (H, W, tile)
+    assert cfg3.geometry(4096, 4096)[0] == 576
+    try:
+        cfg3.set_tuning(4096, 4096, 512, 1, 0)
+        assert cfg3.lookup_kernel(4096, 4096) == 2 and cfg3.geometry(4096, 4096)[0] == 512
+        assert cfg3.lookup_kernel(1080, 1920) == 3  # another size bucket keeps the default
+    finally:
+        bf.lib().bf_autotune_clear()
+    four = bf.Plan(16.0, 0.1, 48, 8, 4, host_only=True)  # 4 quadruplets: the overlap-staged tile kernel
+    assert four.info.lattice == 1 and four.info.n_quads == 4 and four.lookup_kernel(4096, 4096) == 2
+    assert bf.Plan(8.0, 0.1, 24, 16, 4, host_only=True).lookup_kernel(1080, 1920) == 1
+    assert bf.Plan(23.3, 0.1, 70, 8, 4, host_only=True).lookup_kernel(300, 300) == 0
+    assert bf.Plan(3.0, 0.1, 9, 8, 4, host_only=True, direct=True).lookup_kernel(64, 64) == -1
+    with pytest.raises(bf.BFError):
+        cfg3.lookup_kernel(0, 5)
+
+
 def test_symmetric_taps_pair_into_quadruplets():
     """The expansion is symmetric on each axis, so every tap (dy, dx) has
     partners (1-dy, dx), (dy, 1-dx), (1-dy, 1-dx) with weights -w, -w, w up to
