@@ -824,8 +824,10 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = tab->lat_s, G = tab->lat_g;
   const LatGrid lg = lat_grid(p.H, p.W, p.tile, s, G);
-  // XCD-aware patches of 8 x 4 tiles (as the LDS tile kernel)
-  constexpr int PW = 8, PH = 4;
+  // XCD-aware patches of one table tile each: the tiles one XCD runs at the
+  // same time read one tile's tables, whose halo rows and columns they share
+  // in that XCD's L2
+  const int PW = p.tile / 64, PH = lg.nsub;
   const int pr = L / (PH * lg.ntx);
   const int rem = L - pr * PH * lg.ntx;
   const int ph = min(PH, lg.nty - pr * PH);
