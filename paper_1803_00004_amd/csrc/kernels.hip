@@ -786,6 +786,10 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
 // LDS tile kernel.
 // ---------------------------------------------------------------------------
 constexpr int kLatU = 8;
+// lattice box mask (bit 4 j + i) of the N_s = 8 Gaussian expansion: its
+// eight level groups leave no box whose row and column indices are both 0 or
+// 2 (offsets of 1 and 3 lattice steps)
+constexpr uint32_t kLatMaskNs8 = 0xFAFAu;
 
 // LDS of the lattice kernel: the region's rows, every residue class modulo s
 // padded to the same count
@@ -811,7 +815,9 @@ __host__ __device__ inline LatGrid lat_grid(int H, int W, int tile, int s, int g
   return q;
 }
 
-template <int PITCH, int M, int N, bool U8>
+// MASK: bit 4 j + i set where the plan may have a box (dy_j, dx_i); boxes
+// outside it have weight 0 and are skipped (adding 0 changes no bit).
+template <int PITCH, int M, int N, bool U8, uint32_t MASK = 0xFFFFu>
 __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageParams &p,
                                         const DevTables *__restrict__ tab,
                                         const int32_t *__restrict__ ws, float *__restrict__ out,
@@ -994,7 +1000,7 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
 #pragma unroll
             for (int u = 0; u < U; ++u) {
               const int j = kb - u;
-              if (j < 0 || j >= M) continue;
+              if (j < 0 || j >= M || !((MASK >> (4 * j + i)) & 1u)) continue;
               // pairs without a quadruplet carry weight 0 (adding 0 changes no bit)
               const int box = (int)(hb[t][i] - (uint32_t)ht[u + M - 1 - j][i]);
               sv[u] = __builtin_fmaf(wq[j][i], (float)box, sv[u]);
@@ -1033,7 +1039,7 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
   }
 }
 
-template <int PITCH, int M, int N, bool U8>
+template <int PITCH, int M, int N, bool U8, uint32_t MASK = 0xFFFFu>
 __global__ __launch_bounds__(1024) void kl_tile(const void *__restrict__ I, ImageParams p,
                                                const DevTables *__restrict__ tab,
                                                const int32_t *__restrict__ ws,
@@ -1042,7 +1048,7 @@ __global__ __launch_bounds__(1024) void kl_tile(const void *__restrict__ I, Imag
   const int per_xcd = (n_tiles + 7) / 8;
   const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (L >= n_tiles) return;
-  kl_body<PITCH, M, N, U8>(I, p, tab, ws, out, num_out, den_out, L);
+  kl_body<PITCH, M, N, U8, MASK>(I, p, tab, ws, out, num_out, den_out, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -2366,10 +2372,10 @@ int lookup_kernel_for(const DevTables &h, int kb_single) {
 
 int lattice_rows(const DevTables &h) { return h.lat_s * kLatU * h.lat_g; }
 
-template <int PITCH, int M, int N, bool U8>
+template <int PITCH, int M, int N, bool U8, uint32_t MASK = 0xFFFFu>
 static hipError_t launch_kl1(int n_tiles, size_t lds, hipStream_t s, const void *I, ImageParams p,
                              const DevTables *tab, const int32_t *ws, float *out, float *num, float *den) {
-  auto k = kl_tile<PITCH, M, N, U8>;
+  auto k = kl_tile<PITCH, M, N, U8, MASK>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(8 * ((n_tiles + 7) / 8)), dim3(1024), lds, s, I, p, tab, ws, out, num, den, n_tiles);
@@ -2386,8 +2392,13 @@ static hipError_t launch_kl_mn(const DevTables &h, int n_tiles, size_t lds, hipS
                       : launch_kl1<PITCH, 2, 2, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den);
     case 3: return n4 ? launch_kl1<PITCH, 3, 4, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den)
                       : launch_kl1<PITCH, 3, 2, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den);
-    default: return n4 ? launch_kl1<PITCH, 4, 4, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den)
-                       : launch_kl1<PITCH, 4, 2, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den);
+    default:
+      // the boxes of the N_s = 8 Gaussian expansion's level groups: an
+      // instantiation that skips the 4 empty ones of the 16
+      if (n4 && h.lat_mask == (int)kLatMaskNs8)
+        return launch_kl1<PITCH, 4, 4, U8, kLatMaskNs8>(n_tiles, lds, s, I, p, tab, ws, out, num, den);
+      return n4 ? launch_kl1<PITCH, 4, 4, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den)
+                : launch_kl1<PITCH, 4, 2, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den);
   }
 }
 

@@ -150,7 +150,8 @@ def test_wide_regions_in_one_batch(torch_dev):
 # (after splitting steps above 16) and the LDS pitch of the lattice kernel:
 # (H, W, sigma_s, r, N_s, sigma_r, N_r, dtype, table tile, s).
 LATTICE_CASES = [
-    (300, 517, 16.0, 48, 8, 0.05, 32, "f32", 512, 12),   # M 4, N 4, pitch 192
+    (300, 517, 16.0, 48, 8, 0.05, 32, "f32", 512, 12),   # M 4, N 4, pitch 192 (the 12 boxes of N_s = 8)
+    (211, 333, 16.0, 48, 8, 0.05, 32, "u8", 384, 12),    # the same boxes, 8-bit input, whole lattice tiles
     (333, 290, 16.0, 48, 4, 0.1, 8, "u8", 128, 12),      # step 24 split in two (M 3); tiles clip at 128
     (261, 389, 8.0, 24, 6, 0.1, 16, "f32", 64, 6),       # two groups of 6 waves, 64-row table tiles
     (200, 300, 3.0, 9, 4, 0.1, 8, "u8", 64, 5),          # M 2, N 2, three groups
