@@ -327,7 +327,8 @@ bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, i
  * plan -- table tiles of 64, 128, 256 and 512, and for a plan the lattice
  * kernel applies to, the multiples of 64 up to 576 that hold whole lattice
  * tiles (tile + 2r + 1 <= 1024), each
- * with one range term or one table per table-kernel wave, and with every
+ * with one range term, one table or one cosine or sine pair of tables per
+ * table-kernel wave, and with every
  * lookup kernel the plan can use (LDS tile double- or single-buffered,
  * lattice; all give the same bits) --
  * on a temporary mid-grey image (reps launches each, at least
@@ -345,8 +346,9 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
  * by hand, as bf_autotune would: table tile (a multiple of 64 with
  * tile + 2r + 1 <= 1024), kb_single (the lookup kernel: 0 the default
  * choice, 1 the LDS tile kernel single-buffered, 2 the lattice kernel; a
- * kernel the plan cannot use falls back to the default), ka_one (1: one table
- * per table-kernel wave).  BF_ERR_UNSUPPORTED for plans
+ * kernel the plan cannot use falls back to the default), ka_one (table-kernel
+ * waves: 0 one range term each, 1 one table, 2 the cosine pair C I, C or the
+ * sine pair S I, S of a term; BF_ERR_INVALID_ARG otherwise).  BF_ERR_UNSUPPORTED for plans
  * that are not tuned (a fixed tile, direct, range-box or reduced plans). */
 bf_status_t bf_tuning_set(bf_plan_t plan, int H, int W, int tile, int kb_single, int ka_one);
 /* Forget every tuned shape. */

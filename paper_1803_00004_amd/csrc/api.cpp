@@ -598,7 +598,7 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
   for (int t : tiles) {
     if (t + 2 * r + 1 > 1024) continue;
     if ((t > 64 && (t / 2) >= std::max(H, W))) continue;  // one tile already covers the image
-    for (int one = 0; one < 2; ++one) {
+    for (int one = 0; one < 3; ++one) {
       // the default lookup kernel, and each other one the plan can use
       const int dflt = bf::lookup_kernel_for(h, 0);
       cands.push_back({t, 0, one});
@@ -667,7 +667,7 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
 bf_status_t bf_tuning_set(bf_plan_t plan, int H, int W, int tile, int kb_single, int ka_one) {
   if (!plan || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return BF_ERR_INVALID_ARG;
   if (tile < 64 || tile % 64 || tile + 2 * plan->fit.radius + 1 > 1024 || kb_single < 0 || kb_single > 2 ||
-      ka_one & ~1)
+      ka_one < 0 || ka_one > 2)
     return BF_ERR_INVALID_ARG;
   if (!tunable(plan)) return BF_ERR_UNSUPPORTED;
   std::lock_guard<std::mutex> lk(g_tune_mu);

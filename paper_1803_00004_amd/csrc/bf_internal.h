@@ -125,7 +125,8 @@ struct Geometry {
   size_t bytes;                     // whole workspace
   int kb_single = 0;                // lookup kernel: 0 the default choice, 1 the LDS tile kernel
                                     // single-buffered, 2 the lattice kernel (lookup_kernel_for)
-  int ka_one = 0;                   // 1: one table per table-kernel wave (else one range term)
+  int ka_one = 0;                   // table-kernel waves: 0 one range term each, 1 one table,
+                                    // 2 a cosine or sine pair of tables
 };
 
 Geometry make_geometry(int H, int W, int tile, int radius, int n_images, int sat_shift);

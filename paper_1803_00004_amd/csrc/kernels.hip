@@ -106,18 +106,21 @@ constexpr int kPF = 4;
 
 // ONE = false: a wave builds the 1 or 4 tables of one range term (one sin/cos
 // per pixel for all four); ONE = true: a wave builds one table (4x the waves
-// for the same tile, so larger tiles keep the chip busy).  Both store the
-// same integers.  One wave builds unit `unit` (a term, or with ONE a table)
-// of table tile tile_id.  DYN: the wave's 8-bit lookup table lives in the
+// for the same tile, so larger tiles keep the chip busy); PAIR: a wave builds
+// the cosine pair (C*I, C) or the sine pair (S*I, S) of a term (2x the waves,
+// one of sin/cos per pixel each).  All store the same integers.  One wave
+// builds unit `unit` (a term, with ONE a table, with PAIR 2 term + pair) of
+// table tile tile_id.  DYN: the wave's 8-bit lookup table lives in the
 // dynamic LDS (the fused batch kernel), else in a static array of 4 waves.
-template <int G, bool U8, bool ONE, bool DYN>
+template <int G, bool U8, bool ONE, bool DYN, bool PAIR = false>
 __device__ __forceinline__ void ka_unit(const void *__restrict__ I, const ImageParams &p,
                                         const DevTables *__restrict__ tab, int32_t *__restrict__ ws,
                                         int tile_id, int unit) {
   // the wave index is uniform; saying so keeps per-term loads scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int term = ONE ? tab->slot_term[unit] : unit;
+  const int term = ONE ? tab->slot_term[unit] : PAIR ? unit >> 1 : unit;
   const int part = ONE ? tab->slot_part[unit] : 0;  // ONE: the table's part (4: k = 0)
+  const int half = PAIR ? unit & 1 : 0;              // PAIR: 0 the cosine pair, 1 the sine pair
   const int ty = tile_id / p.tiles_x, tx = tile_id - ty * p.tiles_x;
   const int y0 = ty * p.tile, x0 = tx * p.tile;
   const int y1 = min(p.H, y0 + p.tile), x1 = min(p.W, x0 + p.tile);
@@ -125,11 +128,13 @@ __device__ __forceinline__ void ka_unit(const void *__restrict__ I, const ImageP
   const int Eh = min(y1 + p.radius, p.H) - oy + 1;
   const int Ew = min(x1 + p.radius, p.W) - ox + 1;
   const bool k0 = tab->k_is_zero[term] != 0;
-  const int nimg = (k0 || ONE) ? 1 : 4;
+  if (PAIR && k0 && half) return;  // the k = 0 term's one table is its first wave's
+  const int nimg = (k0 || ONE) ? 1 : PAIR ? 2 : 4;
   const float f_hi = tab->f_hi[term], f_lo = tab->f_lo[term];
   const float scale = p.sat_scale;
-  int32_t *base = ws + ((long long)tile_id * p.n_images + (ONE ? unit : tab->slot[term])) * p.table_elems;
-  const long long te = p.table_elems;
+  int32_t *base = ws + ((long long)tile_id * p.n_images + (ONE ? unit : tab->slot[term] + half)) * p.table_elems;
+  // the wave's m-th table (PAIR: parts half and half + 2 of the term)
+  const long long te = (PAIR ? 2 : 1) * (long long)p.table_elems;
 
   // 8-bit input takes 256 values only: each wave tabulates its term's four
   // quantised values per byte value in LDS, with the very expressions of the
@@ -217,6 +222,9 @@ __device__ __forceinline__ void ka_unit(const void *__restrict__ I, const ImageP
           const int4 e = lut[(int)px];
           if (ONE) {
             v[0][c] = (uint32_t)(part == 0 ? e.x : part == 1 ? e.y : part == 2 ? e.z : e.w);
+          } else if (PAIR) {
+            v[0][c] = (uint32_t)(half ? e.y : e.x);
+            v[1][c] = (uint32_t)(half ? e.w : e.z);
           } else {
             v[0][c] = (uint32_t)e.x;
             v[1][c] = (uint32_t)e.y;
@@ -228,6 +236,11 @@ __device__ __forceinline__ void ka_unit(const void *__restrict__ I, const ImageP
           const float fr = phase_rev(f_hi, f_lo, px);
           const float t = (part & 1) ? __builtin_amdgcn_sinf(fr) : __builtin_amdgcn_cosf(fr);
           v[0][c] = (uint32_t)__float2int_rn(t * (part < 2 ? xs : scale));
+        } else if (PAIR) {
+          const float fr = phase_rev(f_hi, f_lo, px);
+          const float t = half ? __builtin_amdgcn_sinf(fr) : __builtin_amdgcn_cosf(fr);
+          v[0][c] = (uint32_t)__float2int_rn(t * xs);
+          v[1][c] = (uint32_t)__float2int_rn(t * scale);
         } else {
           const float fr = phase_rev(f_hi, f_lo, px);
           const float C = __builtin_amdgcn_cosf(fr), S = __builtin_amdgcn_sinf(fr);
@@ -261,20 +274,20 @@ __device__ __forceinline__ void ka_unit(const void *__restrict__ I, const ImageP
 }
 
 // Blocks of 4 waves: wave w builds unit 4 unit_group + w of the tile.
-template <int G, bool U8, bool ONE>
+template <int G, bool U8, bool ONE, bool PAIR = false>
 __device__ __forceinline__ void ka_body(const void *__restrict__ I, const ImageParams &p,
                                         const DevTables *__restrict__ tab, int32_t *__restrict__ ws,
                                         int tile_id, int unit_group) {
   const int unit = unit_group * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (unit >= (ONE ? p.n_images : p.n_terms)) return;
-  ka_unit<G, U8, ONE, false>(I, p, tab, ws, tile_id, unit);
+  if (unit >= (ONE ? p.n_images : PAIR ? 2 * p.n_terms : p.n_terms)) return;
+  ka_unit<G, U8, ONE, false, PAIR>(I, p, tab, ws, tile_id, unit);
 }
 
-template <int G, bool U8, bool ONE>
+template <int G, bool U8, bool ONE, bool PAIR = false>
 __global__ __launch_bounds__(256) void ka_sat(const void *__restrict__ I, ImageParams p,
                                              const DevTables *__restrict__ tab,
                                              int32_t *__restrict__ ws) {
-  ka_body<G, U8, ONE>(I, p, tab, ws, blockIdx.x, blockIdx.y);
+  ka_body<G, U8, ONE, PAIR>(I, p, tab, ws, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -830,10 +843,12 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = tab->lat_s, G = tab->lat_g;
   const LatGrid lg = lat_grid(p.H, p.W, p.tile, s, G);
-  // XCD-aware patches of one table tile each: the tiles one XCD runs at the
-  // same time read one tile's tables, whose halo rows and columns they share
-  // in that XCD's L2
-  const int PW = p.tile / 64, PH = lg.nsub;
+  // XCD-aware patches of one table tile each (or of its first rows, to fit
+  // the 32 CUs of an XCD): the tiles one XCD runs at the same time read one
+  // tile's tables, whose halo rows and columns they share in that XCD's L2
+  const int PW = p.tile / 64;
+  int PH = lg.nsub;
+  while (PH > 1 && PW * PH > 32) PH = (PH + 1) / 2;
   const int pr = L / (PH * lg.ntx);
   const int rem = L - pr * PH * lg.ntx;
   const int ph = min(PH, lg.nty - pr * PH);
@@ -2192,11 +2207,26 @@ static hipError_t launch_ka1(int G, dim3 grid, dim3 block, hipStream_t s, const 
   return hipGetLastError();
 }
 
+// the pair form, for table rows of up to 4 chunks
 template <bool U8>
-static hipError_t launch_ka(int G, bool one, dim3 grid, dim3 block, hipStream_t s, const void *I,
+static hipError_t launch_ka_pair(int G, dim3 grid, dim3 block, hipStream_t s, const void *I, ImageParams p,
+                                 const DevTables *tab, int32_t *ws) {
+  switch (G) {
+    case 1: hipLaunchKernelGGL((ka_sat<1, U8, false, true>), grid, block, 0, s, I, p, tab, ws); break;
+    case 2: hipLaunchKernelGGL((ka_sat<2, U8, false, true>), grid, block, 0, s, I, p, tab, ws); break;
+    case 3: hipLaunchKernelGGL((ka_sat<3, U8, false, true>), grid, block, 0, s, I, p, tab, ws); break;
+    default: hipLaunchKernelGGL((ka_sat<4, U8, false, true>), grid, block, 0, s, I, p, tab, ws); break;
+  }
+  return hipGetLastError();
+}
+
+// mode: 0 a range term per wave, 1 a table, 2 a cosine or sine pair
+template <bool U8>
+static hipError_t launch_ka(int G, int mode, dim3 grid, dim3 block, hipStream_t s, const void *I,
                             ImageParams p, const DevTables *tab, int32_t *ws) {
-  return one ? launch_ka1<U8, true>(G, grid, block, s, I, p, tab, ws)
-             : launch_ka1<U8, false>(G, grid, block, s, I, p, tab, ws);
+  if (mode == 2) return launch_ka_pair<U8>(G, grid, block, s, I, p, tab, ws);
+  return mode == 1 ? launch_ka1<U8, true>(G, grid, block, s, I, p, tab, ws)
+                   : launch_ka1<U8, false>(G, grid, block, s, I, p, tab, ws);
 }
 
 template <bool U8>
@@ -2418,11 +2448,13 @@ bf_status_t launch_tables(const DevTables *dev, const DevTables &host, const Geo
   const ImageParams p = image_params(host, g);
   const int G = ka_chunks(g);
   if (G > kMaxChunks) return BF_ERR_UNSUPPORTED;
-  const bool one = g.ka_one != 0;
-  dim3 ga(g.tiles_y * g.tiles_x, ((one ? host.n_images : host.n_terms) + 3) / 4), ba(256);
+  // a pair per wave only where its instantiations go (rows of up to 4 chunks)
+  const int mode = g.ka_one == 2 && G > 4 ? 0 : g.ka_one;
+  const int units = mode == 1 ? host.n_images : mode == 2 ? 2 * host.n_terms : host.n_terms;
+  dim3 ga(g.tiles_y * g.tiles_x, (units + 3) / 4), ba(256);
   profile_mark(0, 1, stream);
-  hipError_t e = host.in_u8 ? launch_ka<true>(G, one, ga, ba, s, I, p, dev, ws)
-                            : launch_ka<false>(G, one, ga, ba, s, I, p, dev, ws);
+  hipError_t e = host.in_u8 ? launch_ka<true>(G, mode, ga, ba, s, I, p, dev, ws)
+                            : launch_ka<false>(G, mode, ga, ba, s, I, p, dev, ws);
   profile_mark(0, 0, stream);
   return e == hipSuccess ? BF_OK : BF_ERR_DEVICE;
 }

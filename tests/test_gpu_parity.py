@@ -622,11 +622,20 @@ def test_tiling_and_autotuning_do_not_change_results(torch_dev):
     # every launch shape the tuner may pick, pinned by hand
     for tile in (64, 128, 256, 512):
         for kb_single in (0, 1):
-            for ka_one in (0, 1):
+            for ka_one in (0, 1, 2):  # a range term, a table, a cosine or sine pair per table wave
                 p.set_tuning(333, 517, tile, kb_single, ka_one)
                 o = bf.filter(p, I)
                 torch.cuda.synchronize()
                 assert torch.equal(o, ref), (tile, kb_single, ka_one)
+    # the three table-wave forms on 8-bit input (its k = 0 table is the bytes) agree too
+    Iu = torch.from_numpy(synth.gen_image_u8(333, 517, 6, 0.03, 79)).cuda()
+    pu = bf.Plan(8.0, 0.1, 24, 16, 6, dtype="u8")
+    outs_u8 = []
+    for ka_one in (0, 1, 2):
+        pu.set_tuning(333, 517, 128, 0, ka_one)
+        outs_u8.append(bf.filter(pu, Iu).clone())
+    torch.cuda.synchronize()
+    assert torch.equal(outs_u8[0], outs_u8[1]) and torch.equal(outs_u8[0], outs_u8[2])
     # and in a batch (one table-kernel launch for both images)
     I2 = torch.from_numpy(synth.gen_image(333, 517, 6, 0.03, 78)).cuda()
     p.set_tuning(333, 517, 256, 1, 1)

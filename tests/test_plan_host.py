@@ -150,6 +150,15 @@ def test_lookup_kernel_choice_and_lattice_tiles():
     assert bf.Plan(3.0, 0.1, 9, 8, 4, host_only=True, direct=True).lookup_kernel(64, 64) == -1
     with pytest.raises(bf.BFError):
         cfg3.lookup_kernel(0, 5)
+    # table-kernel wave forms 0, 1, 2 (a range term, a table, a cosine or sine pair); nothing else
+    try:
+        for ka_one in (0, 1, 2):
+            cfg3.set_tuning(4096, 4096, 576, 2, ka_one)
+        for bad in (-1, 3):
+            with pytest.raises(bf.BFError):
+                cfg3.set_tuning(4096, 4096, 576, 2, bad)
+    finally:
+        bf.lib().bf_autotune_clear()
 
 
 def test_symmetric_taps_pair_into_quadruplets():
