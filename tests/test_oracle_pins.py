@@ -169,7 +169,7 @@ def test_haar_expansion_reproduces_cell_averages(sigma, T):
 
 def test_haar_parseval_levels():
     """Sum of level energies -> ||g||^2 on [-T, T] as J grows (Parseval), and the
-    survey-independent value of ||exp(-x^2/2)||^2 on [-3, 3] = sqrt(pi) erf(3)."""
+    closed-form value of ||exp(-x^2/2)||^2 on [-3, 3] = sqrt(pi) erf(3)."""
     sigma, T = 1.0, 3.0
     norm2 = math.sqrt(math.pi) * math.erf(3.0)
     for J, tol in ((3, 0.02), (10, 1e-6)):
