@@ -2664,15 +2664,15 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
   }
-  // each image's lookup kernel, as its single-image call would choose it
+  // each image's lookup kernel, as its single-image call would choose it;
+  // 4: the lattice kernel as the untuned default, launched per image as a
+  // single call launches it (its persistent form, for images tuned to the
+  // lattice kernel, spills registers at four columns of boxes)
   int kind[kMaxBatch];
-  // (where the lattice kernel is only the default, a batch keeps the LDS tile
-  // kernel: the lattice kernel's persistent form spills registers; both give
-  // the same bits)
   for (int j = 0; j < n; ++j) {
     const BatchItem &it = items[idx[j]];
     kind[j] = lookup_kernel_for(*it.host, it.g.kb_single);
-    if (kind[j] == 3 && it.g.kb_single != 2 && kb_tile_eligible(*it.host)) kind[j] = 2;
+    if (kind[j] == 3 && it.g.kb_single != 2) kind[j] = 4;
   }
   {
     int nq, G;
@@ -2805,11 +2805,16 @@ static bf_status_t launch_batch_chunk(const BatchItem *items, const int *idx, in
   }
   for (int j = 0; j < n; ++j) {
     const BatchItem &it = items[idx[j]];
-    if (kind[j] != 0) continue;
+    if (kind[j] != 0 && kind[j] != 4) continue;
     const BatchImage &im = ka.img[j];
-    dim3 gb((it.g.W + 63) / 64, (it.g.H + 3) / 4), bb(256);
-    e = u8 ? launch_kb<true>(gb, bb, s, it.I, im.p, it.dev, it.ws, it.out, nullptr, nullptr)
-           : launch_kb<false>(gb, bb, s, it.I, im.p, it.dev, it.ws, it.out, nullptr, nullptr);
+    if (kind[j] == 4) {
+      e = u8 ? launch_kl<true>(*it.host, it.g, s, it.I, im.p, it.dev, it.ws, it.out, nullptr, nullptr)
+             : launch_kl<false>(*it.host, it.g, s, it.I, im.p, it.dev, it.ws, it.out, nullptr, nullptr);
+    } else {
+      dim3 gb((it.g.W + 63) / 64, (it.g.H + 3) / 4), bb(256);
+      e = u8 ? launch_kb<true>(gb, bb, s, it.I, im.p, it.dev, it.ws, it.out, nullptr, nullptr)
+             : launch_kb<false>(gb, bb, s, it.I, im.p, it.dev, it.ws, it.out, nullptr, nullptr);
+    }
     if (e != hipSuccess) break;
   }
   profile_mark(1, 0, s);
