@@ -332,7 +332,8 @@ bf_status_t bf_plan_spatial_groups(bf_plan_t plan, int *level_x, int *level_y, i
  * lookup kernel the plan can use (LDS tile double- or single-buffered,
  * lattice; all give the same bits) --
  * on a temporary mid-grey image (reps launches each, at least
- * 3) and keeps the fastest, process-wide, for the plan's shape class (the
+ * 3) and keeps the fastest (among shapes within 1% of it, the one with the
+ * smallest workspace), process-wide, for the plan's shape class (the
  * radius, term and quadruplet counts, input type) and images in the same
  * 256-pixel size bucket of H and W.  From then on every call path (bf_filter,
  * bf_filter_ws, bf_filter_batch, bf_workspace_size, the request loop) uses

@@ -631,8 +631,8 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
     cleanup();
     return BF_ERR_DEVICE;
   }
-  float best_ms = 0;
-  Cand best = cands[0];
+  std::vector<float> times;
+  times.reserve(cands.size());
   for (const Cand &c : cands) {
     const bf::Geometry g = geometry_with(plan, H, W, c.tile, c.single, c.one);
     st = bf::launch_filter(plan->dev_tables, h, g, I, static_cast<float *>(out), nullptr, nullptr,
@@ -648,14 +648,24 @@ bf_status_t bf_autotune(bf_plan_t plan, int H, int W, int reps, void *stream, in
       if (st == BF_OK) st = BF_ERR_DEVICE;
       break;
     }
-    if (&c == &cands[0] || ms < best_ms) {
-      best_ms = ms;
-      best = c;
-    }
+    times.push_back(ms);
   }
   if (st == BF_OK && hipStreamSynchronize(s) != hipSuccess) st = BF_ERR_DEVICE;
   cleanup();
   if (st != BF_OK) return st;
+  // the fastest shape; among those within 1% of it (timing noise), the one
+  // with the smallest workspace
+  const float fastest = *std::min_element(times.begin(), times.end());
+  Cand best = cands[0];
+  size_t best_bytes = SIZE_MAX;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    if (times[i] > 1.01f * fastest) continue;
+    const size_t b = geometry_with(plan, H, W, cands[i].tile, cands[i].single, cands[i].one).bytes;
+    if (b < best_bytes) {
+      best_bytes = b;
+      best = cands[i];
+    }
+  }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[tune_key(plan, H, W)] = TuneVal{best.tile, best.single, best.one};
