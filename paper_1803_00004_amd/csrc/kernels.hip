@@ -793,8 +793,9 @@ __global__ __launch_bounds__(1024) void kb_tile(const void *__restrict__ I, Imag
 // ends the table.
 //
 // Output tiles are TR = s U G rows (G groups of s waves) by 64 columns,
-// clipped to the table tile they lie in.  The block has 16 waves: all copy,
-// the first s G compute.  Each pixel sums its boxes in (dy, dx) order, the
+// clipped to the table tile they lie in.  The block has NWV waves: all
+// copy, the first s G compute (NWV = 16, or 12 where s G = 12 for the N_s = 8
+// box pattern, so no wave only copies).  Each pixel sums its boxes in (dy, dx) order, the
 // order of the plan's quadruplet list, so the result is bitwise that of the
 // LDS tile kernel.
 // ---------------------------------------------------------------------------
@@ -830,7 +831,7 @@ __host__ __device__ inline LatGrid lat_grid(int H, int W, int tile, int s, int g
 
 // MASK: bit 4 j + i set where the plan may have a box (dy_j, dx_i); boxes
 // outside it have weight 0 and are skipped (adding 0 changes no bit).
-template <int PITCH, int M, int N, bool U8, uint32_t MASK = 0xFFFFu>
+template <int PITCH, int M, int N, bool U8, uint32_t MASK = 0xFFFFu, int NWV = 16>
 __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageParams &p,
                                         const DevTables *__restrict__ tab,
                                         const int32_t *__restrict__ ws, float *__restrict__ out,
@@ -900,12 +901,12 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
           __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)(dst + 64 * c), 4, xoff4[c], soff, 0, 0);
     }
   };
-  // rows [lo, RH) of table m: wave w copies rows lo + w, lo + w + 16, ...
-  const int d16 = 16 / s, m16 = 16 - d16 * s;
+  // rows [lo, RH) of table m: wave w copies rows lo + w, lo + w + NWV, ...
+  const int d16 = NWV / s, m16 = NWV - d16 * s;
   auto stage_from = [&](int m, int lo) {
     int R = lo + wave;
     int rq = R / s, rr = R - rq * s;
-    for (; R < RH; R += 16) {
+    for (; R < RH; R += NWV) {
       copy_row(m, R, rr * KB + rq);
       rq += d16;
       rr += m16;
@@ -1054,8 +1055,8 @@ __device__ __forceinline__ void kl_body(const void *__restrict__ I, const ImageP
   }
 }
 
-template <int PITCH, int M, int N, bool U8, uint32_t MASK = 0xFFFFu>
-__global__ __launch_bounds__(1024) void kl_tile(const void *__restrict__ I, ImageParams p,
+template <int PITCH, int M, int N, bool U8, uint32_t MASK = 0xFFFFu, int NWV = 16>
+__global__ __launch_bounds__(64 * NWV) void kl_tile(const void *__restrict__ I, ImageParams p,
                                                const DevTables *__restrict__ tab,
                                                const int32_t *__restrict__ ws,
                                                float *__restrict__ out, float *__restrict__ num_out,
@@ -1063,7 +1064,7 @@ __global__ __launch_bounds__(1024) void kl_tile(const void *__restrict__ I, Imag
   const int per_xcd = (n_tiles + 7) / 8;
   const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (L >= n_tiles) return;
-  kl_body<PITCH, M, N, U8, MASK>(I, p, tab, ws, out, num_out, den_out, L);
+  kl_body<PITCH, M, N, U8, MASK, NWV>(I, p, tab, ws, out, num_out, den_out, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -2404,11 +2405,15 @@ int lattice_rows(const DevTables &h) { return h.lat_s * kLatU * h.lat_g; }
 
 template <int PITCH, int M, int N, bool U8, uint32_t MASK = 0xFFFFu>
 static hipError_t launch_kl1(int n_tiles, size_t lds, hipStream_t s, const void *I, ImageParams p,
-                             const DevTables *tab, const int32_t *ws, float *out, float *num, float *den) {
+                             const DevTables *tab, const int32_t *ws, float *out, float *num, float *den, bool tab12 = false) {
   auto k = kl_tile<PITCH, M, N, U8, MASK>;
-  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  auto k12 = kl_tile<PITCH, M, N, U8, MASK, 12>;
+  // twelve-wave blocks where twelve waves compute (no wave that only copies)
+  const bool w12 = MASK != 0xFFFFu && tab12;
+  hipError_t e = hipFuncSetAttribute(w12 ? (const void *)k12 : (const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(8 * ((n_tiles + 7) / 8)), dim3(1024), lds, s, I, p, tab, ws, out, num, den, n_tiles);
+  if (w12) hipLaunchKernelGGL(k12, dim3(8 * ((n_tiles + 7) / 8)), dim3(768), lds, s, I, p, tab, ws, out, num, den, n_tiles);
+  else hipLaunchKernelGGL(k, dim3(8 * ((n_tiles + 7) / 8)), dim3(1024), lds, s, I, p, tab, ws, out, num, den, n_tiles);
   return hipGetLastError();
 }
 
@@ -2426,7 +2431,7 @@ static hipError_t launch_kl_mn(const DevTables &h, int n_tiles, size_t lds, hipS
       // the boxes of the N_s = 8 Gaussian expansion's level groups: an
       // instantiation that skips the 4 empty ones of the 16
       if (n4 && h.lat_mask == (int)kLatMaskNs8)
-        return launch_kl1<PITCH, 4, 4, U8, kLatMaskNs8>(n_tiles, lds, s, I, p, tab, ws, out, num, den);
+        return launch_kl1<PITCH, 4, 4, U8, kLatMaskNs8>(n_tiles, lds, s, I, p, tab, ws, out, num, den, h.lat_s * h.lat_g == 12);
       return n4 ? launch_kl1<PITCH, 4, 4, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den)
                 : launch_kl1<PITCH, 4, 2, U8>(n_tiles, lds, s, I, p, tab, ws, out, num, den);
   }
